@@ -1,0 +1,215 @@
+"""FP64 CPU oracle for the density-fitted J/K build (test infrastructure).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  It shares no code with the GPU library.  The integrals, the
+Boys function, the Cholesky factor and the forward substitution live in the
+plain C file ``oracle.c``; this module strings them together with numpy in
+the order the textbook definition of Coulomb-metric density fitting gives:
+
+    U_{P,mu nu} = (mu nu | P)                 three-centre integrals
+    V_{PQ}      = (P | Q),  V = L L^T          metric and its Cholesky factor
+    B           = L^{-1} U                     whitened three-centre tensor
+    c_P         = sum_{mu nu} B_{P,mu nu} D_{mu nu}
+    J_{mu nu}   = sum_P B_{P,mu nu} c_P
+    K_{mu nu}   = sum_P sum_{la si} B_{P,mu la} D_{la si} B_{P,si nu}
+    E_J = 1/2 Tr(D J),   E_K = -1/4 Tr(D K)
+
+With occupied orbitals C the density is D = 2 C C^T (closed shell) and K is
+taken through the half-transformed tensor X_{P,mu i} = sum_nu B_{P,mu nu} C_{nu i},
+K = 2 sum_{P,i} X_{P,mu i} X_{P,nu i}.  None of these formulas appears in the
+paper (GPU4PySCF v1.0), which only names the method (Introduction; Section
+"Dataset and Performance"); they are the standard Coulomb-metric fitting
+(Whitten 1973; Vahtras, Almloef and Feyereisen 1993).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    """Load (building if needed) the C oracle."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB) or (
+                os.path.getmtime(_build.LIB) < os.path.getmtime(os.path.join(_build.HERE, "oracle.c"))):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_boys.argtypes = [ctypes.c_int, ctypes.c_double, dp]
+        L.orc_norm.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_norm.restype = ctypes.c_double
+        L.orc_int3c.argtypes = [dp, ctypes.c_int, ip, ip, dp, ctypes.c_int, ip, ip, dp,
+                                ctypes.c_int, ctypes.c_int, dp]
+        L.orc_int2c.argtypes = [dp, ctypes.c_int, ip, ip, dp, dp]
+        L.orc_int4c.argtypes = [dp, ctypes.c_int, ip, ip, dp, dp]
+        L.orc_overlap.argtypes = [dp, ctypes.c_int, ip, ip, dp, dp]
+        L.orc_cholesky.argtypes = [ctypes.c_long, dp, dp]
+        L.orc_cholesky.restype = ctypes.c_long
+        L.orc_forward_subst.argtypes = [ctypes.c_long, dp, ctypes.c_long, dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _basis(atom, l, e):
+    return (len(l), np.ascontiguousarray(atom, np.int32), np.ascontiguousarray(l, np.int32),
+            np.ascontiguousarray(e, np.float64))
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def boys(mmax, T):
+    """F_0(T) .. F_mmax(T)."""
+    F = np.zeros(mmax + 1)
+    lib().orc_boys(mmax, float(T), _d(F))
+    return F
+
+
+def norm(l, a):
+    """Normalisation constant N_l(a) of a Racah-normalised solid-harmonic Gaussian."""
+    return lib().orc_norm(l, float(a))
+
+
+def int3c(mol, c0=0, c1=None):
+    """(mu nu|P) for aux shells [c0, c1): array (naux_slice, nao, nao)."""
+    n, aa, al, ae = _basis(mol.ao_atom, mol.ao_l, mol.ao_exp)
+    m, xa, xl, xe = _basis(mol.aux_atom, mol.aux_l, mol.aux_exp)
+    if c1 is None:
+        c1 = m
+    nsl = int(np.sum(2 * xl[c0:c1] + 1))
+    out = np.zeros((nsl, mol.nao, mol.nao))
+    xyz = np.ascontiguousarray(mol.coords, np.float64)
+    rc = lib().orc_int3c(_d(xyz), n, _i(aa), _i(al), _d(ae), m, _i(xa), _i(xl), _d(xe),
+                         c0, c1, _d(out))
+    if rc:
+        raise ValueError("angular momentum out of range")
+    return out
+
+
+def _two_index(fn, mol, which):
+    if which == "aux":
+        n, a, l, e = _basis(mol.aux_atom, mol.aux_l, mol.aux_exp)
+        nf = mol.naux
+    else:
+        n, a, l, e = _basis(mol.ao_atom, mol.ao_l, mol.ao_exp)
+        nf = mol.nao
+    out = np.zeros((nf, nf))
+    xyz = np.ascontiguousarray(mol.coords, np.float64)
+    if fn(_d(xyz), n, _i(a), _i(l), _d(e), _d(out)):
+        raise ValueError("angular momentum out of range")
+    return out
+
+
+def int2c(mol):
+    """Coulomb metric (P|Q)."""
+    return _two_index(lib().orc_int2c, mol, "aux")
+
+
+def overlap(mol):
+    """AO overlap matrix."""
+    return _two_index(lib().orc_overlap, mol, "ao")
+
+
+def int4c(mol):
+    """(mu nu|la si) over the AO basis, shape (nao,)*4.  Tiny systems only."""
+    n, a, l, e = _basis(mol.ao_atom, mol.ao_l, mol.ao_exp)
+    nf = mol.nao
+    out = np.zeros((nf, nf, nf, nf))
+    xyz = np.ascontiguousarray(mol.coords, np.float64)
+    if lib().orc_int4c(_d(xyz), n, _i(a), _i(l), _d(e), _d(out)):
+        raise ValueError("angular momentum out of range")
+    return out
+
+
+class NotPositiveDefinite(ValueError):
+    def __init__(self, pivot):
+        super().__init__("metric not positive definite at pivot %d" % pivot)
+        self.pivot = pivot
+
+
+def cholesky(V):
+    """Lower-triangular L with V = L L^T (plain column algorithm)."""
+    V = np.ascontiguousarray(V, np.float64)
+    L = np.zeros_like(V)
+    piv = lib().orc_cholesky(V.shape[0], _d(V), _d(L))
+    if piv >= 0:
+        raise NotPositiveDefinite(int(piv))
+    return L
+
+
+def forward_subst(L, B):
+    """X with L X = B (B of shape (n, m)), by plain forward substitution."""
+    L = np.ascontiguousarray(L, np.float64)
+    X = np.array(B, dtype=np.float64, order="C", copy=True)
+    n = L.shape[0]
+    m = X.size // n
+    lib().orc_forward_subst(n, _d(L), m, _d(X))
+    return X
+
+
+def whitened_3c(mol, U=None):
+    """B = L^{-1} U with V = L L^T; returns (B, L) with B shaped (naux, nao, nao)."""
+    if U is None:
+        U = int3c(mol)
+    L = cholesky(int2c(mol))
+    B = forward_subst(L, U.reshape(U.shape[0], -1)).reshape(U.shape)
+    return B, L
+
+
+def density(C):
+    """Closed-shell density D = 2 C C^T."""
+    return 2.0 * C @ C.T
+
+
+def jk_from_B(B, C=None, D=None):
+    """J, K, E_J, E_K from the whitened tensor B (naux, nao, nao)."""
+    if (C is None) == (D is None):
+        raise ValueError("give exactly one of C and D")
+    naux, nao, _ = B.shape
+    Bm = B.reshape(naux, nao * nao)
+    if C is not None:
+        D = density(C)
+    c = Bm @ D.ravel()
+    J = (c @ Bm).reshape(nao, nao)
+    if C is not None:
+        X = B @ C                                     # X[P, mu, i]
+        K = 2.0 * np.tensordot(X, X, axes=([0, 2], [0, 2]))
+    else:
+        K = np.zeros((nao, nao))
+        for P in range(naux):
+            K += B[P] @ D @ B[P]
+    EJ = 0.5 * float(np.sum(D * J))
+    EK = -0.25 * float(np.sum(D * K))
+    return {"J": J, "K": K, "EJ": EJ, "EK": EK, "c": c, "D": D}
+
+
+def dfjk(mol, C=None, D=None):
+    """The full DF-J/K build for a molecule (unscreened)."""
+    B, _ = whitened_3c(mol)
+    return jk_from_B(B, C=C, D=D)
+
+
+def exact_jk(mol, D):
+    """Exact (non-fitted) J and K from four-centre integrals (tiny systems)."""
+    eri = int4c(mol)
+    J = np.einsum("mnls,ls->mn", eri, D)
+    K = np.einsum("mlns,ls->mn", eri, D)
+    return J, K, 0.5 * float(np.sum(D * J)), -0.25 * float(np.sum(D * K))

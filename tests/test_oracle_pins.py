@@ -1,0 +1,372 @@
+"""Pins for the CPU oracle, checked against things other than itself:
+closed forms, a library routine, brute-force quadrature, exactness cases and
+invariants of Coulomb-metric density fitting.  All CPU-only."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.special
+
+import oracle
+import workload as W
+from tests import brute
+
+
+def _mol(ao, aux, coords, charges=None):
+    """Molecule from explicit shell lists [(atom, l, exp), ...]."""
+    coords = np.asarray(coords, float)
+    if charges is None:
+        charges = np.zeros(len(coords), int)
+    ao = np.array(ao, dtype=object)
+    aux = np.array(aux, dtype=object)
+    return W.Molecule(charges=np.asarray(charges), coords=coords,
+                      ao_atom=ao[:, 0].astype(np.int32), ao_l=ao[:, 1].astype(np.int32),
+                      ao_exp=ao[:, 2].astype(float),
+                      aux_atom=aux[:, 0].astype(np.int32), aux_l=aux[:, 1].astype(np.int32),
+                      aux_exp=aux[:, 2].astype(float))
+
+
+@pytest.fixture(scope="module")
+def water():
+    z, x = W.water_monomer()
+    mol = W.make_molecule(z, x)
+    S = W.overlap_by_quadrature(mol)
+    C = W.occupied_orbitals(S, 5, 0)
+    return mol, S, C
+
+
+# --------------------------------------------------------------------------
+# Boys function
+
+def _boys_mp(m, T):
+    import mpmath
+    mpmath.mp.dps = 50
+    if T == 0:
+        return 1.0 / (2 * m + 1)
+    T = mpmath.mpf(T)
+    return float(mpmath.gammainc(m + mpmath.mpf(1) / 2, 0, T) / (2 * T ** (m + mpmath.mpf(1) / 2)))
+
+
+def test_boys_against_mpmath():
+    Ts = list(np.linspace(0.0, 40.0, 81)) + list(np.logspace(-10, np.log10(200.0), 40)) + [29.999, 30.001]
+    worst = 0.0
+    for T in Ts:
+        F = oracle.boys(8, T)
+        for m in range(9):
+            ref = _boys_mp(m, T)
+            worst = max(worst, abs(F[m] - ref) / ref)
+    assert worst <= 1e-14, worst
+
+
+def test_boys_special_values():
+    F = oracle.boys(12, 0.0)
+    assert np.allclose(F, [1.0 / (2 * m + 1) for m in range(13)], rtol=0, atol=1e-16)
+    for T in (1e-3, 0.7, 3.0, 12.0, 31.0, 90.0):
+        F = oracle.boys(8, T)
+        assert abs(F[0] - 0.5 * math.sqrt(math.pi / T) * math.erf(math.sqrt(T))) <= 1e-15 * F[0]
+        for m in range(9):                       # Kummer form
+            ref = scipy.special.hyp1f1(m + 0.5, m + 1.5, -T) / (2 * m + 1)
+            assert abs(F[m] - ref) <= 1e-12 * ref
+        for m in range(8):                       # downward-recursion identity
+            assert abs((2 * m + 1) * F[m] - (2 * T * F[m + 1] + math.exp(-T))) <= 1e-14 * (2 * m + 1) * F[m]
+
+
+def test_boys_large_T_asymptote():
+    for T in (80.0, 150.0, 400.0):
+        F = oracle.boys(8, T)
+        for m in range(9):
+            dfm = np.prod(np.arange(2 * m - 1, 0, -2)) if m > 0 else 1.0
+            asym = dfm / 2 ** (m + 1) * math.sqrt(math.pi / T ** (2 * m + 1))
+            assert abs(F[m] - asym) <= 1e-14 * asym
+
+
+# --------------------------------------------------------------------------
+# Normalisation, overlap and the spherical convention
+
+def test_overlap_unit_diagonal_and_one_centre_identity():
+    mol = _mol([(0, l, e) for l in range(4) for e in (0.3, 2.0)], [(0, 0, 1.0)], [[0.1, 0.2, 0.3]])
+    S = oracle.overlap(mol)
+    off = np.concatenate([[0], np.cumsum(2 * mol.ao_l + 1)])
+    assert np.abs(np.diag(S) - 1).max() <= 1e-14
+    for k in range(len(mol.ao_l)):
+        blk = S[off[k]:off[k + 1], off[k]:off[k + 1]]
+        assert np.abs(blk - np.eye(len(blk))).max() <= 1e-14
+
+
+def test_norm_against_numeric_radial_integral():
+    for l in range(4):
+        for a in (0.05, 1.0, 700.0):
+            # Racah-normalised angular part integrates to 4 pi / (2l+1)
+            radial = scipy.special.gamma(l + 1.5) / (2 * (2 * a) ** (l + 1.5))
+            N = oracle.norm(l, a)
+            assert abs(N * N * radial * 4 * math.pi / (2 * l + 1) - 1.0) <= 1e-13
+
+
+def test_overlap_matches_generator_quadrature(water):
+    mol, S_quad, C = water
+    S = oracle.overlap(mol)
+    assert np.abs(S - S_quad).max() <= 1e-13
+    # shells up to f on several centres, against the quadrature too
+    mol2 = _mol([(0, 3, 0.9), (1, 2, 0.5), (2, 1, 1.7), (0, 0, 3.0), (1, 3, 0.4)],
+                [(0, 0, 1.0)], [[0, 0, 0], [0.8, -0.4, 0.3], [-0.5, 0.6, 1.1]])
+    assert np.abs(oracle.overlap(mol2) - W.overlap_by_quadrature(mol2)).max() <= 1e-13
+
+
+def test_density_trace_is_electron_count(water):
+    mol, S_quad, C = water
+    D = oracle.density(C)
+    assert abs(np.sum(D * oracle.overlap(mol)) - mol.nelec) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# Integrals: closed forms and brute force
+
+def test_ss_s_and_s_s_and_ssss_closed_forms():
+    A, B, C = np.array([0.0, 0, 0]), np.array([0.9, -0.3, 0.4]), np.array([-0.6, 1.2, 0.2])
+    a, b, g = 1.7, 0.45, 0.8
+    mol = _mol([(0, 0, a), (1, 0, b)], [(2, 0, g), (0, 0, 2.3)], [A, B, C])
+    U = oracle.int3c(mol)
+    n = lambda e: (2 * e / math.pi) ** 0.75
+    p = a + b
+    P = (a * A + b * B) / p
+    al = p * g / (p + g)
+    ref = (n(a) * n(b) * n(g) * 2 * math.pi ** 2.5 / (p * g * math.sqrt(p + g))
+           * math.exp(-a * b / p * np.sum((A - B) ** 2)) * brute.boys0(al * np.sum((P - C) ** 2)))
+    assert abs(U[0, 0, 1] - ref) <= 1e-14 * ref
+    assert U[0, 0, 1] == U[0, 1, 0]
+    V = oracle.int2c(mol)
+    g2 = 2.3
+    ref2 = n(g) * n(g2) * 2 * math.pi ** 2.5 / (g * g2 * math.sqrt(g + g2)) * brute.boys0(
+        g * g2 / (g + g2) * np.sum((C - A) ** 2))
+    assert abs(V[0, 1] - ref2) <= 1e-14 * ref2
+    # self-repulsion of one normalised s: (aa|aa) = 2 sqrt(a/pi)
+    eri = oracle.int4c(_mol([(0, 0, a)], [(0, 0, 1.0)], [A]))
+    assert abs(eri[0, 0, 0, 0] - 2 * math.sqrt(a / math.pi)) <= 1e-14
+    # a generic (ss|ss) against the closed form
+    eri = oracle.int4c(mol)
+    ref4 = brute.ssss(a, A, b, B, b, B, a, A)
+    assert abs(eri[0, 1, 1, 0] - ref4) <= 1e-14 * ref4
+
+
+@pytest.mark.parametrize("la,lb,lc", [(1, 0, 0), (0, 0, 1), (1, 1, 2), (2, 0, 3), (2, 1, 1), (2, 2, 3), (0, 2, 2)])
+def test_int3c_against_t_quadrature(la, lb, lc):
+    A, B, C = [0.2, -0.1, 0.3], [1.1, 0.6, -0.5], [-0.4, 0.9, 0.7]
+    a, b, g = 1.4, 0.55, 0.95
+    mol = _mol([(0, la, a), (1, lb, b)], [(2, lc, g)], [A, B, C])
+    U = oracle.int3c(mol)
+    na, nb = 2 * la + 1, 2 * lb + 1
+    got = U[:, 0:na, na:na + nb].transpose(1, 2, 0)
+    ref = brute.coulomb3c_block(la, a, A, lb, b, B, lc, g, C)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_int3c_same_centre_against_t_quadrature():
+    A = [0.3, 0.2, -0.4]
+    mol = _mol([(0, 2, 0.8), (0, 1, 2.2)], [(0, 3, 1.5)], [A])
+    U = oracle.int3c(mol)
+    got = U[:, 0:5, 5:8].transpose(1, 2, 0)
+    ref = brute.coulomb3c_block(2, 0.8, A, 1, 2.2, A, 3, 1.5, A)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_int3c_shell_order_reversal():
+    """Reversing the AO shell list swaps the roles of the two E recursions."""
+    z, x = W.water_monomer()
+    mol = W.make_molecule(z, x)
+    U = oracle.int3c(mol)
+    rev = _mol(list(zip(mol.ao_atom[::-1], mol.ao_l[::-1], mol.ao_exp[::-1])),
+               list(zip(mol.aux_atom, mol.aux_l, mol.aux_exp)), mol.coords)
+    Ur = oracle.int3c(rev)
+    off = np.concatenate([[0], np.cumsum(2 * mol.ao_l + 1)])
+    perm = np.concatenate([np.arange(off[k], off[k + 1]) for k in range(len(mol.ao_l))[::-1]])
+    assert np.abs(Ur - U[:, perm][:, :, perm]).max() <= 1e-13 * np.abs(U).max()
+
+
+def test_int2c_equals_int3c_with_flat_partner():
+    """(P|Q) is (P s_eps|Q) / N_0(eps) for a vanishing-exponent s partner."""
+    coords = [[0, 0, 0], [0.7, -0.2, 0.5], [-0.3, 0.8, 0.1]]
+    aux_shells = [(0, 0, 1.2), (1, 1, 0.7), (2, 2, 1.9), (0, 3, 0.8)]
+    eps = 1e-10
+    for sh in aux_shells:
+        mol3 = _mol([sh, (0, 0, eps)], aux_shells, coords)
+        U = oracle.int3c(mol3)
+        n1 = 2 * sh[1] + 1
+        got = U[:, 0:n1, n1] / oracle.norm(0, eps)
+        V = oracle.int2c(_mol([(0, 0, 1.0)], aux_shells, coords))
+        k = aux_shells.index(sh)
+        off = np.concatenate([[0], np.cumsum([2 * s[1] + 1 for s in aux_shells])])
+        ref = V[:, off[k]:off[k + 1]]
+        assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_schwarz_inequality_holds(water):
+    mol, _, _ = water
+    U = oracle.int3c(mol)
+    eri = oracle.int4c(mol)
+    V = oracle.int2c(mol)
+    n = mol.nao
+    diag = np.sqrt(np.abs(eri.reshape(n * n, n * n).diagonal())).reshape(n, n)
+    bound = diag[None, :, :] * np.sqrt(np.diag(V))[:, None, None]
+    assert np.all(np.abs(U) <= bound * (1 + 1e-12) + 1e-300)
+
+
+# --------------------------------------------------------------------------
+# Linear algebra
+
+def test_cholesky_and_forward_substitution_against_lapack(water):
+    mol, _, _ = water
+    V = oracle.int2c(mol)
+    L = oracle.cholesky(V)
+    assert np.allclose(np.triu(L, 1), 0.0)
+    assert np.abs(L @ L.T - V).max() <= 1e-14 * np.abs(V).max()
+    assert np.abs(L - np.linalg.cholesky(V)).max() <= 1e-12 * np.abs(L).max()
+    rng = np.random.default_rng(3)
+    Bm = rng.standard_normal((V.shape[0], 700))
+    X = oracle.forward_subst(L, Bm)
+    ref = scipy.linalg.solve_triangular(L, Bm, lower=True)
+    assert np.abs(X - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_cholesky_reports_nonpositive_pivot():
+    A = np.array([[4.0, 2.0, 0.0], [2.0, 1.0, 1.0], [0.0, 1.0, 3.0]])   # pivot 1 is 0
+    with pytest.raises(oracle.NotPositiveDefinite) as ei:
+        oracle.cholesky(A)
+    assert ei.value.pivot == 1
+    with pytest.raises(oracle.NotPositiveDefinite) as ei:
+        oracle.cholesky(np.diag([1.0, 2.0, -1.0]))
+    assert ei.value.pivot == 2
+
+
+# --------------------------------------------------------------------------
+# DF-J/K: exactness, bounds and invariants
+
+def test_df_exact_one_centre():
+    a = 1.3
+    mol = _mol([(0, 0, a)], [(0, 0, 2 * a)], [[0.0, 0.0, 0.0]])
+    r = oracle.dfjk(mol, D=np.array([[2.0]]))
+    assert abs(r["EJ"] - 4 * math.sqrt(a / math.pi)) <= 1e-14
+    assert abs(r["EK"] + 2 * math.sqrt(a / math.pi)) <= 1e-14
+
+
+def test_df_exact_two_centre():
+    """Aux {2a@A, 2b@B, (a+b)@P} spans every AO product: DF J/K equal the exact 4c J/K."""
+    A, B = np.array([0.0, 0.0, 0.0]), np.array([0.4, -0.3, 0.5])
+    a, b = 0.9, 1.6
+    P = (a * A + b * B) / (a + b)
+    mol = _mol([(0, 0, a), (1, 0, b)], [(0, 0, 2 * a), (1, 0, 2 * b), (2, 0, a + b)], [A, B, P])
+    rng = np.random.default_rng(0)
+    M = rng.standard_normal((2, 2))
+    D = M + M.T
+    r = oracle.dfjk(mol, D=D)
+    cen, ex = [A, B], [a, b]
+    eri = np.zeros((2, 2, 2, 2))
+    for i in range(2):
+        for j in range(2):
+            for k in range(2):
+                for l in range(2):
+                    eri[i, j, k, l] = brute.ssss(ex[i], cen[i], ex[j], cen[j], ex[k], cen[k], ex[l], cen[l])
+    J = np.einsum("ijkl,kl->ij", eri, D)
+    K = np.einsum("ikjl,kl->ij", eri, D)
+    assert np.abs(r["J"] - J).max() <= 1e-12 * np.abs(J).max()
+    assert np.abs(r["K"] - K).max() <= 1e-12 * np.abs(K).max()
+
+
+def test_df_variational_bounds(water):
+    mol, _, C = water
+    D = oracle.density(C)
+    r = oracle.dfjk(mol, C=C)
+    _, _, EJ, EK = oracle.exact_jk(mol, D)
+    assert r["EJ"] <= EJ + 1e-12
+    assert abs(r["EK"]) <= abs(EK) + 1e-12
+
+
+def test_k_routes_agree_with_literal_four_index_sum(water):
+    mol, _, C = water
+    B, _ = oracle.whitened_3c(mol)
+    D = oracle.density(C)
+    viaC = oracle.jk_from_B(B, C=C)
+    viaD = oracle.jk_from_B(B, D=D)
+    eri_df = np.einsum("Pml,Pns->mlns", B, B)        # (ml|ns)_DF
+    K = np.einsum("mlns,ls->mn", eri_df, D)
+    J = np.einsum("mnls,ls->mn", eri_df, D)
+    s = np.abs(K).max()
+    assert np.abs(viaC["K"] - K).max() <= 1e-13 * s
+    assert np.abs(viaD["K"] - K).max() <= 1e-13 * s
+    assert np.abs(viaC["J"] - J).max() <= 1e-13 * np.abs(J).max()
+
+
+def test_jk_structure_and_energy_identities(water):
+    mol, _, C = water
+    B, _ = oracle.whitened_3c(mol)
+    r = oracle.jk_from_B(B, C=C)
+    J, K = r["J"], r["K"]
+    assert np.abs(J - J.T).max() <= 1e-13 * np.abs(J).max()
+    assert np.abs(K - K.T).max() <= 1e-13 * np.abs(K).max()
+    assert np.linalg.eigvalsh(0.5 * (K + K.T)).min() >= -1e-12 * np.abs(K).max()
+    assert abs(r["EJ"] - 0.5 * np.sum(r["c"] ** 2)) <= 1e-12 * abs(r["EJ"])
+    Bij = np.einsum("mi,Pmn,nj->Pij", C, B, C)
+    assert abs(r["EK"] + np.sum(Bij ** 2)) <= 1e-12 * abs(r["EK"])
+    # linearity in D
+    rng = np.random.default_rng(5)
+    M = rng.standard_normal(J.shape)
+    D1, D2 = M + M.T, r["D"]
+    ra, rb = oracle.jk_from_B(B, D=D1), oracle.jk_from_B(B, D=D2)
+    rs = oracle.jk_from_B(B, D=0.3 * D1 + 1.7 * D2)
+    assert np.abs(rs["J"] - (0.3 * ra["J"] + 1.7 * rb["J"])).max() <= 1e-12 * np.abs(rs["J"]).max()
+    assert np.abs(rs["K"] - (0.3 * ra["K"] + 1.7 * rb["K"])).max() <= 1e-12 * np.abs(rs["K"]).max()
+
+
+def test_aux_permutation_invariance(water):
+    mol, _, C = water
+    r = oracle.dfjk(mol, C=C)
+    perm = np.random.default_rng(11).permutation(len(mol.aux_l))
+    mol2 = _mol(list(zip(mol.ao_atom, mol.ao_l, mol.ao_exp)),
+                list(zip(mol.aux_atom[perm], mol.aux_l[perm], mol.aux_exp[perm])), mol.coords)
+    r2 = oracle.dfjk(mol2, C=C)
+    assert np.abs(r2["J"] - r["J"]).max() <= 1e-11 * np.abs(r["J"]).max()
+    assert np.abs(r2["K"] - r["K"]).max() <= 1e-11 * np.abs(r["K"]).max()
+
+
+def test_translation_invariance(water):
+    mol, _, C = water
+    r = oracle.dfjk(mol, C=C)
+    r2 = oracle.dfjk(W.shift_molecule(mol, [3.1, -2.2, 0.7]), C=C)
+    for k in ("J", "K"):
+        assert np.abs(r2[k] - r[k]).max() <= 1e-10 * np.abs(r[k]).max()
+
+
+def test_atom_relabelling_permutes_jk():
+    z, x = W.water_cluster(2, 6.0, 21)
+    mol = W.make_molecule(z, x)
+    S = W.overlap_by_quadrature(mol)
+    C = W.occupied_orbitals(S, 10, 2)
+    r = oracle.dfjk(mol, C=C)
+    order = [3, 4, 5, 0, 1, 2]                      # swap the two waters
+    mol2 = W.make_molecule(z[order], x[order])
+    # AO functions of mol2 in terms of mol: the second water's block first
+    half = mol.nao // 2
+    perm = np.concatenate([np.arange(half, mol.nao), np.arange(half)])
+    r2 = oracle.dfjk(mol2, C=C[perm])
+    assert np.abs(r2["J"] - r["J"][np.ix_(perm, perm)]).max() <= 1e-10 * np.abs(r["J"]).max()
+    assert np.abs(r2["K"] - r["K"][np.ix_(perm, perm)]).max() <= 1e-10 * np.abs(r["K"]).max()
+
+
+def test_far_dimer_exchange_approaches_additivity():
+    """E_K(AB) - E_K(A) - E_K(B) for block-diagonal orbitals decays with R
+    (a power law from the long-range tail of the fitted pair densities)."""
+    z, x = W.water_monomer()
+    mon = W.make_molecule(z, x)
+    S1 = W.overlap_by_quadrature(mon)
+    C1 = W.occupied_orbitals(S1, 5, 0)
+    EK1 = oracle.dfjk(mon, C=C1)["EK"]
+    diffs = []
+    for R in (20.0, 40.0, 80.0):
+        xyz = np.vstack([x, x + np.array([R, 0.0, 0.0])])
+        dim = W.make_molecule(np.concatenate([z, z]), xyz)
+        C = np.zeros((2 * mon.nao, 10))
+        C[:mon.nao, :5] = C1
+        C[mon.nao:, 5:] = C1
+        diffs.append(abs(oracle.dfjk(dim, C=C)["EK"] - 2 * EK1))
+    assert diffs[0] > diffs[1] > diffs[2]
+    assert diffs[2] < 1e-3 * abs(EK1)
