@@ -1,0 +1,181 @@
+/*
+ * dfjk.h -- C ABI of the MI355X (gfx950) density-fitted Coulomb/exchange build.
+ *
+ * One SCF iteration of GPU-accelerated Kohn-Sham/Hartree-Fock with density
+ * fitting needs J and K from the current density.  The paper this library
+ * follows (GPU4PySCF v1.0) describes the path only in words (Introduction:
+ * three-centre integrals for density fitting, then tensor contractions on
+ * matrix units; "Dataset and Performance": integrals kept resident in GPU
+ * memory for small systems; "Limitations and Future Development / Mixed
+ * Precision": single precision guided by Schwarz estimates).  The quantities
+ * computed are the standard Coulomb-metric fitting formulas:
+ *
+ *   U_{P,mu nu} = (mu nu|P)          three-centre integrals, Schwarz screened
+ *   V = (P|Q) = L L^T                metric and its Cholesky factor
+ *   B = L^{-1} U                     whitened three-centre tensor
+ *   c_P = sum_{mu nu} B_{P,mu nu} D_{mu nu};   J_{mu nu} = sum_P B_{P,mu nu} c_P
+ *   K_{mu nu} = sum_P sum_{la si} B_{P,mu la} D_{la si} B_{P,si nu}
+ *             = 2 sum_{P,i} X_{P,i mu} X_{P,i nu},  X_{P,i mu} = sum_nu B_{P,mu nu} C_{nu i}
+ *   E_J = 1/2 Tr(D J),  E_K = -1/4 Tr(D K),  D = 2 C C^T when C is given.
+ *
+ * Conventions.  Units are Bohr and Hartree.  Every shell is one uncontracted
+ * primitive; functions are unit-normalised real solid harmonics (Racah
+ * normalisation) times a Gaussian, AO order follows the caller's shell order,
+ * p functions are (x, y, z) and d/f functions run m = -l..l.  AO l <= 2, aux
+ * l <= 3.  All matrices are row-major doubles.
+ *
+ * Memory.  The caller owns every device buffer (the Python binding allocates
+ * them with torch); the library owns only the opaque plan (host metadata) and
+ * borrows each workspace for as long as the call (or, for the resident
+ * workspace, the plan) needs it.  The library never allocates device memory
+ * itself.  Device pointers must come from hipMalloc (or torch) on the device
+ * that is current when the call is made.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void*; NULL is the default
+ * stream.  Calls enqueue work and return; outputs are valid once the stream
+ * has reached them.  dfjk_screen and dfjk_setup synchronise the stream before
+ * they return (the host needs the screening result and the Cholesky status).
+ *
+ * Errors.  Every call returns a dfjk_status.  Arguments are validated before
+ * any work is enqueued, and output buffers are left untouched when validation
+ * fails.  dfjk_last_error() returns a thread-local message describing the
+ * last failure on the calling thread.
+ */
+#ifndef DFJK_H
+#define DFJK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DFJK_OK = 0,
+    DFJK_E_INVALID = 1,      /* bad argument (NULL pointer, size, ...)          */
+    DFJK_E_UNSUPPORTED = 2,  /* angular momentum or size beyond this version     */
+    DFJK_E_NOT_POSDEF = 3,   /* metric Cholesky met a pivot <= 0 (index in msg) */
+    DFJK_E_OOM = 4,          /* a workspace smaller than the size query asked    */
+    DFJK_E_DEVICE = 5,       /* a HIP runtime error (HIP message in the text)    */
+    DFJK_E_NO_DEVICE = 6,    /* no GPU visible                                   */
+    DFJK_E_STATE = 7         /* call out of order (e.g. build before setup)      */
+} dfjk_status;
+
+typedef enum {
+    DFJK_FP64 = 0,           /* every step in FP64                              */
+    DFJK_MIXED_FP32 = 1,     /* X stored FP32, K on FP32 MFMA, FP64 chunk sums   */
+    DFJK_MIXED_BF16X3 = 2    /* X split into BF16 hi+lo, K = hi.hi + hi.lo +
+                                lo.hi on BF16 MFMA, FP32 chunks, FP64 sums       */
+} dfjk_precision;
+
+/* One basis (AO or auxiliary): nshell uncontracted shells on atoms. */
+typedef struct {
+    int32_t nshell;
+    const int32_t *shell_atom;   /* atom index of each shell, 0 <= atom < natm */
+    const int32_t *shell_l;      /* angular momentum of each shell             */
+    const double *shell_exp;     /* Gaussian exponent of each shell, > 0       */
+} dfjk_basis;
+
+typedef struct {
+    double schwarz_thresh;       /* keep (mu nu|P) iff Q_ab * Q_P >= thresh,
+                                    Q the Schwarz factors sqrt|(ab|ab)|,
+                                    sqrt (P|P); 0 keeps everything.  Default
+                                    1e-14.                                    */
+} dfjk_options;
+
+typedef struct dfjk_plan dfjk_plan;
+
+/* Plan facts, filled by dfjk_plan_info. */
+typedef struct {
+    int64_t nao, naux;           /* basis sizes                                */
+    int64_t naux_pad;            /* aux dimension as stored (multiple of 64)   */
+    int64_t nshell_pairs;        /* AO shell pairs a >= b                      */
+    int64_t sig_shell_pairs;     /* pairs surviving screening (after screen)   */
+    int64_t nf;                  /* stored function pairs (after screen)       */
+    int64_t triplets_kept;       /* shell triplets evaluated (after screen)    */
+    int32_t stage;               /* 0 created, 1 screened, 2 set up            */
+} dfjk_info;
+
+/* Default options. */
+int dfjk_options_default(dfjk_options *opt);
+
+/* Host preparation (no device work): validates the molecule, orders the
+ * auxiliary shells by angular momentum and enumerates AO shell pairs.
+ * coords: natm x 3 Bohr.  opt may be NULL (defaults).  *out receives a plan
+ * that the caller releases with dfjk_plan_destroy. */
+int dfjk_plan_create(int32_t natm, const double *coords, const dfjk_basis *ao,
+                     const dfjk_basis *aux, const dfjk_options *opt, dfjk_plan **out);
+
+int dfjk_plan_info(const dfjk_plan *plan, dfjk_info *info);
+
+/* The library's internal aux order: out[i] (host array of naux int32) is the
+ * caller's aux function index of internal aux function i.  DFJK_EXPORT_CHOL,
+ * DFJK_EXPORT_B and the whitened samples of dfjk_sample use this order. */
+int dfjk_plan_aux_order(const dfjk_plan *plan, int32_t *out);
+
+/* Schwarz screening.  dfjk_screen_bytes gives the size of the device scratch
+ * dfjk_screen needs; dfjk_screen computes Q_ab for every AO shell pair and
+ * Q_P for every aux shell on the GPU, copies them back, and keeps the pairs
+ * whose largest triplet bound reaches the threshold.  Synchronises `stream`. */
+int dfjk_screen_bytes(const dfjk_plan *plan, size_t *bytes);
+int dfjk_screen(dfjk_plan *plan, void *d_scratch, size_t bytes, void *stream);
+
+/* Per-molecule setup on the resident workspace: three-centre integrals,
+ * metric, its Cholesky factor, L^{-1} and the whitened tensor B.  The
+ * workspace stays borrowed until dfjk_plan_destroy (or the next setup) and
+ * must not be touched by the caller meanwhile.  Returns DFJK_E_NOT_POSDEF
+ * with the failing pivot in the message if the metric is not positive
+ * definite.  Synchronises `stream`. */
+int dfjk_setup_bytes(const dfjk_plan *plan, size_t *bytes);
+int dfjk_setup(dfjk_plan *plan, void *d_workspace, size_t bytes, void *stream);
+
+/* One J/K build.  Give exactly one of
+ *   d_C: nao x nocc occupied orbitals (D = 2 C C^T), 1 <= nocc <= nao, or
+ *   d_D: nao x nao symmetric density (nocc ignored; precision must be FP64).
+ * Outputs: d_J, d_K (nao x nao, full symmetric), d_E[2] = {E_J, E_K}.
+ * d_scratch must hold dfjk_build_bytes(plan, nocc, precision, d_D != NULL).
+ * No host synchronisation; safe to capture in a HIP graph. */
+int dfjk_build_bytes(const dfjk_plan *plan, int32_t nocc, int32_t precision,
+                     int32_t with_density, size_t *bytes);
+int dfjk_build(dfjk_plan *plan, const double *d_C, int32_t nocc, const double *d_D,
+               int32_t precision, double *d_J, double *d_K, double *d_E,
+               void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* Diagnostics for tests (valid after setup).  Dense copies of intermediate
+ * quantities in the caller's function order:
+ *   DFJK_EXPORT_INT3C   (naux x nao x nao) unwhitened (mu nu|P), screened
+ *                       entries 0
+ *   DFJK_EXPORT_B       (naux x nao x nao) whitened B, aux index in the
+ *                       internal order (B = L^{-1} U depends on the order)
+ *   DFJK_EXPORT_METRIC  (naux x naux) (P|Q)
+ *   DFJK_EXPORT_CHOL    (naux x naux) L, upper triangle 0, in the internal
+ *                       aux order of dfjk_plan_aux_order (a Cholesky factor
+ *                       depends on the order of the rows)
+ * Every other aux index follows the caller's aux function order. */
+typedef enum {
+    DFJK_EXPORT_INT3C = 0,
+    DFJK_EXPORT_B = 1,
+    DFJK_EXPORT_METRIC = 2,
+    DFJK_EXPORT_CHOL = 3
+} dfjk_export_kind;
+int dfjk_export(const dfjk_plan *plan, int32_t kind, double *d_out, void *stream);
+
+/* Sampled values of the unwhitened (kind 0) or whitened (kind 1) tensor:
+ * d_idx holds n triples (P, mu, nu) in caller order, d_out receives n values. */
+int dfjk_sample(const dfjk_plan *plan, int32_t kind, int64_t n, const int32_t *d_idx,
+                double *d_out, void *stream);
+
+/* Boys function F_0..F_mmax at n points (the device routine the integral
+ * kernels use): d_T[n] -> d_F[n * (mmax+1)], mmax <= 16. */
+int dfjk_boys(int32_t mmax, int64_t n, const double *d_T, double *d_F, void *stream);
+
+int dfjk_plan_destroy(dfjk_plan *plan);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *dfjk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFJK_H */

@@ -1,0 +1,512 @@
+// Gaussian-integral kernels for gfx950: Boys evaluation, Schwarz factors,
+// three-centre (mu nu|P) and the two-centre metric (P|Q).
+//
+// Method (McMurchie-Davidson with a solid-harmonic ket).  The bra product of
+// two AO shells is expanded in Hermite Gaussians at P with coefficients
+// E^{ab}_{tuv}.  A pure solid-harmonic Gaussian S_lm(r-C) exp(-g|r-C|^2) is,
+// by Hobson's theorem, exactly (2g)^{-l} sum_{tau+nu+phi=l} s_lm(tau,nu,phi)
+// d^tau_Cx d^nu_Cy d^phi_Cz exp(-g|r-C|^2), so the ket needs only Hermite
+// orders of total degree l and no Cartesian-to-spherical step.  Then
+//   (ab|c) = N_a N_b N_c 2 pi^{5/2} / (p g sqrt(p+g)) (-1)^l (2g)^{-l}
+//            sum_{tuv} E^{ab}_{tuv} sum_{|tau nu phi|=l} s_lm R_{t+tau,u+nu,v+phi}(alpha, P-C),
+// alpha = p g/(p+g).  The bra is taken to spherical form after the sums.
+// One thread evaluates one (shell pair, aux shell) triplet; a launch covers
+// one (la, lb, lc) class so every loop is unrolled at compile time.
+#include "dfjk_internal.h"
+#include "hermite.h"
+
+namespace dfjk {
+
+// Solid-harmonic monomial coefficients and the Boys Taylor table; one copy per
+// device, written once by ensure_device_constants.
+__constant__ double c_sph[kMaxLAux + 1][7][10];
+__device__ double g_boys[kBoysNT * kBoysNM];
+
+void upload_constants(const double coef[kMaxLAux + 1][7][10], hipStream_t s)
+{
+    (void)s;
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(c_sph), coef, sizeof(double) * (kMaxLAux + 1) * 70, 0,
+                            hipMemcpyHostToDevice);
+}
+
+void upload_boys_table(const double *host, size_t n, const double **dev_addr, hipError_t *err)
+{
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_boys), host, n * sizeof(double), 0, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_boys));
+        *dev_addr = static_cast<const double *>(ptr);
+    }
+    *err = e;
+}
+
+// --------------------------------------------------------------------------
+// Boys function on an array (tests the device routine the kernels use).
+
+template <int M>
+__global__ void k_boys_eval(int64_t n, const double *__restrict__ T, double *__restrict__ F,
+                            const double *__restrict__ tab)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double t = T[i];
+    if (!(t >= 0.0) || !(t < 1e300)) {   // negative, NaN or infinite: no table lookup
+#pragma unroll
+        for (int m = 0; m <= M; ++m) F[i * (M + 1) + m] = __builtin_nan("");
+        return;
+    }
+    double f[M + 1];
+    boys<M>(t, f, tab);
+#pragma unroll
+    for (int m = 0; m <= M; ++m) F[i * (M + 1) + m] = f[m];
+}
+
+void launch_boys_eval(int mmax, int64_t n, const double *T, double *F, const double *tab, hipStream_t s)
+{
+    const int bs = 256;
+    const unsigned nb = (unsigned)((n + bs - 1) / bs);
+#define BOYS_CASE(M) \
+    case M: hipLaunchKernelGGL(k_boys_eval<M>, dim3(nb), dim3(bs), 0, s, n, T, F, tab); break;
+    switch (mmax) {
+        BOYS_CASE(0) BOYS_CASE(1) BOYS_CASE(2) BOYS_CASE(3) BOYS_CASE(4) BOYS_CASE(5)
+        BOYS_CASE(6) BOYS_CASE(7) BOYS_CASE(8) BOYS_CASE(9) BOYS_CASE(10) BOYS_CASE(11)
+        BOYS_CASE(12) BOYS_CASE(13) BOYS_CASE(14) BOYS_CASE(15) BOYS_CASE(16)
+    }
+#undef BOYS_CASE
+}
+
+// --------------------------------------------------------------------------
+// Schwarz factors.  At coincident centres R_{tuv}(alpha, 0) vanishes unless
+// t, u, v are all even, and R_{2i,2j,2k} = (2i-1)!!(2j-1)!!(2k-1)!!
+// (-2 alpha)^{i+j+k} / (2(i+j+k)+1).
+
+constexpr double dfact_m1(int n)   // (n-1)!! for even n, (−1)!! = 1
+{
+    double r = 1.0;
+    for (int k = n - 1; k > 1; k -= 2) r *= k;
+    return r;
+}
+
+template <int L>
+__device__ __forceinline__ void hermite_R_origin(double alpha, double (&R)[nherm(L)])
+{
+    double pw[L / 2 + 1];
+    pw[0] = 1.0;
+#pragma unroll
+    for (int s = 1; s <= L / 2; ++s) pw[s] = pw[s - 1] * (-2.0 * alpha);
+#pragma unroll
+    for (int t = 0; t <= L; ++t)
+#pragma unroll
+        for (int u = 0; u + t <= L; ++u)
+#pragma unroll
+            for (int v = 0; v + u + t <= L; ++v) {
+                if ((t | u | v) & 1) {
+                    R[hidx(t, u, v)] = 0.0;
+                } else {
+                    const int s = (t + u + v) / 2;
+                    R[hidx(t, u, v)] = dfact_m1(t) * dfact_m1(u) * dfact_m1(v) * pw[s] / (2 * s + 1);
+                }
+            }
+}
+
+// Spherical-bra Hermite coefficients of function pair (ma, mb):
+// Es[tuv] = sum_{ca,cb} s_a[ma][ca] s_b[mb][cb] Ex Ey Ez.
+template <int LA, int LB>
+__device__ __forceinline__ void bra_sph(int ma, int mb, const double (&Ex)[LA + 1][LB + 1][LA + LB + 1],
+                                        const double (&Ey)[LA + 1][LB + 1][LA + LB + 1],
+                                        const double (&Ez)[LA + 1][LB + 1][LA + LB + 1],
+                                        double (&Es)[nherm(LA + LB)])
+{
+    constexpr int CA = ncart(LA), CB = ncart(LB);
+#pragma unroll
+    for (int i = 0; i < nherm(LA + LB); ++i) Es[i] = 0.0;
+#pragma unroll
+    for (int ca = 0; ca < CA; ++ca) {
+        const double sa = c_sph[LA][ma][ca];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const double s = sa * c_sph[LB][mb][cb];
+            const int ax = cart_pow(LA, ca, 0), ay = cart_pow(LA, ca, 1), az = cart_pow(LA, ca, 2);
+            const int bx = cart_pow(LB, cb, 0), by = cart_pow(LB, cb, 1), bz = cart_pow(LB, cb, 2);
+#pragma unroll
+            for (int t = 0; t <= ax + bx; ++t)
+#pragma unroll
+                for (int u = 0; u <= ay + by; ++u)
+#pragma unroll
+                    for (int v = 0; v <= az + bz; ++v)
+                        Es[hidx(t, u, v)] += s * Ex[ax][bx][t] * Ey[ay][by][u] * Ez[az][bz][v];
+        }
+    }
+}
+
+template <int LA, int LB>
+__device__ double schwarz_pair(double ea, double eb, double ax_, double ay_, double az_, double bx_,
+                               double by_, double bz_, double na, double nb)
+{
+    constexpr int LAB = LA + LB, L = 2 * LAB;
+    const double p = ea + eb, ip = 1.0 / p;
+    const double Px = (ea * ax_ + eb * bx_) * ip, Py = (ea * ay_ + eb * by_) * ip,
+                 Pz = (ea * az_ + eb * bz_) * ip;
+    const double mu = ea * eb * ip;
+    double Ex[LA + 1][LB + 1][LAB + 1], Ey[LA + 1][LB + 1][LAB + 1], Ez[LA + 1][LB + 1][LAB + 1];
+    hermite_E<LA, LB>(Px - ax_, Px - bx_, 0.5 * ip, exp(-mu * (ax_ - bx_) * (ax_ - bx_)), Ex);
+    hermite_E<LA, LB>(Py - ay_, Py - by_, 0.5 * ip, exp(-mu * (ay_ - by_) * (ay_ - by_)), Ey);
+    hermite_E<LA, LB>(Pz - az_, Pz - bz_, 0.5 * ip, exp(-mu * (az_ - bz_) * (az_ - bz_)), Ez);
+    double R[nherm(L)];
+    hermite_R_origin<L>(0.5 * p, R);
+    const double pref = kTwoPi52 / (p * p * sqrt(2.0 * p)) * (na * nb) * (na * nb);
+    double best = 0.0;
+    for (int ma = 0; ma < 2 * LA + 1; ++ma)
+        for (int mb = 0; mb < 2 * LB + 1; ++mb) {
+            double Es[nherm(LAB)];
+            bra_sph<LA, LB>(ma, mb, Ex, Ey, Ez, Es);
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+                for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+                    for (int v = 0; v + u + t <= LAB; ++v) {
+                        double inner = 0.0;
+#pragma unroll
+                        for (int t2 = 0; t2 <= LAB; ++t2)
+#pragma unroll
+                            for (int u2 = 0; u2 + t2 <= LAB; ++u2)
+#pragma unroll
+                                for (int v2 = 0; v2 + u2 + t2 <= LAB; ++v2) {
+                                    if (((t + t2) | (u + u2) | (v + v2)) & 1) continue;
+                                    const double sg = ((t2 + u2 + v2) & 1) ? -1.0 : 1.0;
+                                    inner += sg * Es[hidx(t2, u2, v2)] * R[hidx(t + t2, u + u2, v + v2)];
+                                }
+                        s += Es[hidx(t, u, v)] * inner;
+                    }
+            best = fmax(best, fabs(s));
+        }
+    return sqrt(best * pref);
+}
+
+__global__ void k_schwarz_pairs(int64_t npair, ShellsDev ao, double *__restrict__ q)
+{
+    const int64_t ab = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (ab >= npair) return;
+    int a = (int)((sqrt(8.0 * (double)ab + 1.0) - 1.0) * 0.5);
+    while ((int64_t)a * (a + 1) / 2 > ab) --a;
+    while ((int64_t)(a + 1) * (a + 2) / 2 <= ab) ++a;
+    int b = (int)(ab - (int64_t)a * (a + 1) / 2);
+    if (ao.l[a] < ao.l[b]) { const int t = a; a = b; b = t; }
+    const int la = ao.l[a], lb = ao.l[b];
+    double r = 0.0;
+#define SCH(LA, LB)                                                                                  \
+    r = schwarz_pair<LA, LB>(ao.exp[a], ao.exp[b], ao.x[a], ao.y[a], ao.z[a], ao.x[b], ao.y[b], ao.z[b], \
+                             ao.norm[a], ao.norm[b]);
+    if (la == 0) { SCH(0, 0) }
+    else if (la == 1) { if (lb == 0) { SCH(1, 0) } else { SCH(1, 1) } }
+    else { if (lb == 0) { SCH(2, 0) } else if (lb == 1) { SCH(2, 1) } else { SCH(2, 2) } }
+#undef SCH
+    q[ab] = r;
+}
+
+void launch_schwarz_pairs(int64_t npair, const ShellsDev &ao, double *q, hipStream_t s)
+{
+    const int bs = 128;
+    hipLaunchKernelGGL(k_schwarz_pairs, dim3((unsigned)((npair + bs - 1) / bs)), dim3(bs), 0, s, npair, ao, q);
+}
+
+// (c|c) of one solid-harmonic Gaussian, largest over m (all equal in exact
+// arithmetic by rotational invariance of the Coulomb operator).
+template <int LC>
+__device__ double schwarz_aux(double g, double nc)
+{
+    constexpr int CC = ncart(LC), L = 2 * LC;
+    double R[nherm(L)];
+    hermite_R_origin<L>(0.5 * g, R);
+    double scale = 1.0;
+    for (int k = 0; k < LC; ++k) scale /= (2.0 * g) * (2.0 * g);
+    const double pref = kTwoPi52 / (g * g * sqrt(2.0 * g)) * nc * nc * scale * ((LC & 1) ? -1.0 : 1.0);
+    double best = 0.0;
+    for (int m = 0; m < 2 * LC + 1; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < CC; ++i)
+#pragma unroll
+            for (int j = 0; j < CC; ++j) {
+                const int t = cart_pow(LC, i, 0) + cart_pow(LC, j, 0);
+                const int u = cart_pow(LC, i, 1) + cart_pow(LC, j, 1);
+                const int v = cart_pow(LC, i, 2) + cart_pow(LC, j, 2);
+                s += c_sph[LC][m][i] * c_sph[LC][m][j] * R[hidx(t, u, v)];
+            }
+        best = fmax(best, fabs(s * pref));
+    }
+    return sqrt(best);
+}
+
+__global__ void k_schwarz_aux(int32_t nsh, ShellsDev ax, double *__restrict__ q)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nsh) return;
+    const double g = ax.exp[c], nc = ax.norm[c];
+    double r;
+    switch (ax.l[c]) {
+    case 0: r = schwarz_aux<0>(g, nc); break;
+    case 1: r = schwarz_aux<1>(g, nc); break;
+    case 2: r = schwarz_aux<2>(g, nc); break;
+    default: r = schwarz_aux<3>(g, nc); break;
+    }
+    q[c] = r;
+}
+
+void launch_schwarz_aux(int32_t nsh, const ShellsDev &ax, double *q, hipStream_t s)
+{
+    const int bs = 128;
+    hipLaunchKernelGGL(k_schwarz_aux, dim3((nsh + bs - 1) / bs), dim3(bs), 0, s, nsh, ax, q);
+}
+
+// --------------------------------------------------------------------------
+// Three-centre integrals.
+
+struct Int3cArgs {
+    const int32_t *pa, *pb, *pf0;
+    const double *pq;
+    int32_t p_begin, p_end, c_begin, c_end;
+    ShellsDev ao, ax;
+    const double *boys;
+    double tau;
+    double *U;
+    int64_t ld;
+};
+
+template <int LA, int LB, int LC>
+__global__ __launch_bounds__(128) void k_int3c(Int3cArgs g)
+{
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1;
+    constexpr int CA = ncart(LA), CB = ncart(LB), CC = ncart(LC);
+    constexpr int LAB = LA + LB, L = LAB + LC;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int npc = g.c_end - g.c_begin;
+    const int64_t total = (int64_t)(g.p_end - g.p_begin) * npc;
+    if (tid >= total) return;
+    const int ip = g.p_begin + (int)(tid / npc);
+    const int ic = g.c_begin + (int)(tid % npc);
+    const int a = g.pa[ip], b = g.pb[ip];
+    double *out = g.U + (int64_t)g.pf0[ip] * g.ld + g.ax.off[ic];
+
+    if (g.pq[ip] * g.ax.q[ic] < g.tau) {
+#pragma unroll
+        for (int i = 0; i < NA * NB; ++i)
+#pragma unroll
+            for (int m = 0; m < NC; ++m) out[i * g.ld + m] = 0.0;
+        return;
+    }
+    const double ea = g.ao.exp[a], eb = g.ao.exp[b], gc = g.ax.exp[ic];
+    const double Ax = g.ao.x[a], Ay = g.ao.y[a], Az = g.ao.z[a];
+    const double Bx = g.ao.x[b], By = g.ao.y[b], Bz = g.ao.z[b];
+    const double Cx = g.ax.x[ic], Cy = g.ax.y[ic], Cz = g.ax.z[ic];
+    const double p = ea + eb, ipp = 1.0 / p;
+    const double Px = (ea * Ax + eb * Bx) * ipp, Py = (ea * Ay + eb * By) * ipp, Pz = (ea * Az + eb * Bz) * ipp;
+    const double mu = ea * eb * ipp;
+    double Ex[LA + 1][LB + 1][LAB + 1], Ey[LA + 1][LB + 1][LAB + 1], Ez[LA + 1][LB + 1][LAB + 1];
+    hermite_E<LA, LB>(Px - Ax, Px - Bx, 0.5 * ipp, exp(-mu * (Ax - Bx) * (Ax - Bx)), Ex);
+    hermite_E<LA, LB>(Py - Ay, Py - By, 0.5 * ipp, exp(-mu * (Ay - By) * (Ay - By)), Ey);
+    hermite_E<LA, LB>(Pz - Az, Pz - Bz, 0.5 * ipp, exp(-mu * (Az - Bz) * (Az - Bz)), Ez);
+
+    const double pg = p + gc;
+    const double alpha = p * gc / pg;
+    const double X = Px - Cx, Y = Py - Cy, Z = Pz - Cz;
+    double F[L + 1];
+    boys<L>(alpha * (X * X + Y * Y + Z * Z), F, g.boys);
+    double R[nherm(L)];
+    hermite_R<L>(alpha, X, Y, Z, F, R);
+
+    double ket = 1.0;
+#pragma unroll
+    for (int k = 0; k < LC; ++k) ket *= -0.5 / gc;    // (-1)^l (2g)^{-l}
+    const double pref = kTwoPi52 / (p * gc * sqrt(pg)) * ket * g.ao.norm[a] * g.ao.norm[b] * g.ax.norm[ic];
+
+#pragma unroll
+    for (int mc = 0; mc < NC; ++mc) {
+        // ket-contracted Hermite integrals W[tuv] = sum_k s_lm(k) R[tuv + k]
+        double W[nherm(LAB)];
+#pragma unroll
+        for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+            for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+                for (int v = 0; v + u + t <= LAB; ++v) {
+                    double w = 0.0;
+#pragma unroll
+                    for (int k = 0; k < CC; ++k)
+                        w += c_sph[LC][mc][k] *
+                             R[hidx(t + cart_pow(LC, k, 0), u + cart_pow(LC, k, 1), v + cart_pow(LC, k, 2))];
+                    W[hidx(t, u, v)] = w;
+                }
+        // Cartesian bra
+        double cart[CA][CB];
+#pragma unroll
+        for (int ca = 0; ca < CA; ++ca)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int ax = cart_pow(LA, ca, 0), ay = cart_pow(LA, ca, 1), az = cart_pow(LA, ca, 2);
+                const int bx = cart_pow(LB, cb, 0), by = cart_pow(LB, cb, 1), bz = cart_pow(LB, cb, 2);
+                double s = 0.0;
+#pragma unroll
+                for (int t = 0; t <= ax + bx; ++t) {
+                    double su = 0.0;
+#pragma unroll
+                    for (int u = 0; u <= ay + by; ++u) {
+                        double sv = 0.0;
+#pragma unroll
+                        for (int v = 0; v <= az + bz; ++v) sv += Ez[az][bz][v] * W[hidx(t, u, v)];
+                        su += Ey[ay][by][u] * sv;
+                    }
+                    s += Ex[ax][bx][t] * su;
+                }
+                cart[ca][cb] = s;
+            }
+        // spherical bra, two one-index transforms
+        double half[NA][CB];
+#pragma unroll
+        for (int ma = 0; ma < NA; ++ma)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                double s = 0.0;
+#pragma unroll
+                for (int ca = 0; ca < CA; ++ca) s += c_sph[LA][ma][ca] * cart[ca][cb];
+                half[ma][cb] = s;
+            }
+#pragma unroll
+        for (int ma = 0; ma < NA; ++ma)
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb) {
+                double s = 0.0;
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) s += c_sph[LB][mb][cb] * half[ma][cb];
+                out[(ma * NB + mb) * g.ld + mc] = pref * s;
+            }
+    }
+}
+
+template <int LA, int LB, int LC>
+static void launch_class(Int3cArgs g, hipStream_t s)
+{
+    const int64_t total = (int64_t)(g.p_end - g.p_begin) * (g.c_end - g.c_begin);
+    if (total <= 0) return;
+    const int bs = 128;
+    hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, g);
+}
+
+static ShellsDev ao_view(const Plan &p)
+{
+    return ShellsDev{p.d.ao_exp, p.d.ao_x, p.d.ao_y, p.d.ao_z, p.d.ao_norm, nullptr, p.d.ao_l, p.d.ao_off};
+}
+static ShellsDev ax_view(const Plan &p)
+{
+    return ShellsDev{p.d.ax_exp, p.d.ax_x, p.d.ax_y, p.d.ax_z, p.d.ax_norm, p.d.ax_q, p.d.ax_l, p.d.ax_off};
+}
+
+void launch_int3c(const Plan &p, hipStream_t s)
+{
+    Int3cArgs g{};
+    g.pa = p.d.sp_a; g.pb = p.d.sp_b; g.pf0 = p.d.sp_f0; g.pq = p.d.sp_q;
+    g.ao = ao_view(p); g.ax = ax_view(p);
+    g.boys = p.d.boys; g.tau = p.thresh; g.U = p.d.U; g.ld = p.naux_pad;
+    static const int cls_la[6] = {0, 1, 1, 2, 2, 2}, cls_lb[6] = {0, 0, 1, 0, 1, 2};
+    for (int pc = 0; pc < 6; ++pc) {
+        g.p_begin = p.sp_class[pc].begin; g.p_end = p.sp_class[pc].end;
+        if (g.p_end <= g.p_begin) continue;
+        for (int lc = 0; lc <= kMaxLAux; ++lc) {
+            g.c_begin = p.ax_class[lc].begin; g.c_end = p.ax_class[lc].end;
+            if (g.c_end <= g.c_begin) continue;
+            const int key = cls_la[pc] * 100 + cls_lb[pc] * 10 + lc;
+#define CLS(A, B, C) case A * 100 + B * 10 + C: launch_class<A, B, C>(g, s); break;
+            switch (key) {
+                CLS(0, 0, 0) CLS(0, 0, 1) CLS(0, 0, 2) CLS(0, 0, 3)
+                CLS(1, 0, 0) CLS(1, 0, 1) CLS(1, 0, 2) CLS(1, 0, 3)
+                CLS(1, 1, 0) CLS(1, 1, 1) CLS(1, 1, 2) CLS(1, 1, 3)
+                CLS(2, 0, 0) CLS(2, 0, 1) CLS(2, 0, 2) CLS(2, 0, 3)
+                CLS(2, 1, 0) CLS(2, 1, 1) CLS(2, 1, 2) CLS(2, 1, 3)
+                CLS(2, 2, 0) CLS(2, 2, 1) CLS(2, 2, 2) CLS(2, 2, 3)
+            }
+#undef CLS
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Two-centre metric (P|Q), both sides solid harmonic (Hobson on each):
+// (c|d) = N_c N_d 2 pi^{5/2}/(g d sqrt(g+d)) (2g)^{-lc} (-1)^{ld} (2d)^{-ld}
+//         sum_{k,k'} s_c(k) s_d(k') R_{k+k'}(alpha, C-D).
+
+struct Int2cArgs {
+    ShellsDev ax;
+    const double *boys;
+    double *V;
+    int64_t ld;
+    int32_t nsh;
+};
+
+template <int LC, int LD>
+__device__ void metric_block(const Int2cArgs &g, int c, int d)
+{
+    constexpr int L = LC + LD, CC = ncart(LC), CD = ncart(LD);
+    const double gc = g.ax.exp[c], gd = g.ax.exp[d];
+    const double X = g.ax.x[c] - g.ax.x[d], Y = g.ax.y[c] - g.ax.y[d], Z = g.ax.z[c] - g.ax.z[d];
+    const double sum = gc + gd, alpha = gc * gd / sum;
+    double F[L + 1];
+    boys<L>(alpha * (X * X + Y * Y + Z * Z), F, g.boys);
+    double R[nherm(L)];
+    hermite_R<L>(alpha, X, Y, Z, F, R);
+    double sc = 1.0;
+#pragma unroll
+    for (int k = 0; k < LC; ++k) sc *= 0.5 / gc;
+#pragma unroll
+    for (int k = 0; k < LD; ++k) sc *= -0.5 / gd;
+    const double pref = kTwoPi52 / (gc * gd * sqrt(sum)) * sc * g.ax.norm[c] * g.ax.norm[d];
+    const int oc = g.ax.off[c], od = g.ax.off[d];
+#pragma unroll
+    for (int mc = 0; mc < 2 * LC + 1; ++mc)
+#pragma unroll
+        for (int md = 0; md < 2 * LD + 1; ++md) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < CC; ++i) {
+                double inner = 0.0;
+#pragma unroll
+                for (int j = 0; j < CD; ++j)
+                    inner += c_sph[LD][md][j] * R[hidx(cart_pow(LC, i, 0) + cart_pow(LD, j, 0),
+                                                       cart_pow(LC, i, 1) + cart_pow(LD, j, 1),
+                                                       cart_pow(LC, i, 2) + cart_pow(LD, j, 2))];
+                s += c_sph[LC][mc][i] * inner;
+            }
+            s *= pref;
+            g.V[(int64_t)(oc + mc) * g.ld + od + md] = s;
+            g.V[(int64_t)(od + md) * g.ld + oc + mc] = s;
+        }
+}
+
+__global__ __launch_bounds__(128) void k_int2c(Int2cArgs g)
+{
+    const int64_t cd = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)g.nsh * (g.nsh + 1) / 2;
+    if (cd >= n) return;
+    int c = (int)((sqrt(8.0 * (double)cd + 1.0) - 1.0) * 0.5);
+    while ((int64_t)c * (c + 1) / 2 > cd) --c;
+    while ((int64_t)(c + 1) * (c + 2) / 2 <= cd) ++c;
+    const int d = (int)(cd - (int64_t)c * (c + 1) / 2);
+    const int key = g.ax.l[c] * 4 + g.ax.l[d];
+#define MB(A, B) case A * 4 + B: metric_block<A, B>(g, c, d); break;
+    switch (key) {
+        MB(0, 0) MB(0, 1) MB(0, 2) MB(0, 3) MB(1, 0) MB(1, 1) MB(1, 2) MB(1, 3)
+        MB(2, 0) MB(2, 1) MB(2, 2) MB(2, 3) MB(3, 0) MB(3, 1) MB(3, 2) MB(3, 3)
+    }
+#undef MB
+}
+
+void launch_int2c(const Plan &p, hipStream_t s)
+{
+    Int2cArgs g{ax_view(p), p.d.boys, p.d.V, p.naux_pad, p.nsh_aux};
+    const int64_t n = (int64_t)p.nsh_aux * (p.nsh_aux + 1) / 2;
+    const int bs = 128;
+    hipLaunchKernelGGL(k_int2c, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, g);
+}
+
+}  // namespace dfjk

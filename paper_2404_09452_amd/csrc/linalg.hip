@@ -1,0 +1,190 @@
+// Dense FP64 linear algebra on the auxiliary metric, gfx950:
+//   - blocked right-looking Cholesky V = L L^T (64-wide panels; the diagonal
+//     block is factored in LDS by one workgroup, the panel below it is solved
+//     row by row, the trailing matrix is updated on FP64 MFMA),
+//   - L^{-1} by blocked forward substitution on the identity,
+//   - the whitening B = U L^{-T}-transposed product, i.e. B[f][P] =
+//     sum_{Q<=P} U[f][Q] Linv[P][Q], as one MFMA GEMM that stops each output
+//     tile's k loop at its last column (Linv is lower triangular).
+// Matrices are row-major with the padded leading dimension npad (a multiple
+// of 64); the pad block of the metric is the identity so every factor stays
+// well defined and the pad rows/columns of B are exactly zero.
+#include <climits>
+
+#include "dfjk_internal.h"
+#include "gemm_f64.h"
+
+namespace dfjk {
+
+constexpr int NBK = 64;   // panel width
+
+__global__ void k_metric_pad(double *V, int64_t n, int64_t npad)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= npad * npad) return;
+    const int64_t r = i / npad, c = i % npad;
+    if (r >= n || c >= n) V[i] = (r == c) ? 1.0 : 0.0;
+}
+
+void launch_metric_pad(double *V, int64_t n, int64_t npad, hipStream_t s)
+{
+    const int64_t tot = npad * npad;
+    hipLaunchKernelGGL(k_metric_pad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V, n, npad);
+}
+
+// Factor the 64x64 diagonal block at (k0, k0) in place.  A pivot <= 0 is
+// recorded (smallest index wins) and replaced by 1 so the remaining steps stay
+// finite; the host reports the recorded index.
+__global__ __launch_bounds__(256) void k_potrf_diag(double *A, int64_t ld, int64_t k0, int32_t *status)
+{
+    __shared__ double S[NBK][NBK + 1];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < NBK * NBK; i += 256) S[i / NBK][i % NBK] = A[(k0 + i / NBK) * ld + k0 + i % NBK];
+    __syncthreads();
+    for (int j = 0; j < NBK; ++j) {
+        if (tid == 0) {
+            double d = S[j][j];
+            if (!(d > 0.0)) {
+                atomicMin(status, (int32_t)(k0 + j));
+                d = 1.0;
+            }
+            S[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        const double djj = S[j][j];
+        for (int i = j + 1 + tid; i < NBK; i += 256) S[i][j] /= djj;
+        __syncthreads();
+        // trailing update of the lower triangle inside the block
+        const int w = NBK - 1 - j;
+        for (int e = tid; e < w * w; e += 256) {
+            const int i = j + 1 + e / w, l = j + 1 + e % w;
+            if (l <= i) S[i][l] -= S[i][j] * S[l][j];
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < NBK * NBK; i += 256) {
+        const int r = i / NBK, c = i % NBK;
+        A[(k0 + r) * ld + k0 + c] = (c <= r) ? S[r][c] : 0.0;
+    }
+}
+
+// Panel: rows i0.. of block column k0 get L_ik = A_ik L_kk^{-T}; one
+// workgroup per 64-row block, one thread per row (x L_kk^T = a, forward).
+__global__ __launch_bounds__(64) void k_trsm_panel(double *A, int64_t ld, int64_t k0)
+{
+    __shared__ double Lk[NBK][NBK + 1];
+    __shared__ double X[NBK][NBK + 1];
+    const int tid = threadIdx.x;
+    const int64_t r0 = k0 + NBK * (1 + (int64_t)blockIdx.x);
+    for (int i = tid; i < NBK * NBK; i += NBK) {
+        Lk[i / NBK][i % NBK] = A[(k0 + i / NBK) * ld + k0 + i % NBK];
+        X[i / NBK][i % NBK] = A[(r0 + i / NBK) * ld + k0 + i % NBK];
+    }
+    __syncthreads();
+    for (int j = 0; j < NBK; ++j) {
+        double v = X[tid][j];
+        for (int l = 0; l < j; ++l) v -= X[tid][l] * Lk[j][l];
+        X[tid][j] = v / Lk[j][j];
+    }
+    __syncthreads();
+    for (int i = tid; i < NBK * NBK; i += NBK) A[(r0 + i / NBK) * ld + k0 + i % NBK] = X[i / NBK][i % NBK];
+}
+
+void launch_cholesky(double *A, int64_t npad, int32_t *status, hipStream_t s)
+{
+    const int64_t nb = npad / NBK;
+    for (int64_t k = 0; k < nb; ++k) {
+        const int64_t k0 = k * NBK;
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, npad, k0, status);
+        const int64_t rest = nb - k - 1;
+        if (rest == 0) break;
+        hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)rest), dim3(NBK), 0, s, A, npad, k0);
+        // A22 -= L21 L21^T on the lower tiles of the trailing matrix
+        GemmArgs g{};
+        const int64_t t0 = k0 + NBK;
+        g.A = A + t0 * npad + k0; g.lda = npad;
+        g.B = A + t0 * npad + k0; g.ldb = npad;
+        g.C = A + t0 * npad + t0; g.ldc = npad;
+        g.M = g.N = npad - t0;
+        g.k_begin = 0; g.k_end = NBK; g.ksplit = NBK;
+        g.alpha = -1.0; g.beta = 1.0; g.lower = 1;
+        gemm_f64<64, false>(g, 1, s);
+    }
+}
+
+__global__ void k_zero_upper(double *A, int64_t npad)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= npad * npad) return;
+    if (i % npad > i / npad) A[i] = 0.0;
+}
+
+__global__ void k_identity(double *A, int64_t npad)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= npad * npad) return;
+    A[i] = (i % npad == i / npad) ? 1.0 : 0.0;
+}
+
+// X[i0 + r][c] <- (L_ii^{-1} X_i)[r][c] for c < ncols; one thread per column.
+__global__ __launch_bounds__(64) void k_trtri_diag(const double *L, double *X, int64_t ld, int64_t i0,
+                                                    int64_t ncols)
+{
+    __shared__ double Li[NBK][NBK + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NBK * NBK; e += NBK) Li[e / NBK][e % NBK] = L[(i0 + e / NBK) * ld + i0 + e % NBK];
+    __syncthreads();
+    const int64_t c = blockIdx.x * (int64_t)NBK + tid;
+    if (c >= ncols) return;
+    double x[NBK];
+#pragma unroll
+    for (int r = 0; r < NBK; ++r) x[r] = X[(i0 + r) * ld + c];
+#pragma unroll
+    for (int r = 0; r < NBK; ++r) {
+        double v = x[r];
+#pragma unroll
+        for (int l = 0; l < r; ++l) v -= Li[r][l] * x[l];
+        x[r] = v / Li[r][r];
+    }
+#pragma unroll
+    for (int r = 0; r < NBK; ++r) X[(i0 + r) * ld + c] = x[r];
+}
+
+void launch_trtri(const double *L, double *X, int64_t npad, hipStream_t s)
+{
+    const int64_t tot = npad * npad;
+    hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       const_cast<double *>(L), npad);
+    hipLaunchKernelGGL(k_identity, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, npad);
+    const int64_t nb = npad / NBK;
+    for (int64_t i = 0; i < nb; ++i) {
+        const int64_t i0 = i * NBK, w = i0 + NBK;
+        hipLaunchKernelGGL(k_trtri_diag, dim3((unsigned)((w + NBK - 1) / NBK)), dim3(NBK), 0, s, L, X, npad,
+                           i0, w);
+        if (i + 1 == nb) break;
+        // X[j rows > i][0:w] -= L[j rows][i cols] X[i rows][0:w]
+        GemmArgs g{};
+        g.A = L + w * npad + i0; g.lda = npad;
+        g.B = X + i0 * npad; g.ldb = npad;
+        g.C = X + w * npad; g.ldc = npad;
+        g.M = npad - w; g.N = w;
+        g.k_begin = 0; g.k_end = NBK; g.ksplit = NBK;
+        g.alpha = -1.0; g.beta = 1.0;
+        gemm_f64<64, true>(g, 1, s);
+    }
+}
+
+void launch_whiten(const double *U, const double *Linv, double *B, int64_t nf_pad, int64_t npad, hipStream_t s)
+{
+    GemmArgs g{};
+    g.A = U; g.lda = npad;
+    g.B = Linv; g.ldb = npad;
+    g.C = B; g.ldc = npad;
+    g.M = nf_pad; g.N = npad;
+    g.k_begin = 0; g.k_end = npad; g.ksplit = npad;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.tri_k = 1;
+    gemm_f64<128, false>(g, 1, s);
+}
+
+}  // namespace dfjk

@@ -1,0 +1,190 @@
+"""Python binding of the DF-J/K library (argument marshalling only).
+
+Every step of the build runs in the HIP kernels behind the C ABI; this module
+turns numpy/torch arguments into pointers, allocates the device workspaces
+with torch and passes torch's current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
+PRECISION = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3}
+EXPORT_INT3C, EXPORT_B, EXPORT_METRIC, EXPORT_CHOL = 0, 1, 2, 3
+
+STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "NOT_POSDEF", 4: "OOM", 5: "DEVICE",
+          6: "NO_DEVICE", 7: "STATE"}
+
+
+class DFJKError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("dfjk %s: %s" % (STATUS.get(code, code), message))
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+        self.message = message
+
+
+def _check(rc):
+    if rc != 0:
+        msg = N.lib().dfjk_last_error()
+        raise DFJKError(rc, msg.decode() if msg else "")
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Plan:
+    """One molecule: host preparation at construction, then screen/setup once
+    and build any number of times.
+
+    coords: (natm, 3) Bohr; ao and aux: (atom, l, exponent) arrays."""
+
+    def __init__(self, coords, ao_atom, ao_l, ao_exp, aux_atom, aux_l, aux_exp, schwarz_thresh=1e-14):
+        L = N.lib()
+        self._keep = []
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+
+        def basis(atom, l, e):
+            a = np.ascontiguousarray(atom, dtype=np.int32)
+            ll = np.ascontiguousarray(l, dtype=np.int32)
+            ee = np.ascontiguousarray(e, dtype=np.float64)
+            self._keep += [a, ll, ee]
+            return N.Basis(len(ll), a.ctypes.data_as(N.P_i32), ll.ctypes.data_as(N.P_i32),
+                           ee.ctypes.data_as(N.P_dbl))
+
+        ao = basis(ao_atom, ao_l, ao_exp)
+        aux = basis(aux_atom, aux_l, aux_exp)
+        opt = N.Options(float(schwarz_thresh))
+        h = ctypes.c_void_p()
+        _check(L.dfjk_plan_create(len(coords), coords.ctypes.data_as(N.P_dbl), ctypes.byref(ao),
+                                  ctypes.byref(aux), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+        self._scratch = {}
+        inf = self.info()
+        self.nao, self.naux = inf["nao"], inf["naux"]
+
+    @classmethod
+    def from_molecule(cls, mol, schwarz_thresh=1e-14):
+        return cls(mol.coords, mol.ao_atom, mol.ao_l, mol.ao_exp, mol.aux_atom, mol.aux_l, mol.aux_exp,
+                   schwarz_thresh=schwarz_thresh)
+
+    # -- facts -------------------------------------------------------------
+    def info(self):
+        inf = N.Info()
+        _check(N.lib().dfjk_plan_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in N.Info._fields_}
+
+    def aux_order(self):
+        out = np.zeros(self.naux, dtype=np.int32)
+        _check(N.lib().dfjk_plan_aux_order(self._h, out.ctypes.data_as(N.P_i32)))
+        return out
+
+    # -- phases ------------------------------------------------------------
+    def screen(self, stream=None):
+        n = ctypes.c_size_t()
+        _check(N.lib().dfjk_screen_bytes(self._h, ctypes.byref(n)))
+        scratch = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+        _check(N.lib().dfjk_screen(self._h, _ptr(scratch), n.value, _stream_handle(stream)))
+        return self
+
+    def setup_bytes(self):
+        n = ctypes.c_size_t()
+        _check(N.lib().dfjk_setup_bytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def setup(self, stream=None):
+        nbytes = self.setup_bytes()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        _check(N.lib().dfjk_setup(self._h, _ptr(self._ws), self._ws.numel(), _stream_handle(stream)))
+        return self
+
+    def build_bytes(self, nocc, precision="fp64", with_density=False):
+        n = ctypes.c_size_t()
+        _check(N.lib().dfjk_build_bytes(self._h, int(nocc), PRECISION[precision], int(with_density),
+                                        ctypes.byref(n)))
+        return n.value
+
+    def scratch(self, nocc, precision="fp64", with_density=False):
+        key = (int(nocc), precision, bool(with_density))
+        if key not in self._scratch:
+            self._scratch[key] = torch.empty(self.build_bytes(nocc, precision, with_density),
+                                             dtype=torch.uint8, device="cuda")
+        return self._scratch[key]
+
+    def build(self, C=None, D=None, precision="fp64", out=None, stream=None):
+        """J, K (nao x nao) and E = [E_J, E_K] as float64 CUDA tensors."""
+        if (C is None) == (D is None):
+            raise ValueError("give exactly one of C and D")
+        dev = torch.device("cuda")
+        if C is not None:
+            C = torch.as_tensor(C, dtype=torch.float64, device=dev).contiguous()
+            if C.dim() != 2 or C.shape[0] != self.nao:
+                raise ValueError("C must be (nao, nocc)")
+            nocc = C.shape[1]
+        else:
+            D = torch.as_tensor(D, dtype=torch.float64, device=dev).contiguous()
+            if tuple(D.shape) != (self.nao, self.nao):
+                raise ValueError("D must be (nao, nao)")
+            nocc = 0
+        if out is None:
+            J = torch.empty((self.nao, self.nao), dtype=torch.float64, device=dev)
+            K = torch.empty_like(J)
+            E = torch.empty(2, dtype=torch.float64, device=dev)
+        else:
+            J, K, E = out
+        scr = self.scratch(nocc if C is not None else 1, precision, D is not None)
+        _check(N.lib().dfjk_build(self._h, _ptr(C), int(nocc), _ptr(D), PRECISION[precision], _ptr(J),
+                                  _ptr(K), _ptr(E), _ptr(scr), scr.numel(), _stream_handle(stream)))
+        return J, K, E
+
+    # -- diagnostics -------------------------------------------------------
+    def export(self, kind, stream=None):
+        if kind in (EXPORT_INT3C, EXPORT_B):
+            shape = (self.naux, self.nao, self.nao)
+        else:
+            shape = (self.naux, self.naux)
+        out = torch.empty(shape, dtype=torch.float64, device="cuda")
+        _check(N.lib().dfjk_export(self._h, int(kind), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def sample(self, kind, idx, stream=None):
+        idx = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device="cuda").contiguous()
+        n = idx.shape[0]
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(N.lib().dfjk_sample(self._h, int(kind), n, _ptr(idx), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().dfjk_plan_destroy(self._h)
+            self._h = None
+        self._ws = None
+        self._scratch = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def boys(mmax, T, stream=None):
+    """F_0..F_mmax at the points T (CUDA float64 tensor) with the device routine."""
+    T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
+    F = torch.empty((T.numel(), mmax + 1), dtype=torch.float64, device="cuda")
+    _check(N.lib().dfjk_boys(int(mmax), T.numel(), _ptr(T), _ptr(F), _stream_handle(stream)))
+    return F

@@ -1,0 +1,139 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Tolerances: the plain FP64 path must agree with the oracle to 1e-10 relative
+(max |diff| / max |oracle|) on J and K and on E_J, E_K; per-kernel checks use
+tighter bounds where the arithmetic allows (integrals 1e-12 relative plus the
+screening threshold, Boys 1e-14 relative)."""
+import numpy as np
+import pytest
+
+import oracle
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2404_09452_amd import dfjk as G  # noqa: E402
+
+TAU = 1e-14
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def case(n, seed=None, box=None):
+    if n == 1:
+        z, x = W.water_monomer()
+    else:
+        z, x = W.water_cluster(n, box or W.cluster_box(n), seed if seed is not None else 100 + n)
+    mol = W.make_molecule(z, x)
+    S = W.overlap_by_quadrature(mol)
+    C = W.occupied_orbitals(S, mol.nelec // 2, 7 + n)
+    return mol, S, C
+
+
+@pytest.fixture(scope="module")
+def water1():
+    mol, S, C = case(1)
+    U = oracle.int3c(mol)
+    V = oracle.int2c(mol)
+    B, L = oracle.whitened_3c(mol, U)
+    ref = oracle.jk_from_B(B, C=C)
+    plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
+    return dict(mol=mol, C=C, U=U, V=V, B=B, ref=ref, plan=plan)
+
+
+def test_boys_device_matches_oracle():
+    T = np.concatenate([[0.0, 1e-12, 1e-6], np.linspace(0.0, 45.0, 1801), [39.975, 39.99, 40.0, 40.01],
+                        np.logspace(-3, 3, 200)])
+    F = G.boys(16, T).cpu().numpy()
+    ref = np.array([oracle.boys(16, t) for t in T])
+    assert rel(F, ref) <= 1e-14
+    relmax = float(np.max(np.abs(F - ref) / np.abs(ref)))
+    assert relmax <= 5e-14, relmax
+
+
+def test_int3c_water(water1):
+    got = water1["plan"].export(G.EXPORT_INT3C).cpu().numpy()
+    ref = water1["U"]
+    assert np.all(np.abs(got - ref) <= 1e-12 * np.abs(ref).max() + 2 * TAU)
+
+
+def test_metric_and_cholesky_water(water1):
+    plan = water1["plan"]
+    V = plan.export(G.EXPORT_METRIC).cpu().numpy()
+    assert rel(V, water1["V"]) <= 1e-13
+    order = plan.aux_order()
+    L = plan.export(G.EXPORT_CHOL).cpu().numpy()
+    Lref = oracle.cholesky(water1["V"][np.ix_(order, order)])
+    assert rel(L, Lref) <= 1e-11
+
+
+def test_whitened_water(water1):
+    """B = L^{-1} U depends on the aux order through L: compare against the
+    oracle's whitening of the metric permuted into the library's order."""
+    plan = water1["plan"]
+    order = plan.aux_order()
+    got = plan.export(G.EXPORT_B).cpu().numpy()
+    Lref = oracle.cholesky(water1["V"][np.ix_(order, order)])
+    U = water1["U"][order]
+    Bref = oracle.forward_subst(Lref, U.reshape(U.shape[0], -1)).reshape(U.shape)
+    assert rel(got, Bref) <= 1e-11
+
+
+def test_jk_water_c_route(water1):
+    J, K, E = water1["plan"].build(C=water1["C"])
+    ref = water1["ref"]
+    J, K, E = J.cpu().numpy(), K.cpu().numpy(), E.cpu().numpy()
+    assert rel(J, ref["J"]) <= 1e-10
+    assert rel(K, ref["K"]) <= 1e-10
+    assert abs(E[0] - ref["EJ"]) <= 1e-10 * abs(ref["EJ"])
+    assert abs(E[1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
+
+
+def test_jk_water_d_route(water1):
+    D = oracle.density(water1["C"])
+    J, K, E = water1["plan"].build(D=D)
+    ref = water1["ref"]
+    assert rel(J.cpu().numpy(), ref["J"]) <= 1e-10
+    assert rel(K.cpu().numpy(), ref["K"]) <= 1e-10
+    E = E.cpu().numpy()
+    assert abs(E[1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
+
+
+def test_build_is_bitwise_deterministic(water1):
+    a = [t.cpu().numpy().copy() for t in water1["plan"].build(C=water1["C"])]
+    b = [t.cpu().numpy().copy() for t in water1["plan"].build(C=water1["C"])]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_jk_clusters(n):
+    """Several tiles and ragged tails: nao = 30 n, naux = 87 n."""
+    mol, S, C = case(n)
+    ref = oracle.dfjk(mol, C=C)
+    plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
+    J, K, E = (t.cpu().numpy() for t in plan.build(C=C))
+    assert rel(J, ref["J"]) <= 1e-10
+    assert rel(K, ref["K"]) <= 1e-10
+    assert abs(E[0] - ref["EJ"]) <= 1e-10 * abs(ref["EJ"])
+    assert abs(E[1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_precision_error_is_reported(prec):
+    mol, S, C = case(3)
+    plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
+    J64, K64, E64 = (t.cpu().numpy() for t in plan.build(C=C))
+    J, K, E = (t.cpu().numpy() for t in plan.build(C=C, precision=prec))
+    dEJ, dEK, dK = abs(E[0] - E64[0]), abs(E[1] - E64[1]), np.abs(K - K64).max()
+    print("%s: |dE_J| %.3e |dE_K| %.3e max|dK| %.3e (E_K %.6f)" % (prec, dEJ, dEK, dK, E64[1]))
+    assert np.array_equal(J, J64)          # J and E_J stay FP64
+    assert dEJ == 0.0
+    bound = 1e-5 if prec == "fp32" else 1e-3
+    assert dEK <= bound * abs(E64[1])
