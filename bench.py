@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""DF-J/K build throughput on one MI355X.
+
+One step is one whole job on the 32-water cluster (960 AO, 2,784 aux, 160
+occupied orbitals; 10 A box, O-O >= 2.6 A, geometry seed 1): host
+preparation, Schwarz screening, three-centre integrals, metric, Cholesky,
+L^{-1}, whitening, then 10 SCF-like J/K builds with perturbed occupied
+orbitals.  `value` is completed builds per second over the timed steps
+(setup included); the steady-state time of one build is reported beside it.
+FP64 is the headline; FP32 and BF16x3 K contractions are timed the same way
+and their energy errors against the FP64 path are reported.
+
+The roofline entry is the dominant kernel (the FP64 K contraction, X X^T on
+FP64 MFMA), timed live by HIP events the library records on its own stream.
+The CPU baseline is the FP64 oracle timed on a bounded sample of the same
+job and scaled to builds per second (see cpu_baseline.sample).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NBUILDS = 10
+PEAK_F64_TFLOPS = 78.6
+PEAK_F32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def make_inputs(n=32, box=10.0, geom_seed=1, cocc_seed=1):
+    import workload as W
+    z, x = W.water_cluster(n, box, geom_seed)
+    mol = W.make_molecule(z, x)
+    S = W.overlap_by_quadrature(mol)
+    C0 = W.occupied_orbitals(S, mol.nelec // 2, cocc_seed)
+    Cs = [W.perturbed_orbitals(C0, S, k, eps=1e-2, seed=1000) for k in range(NBUILDS)]
+    return mol, S, Cs
+
+
+def run_job(Plan, mol, Cd, precision, bufs, profile):
+    plan = Plan.from_molecule(mol, schwarz_thresh=1e-14)
+    if profile:
+        plan.profile(True)
+    plan.screen().setup()
+    outs = []
+    for k, C in enumerate(Cd):
+        J, K, E = bufs[k]
+        plan.build(C=C, precision=precision, out=(J, K, E))
+        outs.append((J, K, E))
+    return plan, outs
+
+
+def cpu_baseline(mol, Cs, target_s=20.0):
+    """The FP64 oracle on a bounded sample of the same job, scaled to builds/s.
+
+    Sample: (a) three-centre integrals for every 44th aux shell (all AO pairs),
+    scaled by the shell count; (b) the full metric; (c) the full Cholesky;
+    (d) forward substitution of 4096 of the nao^2 pair columns, scaled;
+    (e) one build's J and K over a slab of 32 aux functions, scaled by naux
+    and by 10 builds."""
+    import numpy as np
+    import oracle
+    t = {}
+    nsh = len(mol.aux_l)
+    pick = np.arange(0, nsh, 44)
+    t0 = time.perf_counter()
+    slabs = [oracle.int3c(mol, int(c), int(c) + 1) for c in pick]
+    t["int3c"] = (time.perf_counter() - t0) * nsh / len(pick)
+    t0 = time.perf_counter()
+    V = oracle.int2c(mol)
+    t["metric"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L = oracle.cholesky(V)
+    t["cholesky"] = time.perf_counter() - t0
+    nao, naux = mol.nao, mol.naux
+    rng = np.random.default_rng(0)
+    U = np.concatenate([s.reshape(s.shape[0], -1) for s in slabs])
+    cols = rng.choice(nao * nao, size=4096, replace=False)
+    Ufull = np.zeros((naux, 4096))
+    Ufull[: U.shape[0]] = U[:, cols]
+    t0 = time.perf_counter()
+    oracle.forward_subst(L, Ufull)
+    t["whiten"] = (time.perf_counter() - t0) * (nao * nao) / 4096
+    Bslab = np.concatenate(slabs)[:32]
+    t0 = time.perf_counter()
+    oracle.jk_from_B(Bslab, C=Cs[0])
+    t["build"] = (time.perf_counter() - t0) * naux / Bslab.shape[0]
+    total = t["int3c"] + t["metric"] + t["cholesky"] + t["whiten"] + NBUILDS * t["build"]
+    return {
+        "value": NBUILDS / total,
+        "unit": "builds/s",
+        "cores": int(oracle.num_threads()),
+        "kind": "oracle",
+        "sample": ("water32 job (setup + 10 builds) timed on a sample: int3c for every 44th aux shell "
+                   "(x%.1f), full metric and Cholesky, forward substitution of 4096 of %d pair columns, "
+                   "J/K of one build over 32 of %d aux functions; each part scaled to the full job"
+                   % (nsh / len(pick), nao * nao, naux)),
+        "seconds_extrapolated": {k: round(v, 3) for k, v in t.items()},
+        "job_seconds_extrapolated": round(total, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the DF-J/K build would shard).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2404_09452_amd.dfjk import Plan
+
+    dev = torch.device("cuda")
+    print("bench: building inputs (32-water cluster)", file=sys.stderr, flush=True)
+    mol, S, Cs = make_inputs()
+    Cd = [torch.as_tensor(C, device=dev) for C in Cs]
+    nao = mol.nao
+    bufs = [(torch.empty((nao, nao), dtype=torch.float64, device=dev),
+             torch.empty((nao, nao), dtype=torch.float64, device=dev),
+             torch.empty(2, dtype=torch.float64, device=dev)) for _ in range(NBUILDS)]
+
+    results = {}
+    ref_E = None
+    ref_K = None
+    for prec in (["fp64"] + ([] if args.no_mixed else ["fp32", "bf16x3"])):
+        for w in range(args.warmup):
+            run_job(Plan, mol, Cd, prec, bufs, profile=False)
+        torch.cuda.synchronize()
+        print("bench: timing %d steps, %s" % (args.steps, prec), file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        stage_ms, stage_n = {}, {}
+        for s in range(args.steps):
+            plan, outs = run_job(Plan, mol, Cd, prec, bufs, profile=True)
+            torch.cuda.synchronize()
+            for k, (ms, n) in plan.profile_read().items():
+                stage_ms[k] = stage_ms.get(k, 0.0) + ms
+                stage_n[k] = stage_n.get(k, 0) + n
+            info = plan.info()
+            plan.close()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        E = np.array([o[2].cpu().numpy() for o in outs])
+        K_last = outs[-1][1].cpu().numpy()
+        setup_ms = sum(stage_ms[k] for k in stage_ms if k.startswith("setup.")) / args.steps
+        build_ms = sum(stage_ms[k] for k in stage_ms if k.startswith("build.")) / (args.steps * NBUILDS)
+        r = {
+            "builds_per_s": NBUILDS * args.steps / dt,
+            "ms_per_step": 1000.0 * dt / args.steps,
+            "ms_per_build_steady": build_ms,
+            "setup_ms": setup_ms,
+            "stages_ms_per_launch": {k: round(stage_ms[k] / max(stage_n[k], 1), 4) for k in stage_ms},
+            "stage_launches": stage_n,
+            "E_J": E[:, 0].tolist(),
+            "E_K": E[:, 1].tolist(),
+        }
+        if prec == "fp64":
+            ref_E, ref_K = E, K_last
+            r["screening"] = {k: info[k] for k in ("sig_shell_pairs", "nshell_pairs", "nf", "triplets_kept")}
+        else:
+            r["max_abs_dE_J"] = float(np.abs(E[:, 0] - ref_E[:, 0]).max())
+            r["max_abs_dE_K"] = float(np.abs(E[:, 1] - ref_E[:, 1]).max())
+            r["max_abs_dK"] = float(np.abs(K_last - ref_K).max())
+        results[prec] = r
+        print("bench: %s %.2f builds/s, %.3f ms/build steady, setup %.1f ms" %
+              (prec, r["builds_per_s"], build_ms, setup_ms), file=sys.stderr, flush=True)
+
+    f64 = results["fp64"]
+    naux, nocc = mol.naux, mol.nelec // 2
+    k_flops = float(nao) * (nao + 1) * naux * nocc        # lower triangle of 2 X X^T, useful flops
+    k_ms = f64["stages_ms_per_launch"]["build.K"]
+    achieved = k_flops / (k_ms * 1e-3) / 1e12
+    roofline = {"kernel": "build.K (FP64 MFMA X X^T, k_gemm_f64<128>)", "bound": "mfma",
+                "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": k_flops, "ms_per_launch": k_ms}
+    for prec, peak in (("fp32", PEAK_F32_TFLOPS), ("bf16x3", PEAK_BF16_TFLOPS / 3.0)):
+        if prec in results:
+            ms = results[prec]["stages_ms_per_launch"]["build.K"]
+            results[prec]["K_tflops"] = round(k_flops / (ms * 1e-3) / 1e12, 2)
+            results[prec]["K_frac_of_peak"] = round(k_flops / (ms * 1e-3) / 1e12 / peak, 4)
+
+    cpu = None
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(mol, Cs)
+
+    line = {
+        "metric": "DF-J/K builds/sec + ms per build (FP64 vs mixed, |dE|<=1e-6 Eh); p99 serve latency",
+        "value": round(f64["builds_per_s"], 3),
+        "unit": "builds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f64["ms_per_step"], 3),
+        "ms_per_build": round(f64["ms_per_build_steady"], 3),
+        "setup_ms": round(f64["setup_ms"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "water32: 32-water cluster, 960 AO / 2784 aux / nocc 160, "
+                               "Schwarz 1e-14, setup + 10 builds per step",
+                   "nao": nao, "naux": naux, "nocc": nocc, "builds_per_step": NBUILDS},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "mixed": {k: v for k, v in results.items() if k != "fp64"},
+        "fp64_detail": {k: v for k, v in f64.items() if k not in ("E_J", "E_K")},
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,17 @@ int dfjk_sample(const dfjk_plan *plan, int32_t kind, int64_t n, const int32_t *d
  * kernels use): d_T[n] -> d_F[n * (mmax+1)], mmax <= 16. */
 int dfjk_boys(int32_t mmax, int64_t n, const double *d_T, double *d_F, void *stream);
 
+/* Stage profiler.  With dfjk_profile(plan, 1) every later setup and build
+ * records a pair of HIP events around each stage on its stream (no host
+ * synchronisation).  dfjk_profile_read waits for the recorded events, writes
+ * the summed milliseconds and the number of timed launches of each of the
+ * DFJK_NSTAGES stages (host arrays), and clears the record.
+ * dfjk_stage_name(i) names stage i ("build.K", ...). */
+#define DFJK_NSTAGES 10
+int dfjk_profile(dfjk_plan *plan, int32_t on);
+int dfjk_profile_read(dfjk_plan *plan, double *ms, int32_t *count);
+const char *dfjk_stage_name(int32_t stage);
+
 int dfjk_plan_destroy(dfjk_plan *plan);
 
 /* Thread-local description of the last error on this thread ("" if none). */

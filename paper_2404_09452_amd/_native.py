@@ -44,6 +44,9 @@ SIGNATURES = {
     "dfjk_export": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "dfjk_sample": (c_i32, [c_vp, c_i32, c_i64, c_vp, c_vp, c_vp]),
     "dfjk_boys": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp]),
+    "dfjk_profile": (c_i32, [c_vp, c_i32]),
+    "dfjk_profile_read": (c_i32, [c_vp, P_dbl, P_i32]),
+    "dfjk_stage_name": (ctypes.c_char_p, [c_i32]),
     "dfjk_plan_destroy": (c_i32, [c_vp]),
     "dfjk_last_error": (ctypes.c_char_p, []),
 }

@@ -133,8 +133,6 @@ struct HTArgs {
     void *Xlo;                // second plane for the BF16 split
 };
 
-constexpr int kHTK = 32;
-constexpr int kHTCols = 256;
 
 __device__ __forceinline__ unsigned short f32_to_bf16_rne(float x)
 {
@@ -144,62 +142,129 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float x)
 }
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-template <int OUT>
+// Workgroup (mu, 128-row P tile, column pass of NIB*16 columns).  Wave w owns
+// rows p0 + 32w .. +31 as two 16-row MFMA fragments.  The k list of mu is
+// walked in chunks of 16: the gathered coefficient rows C[nu_k][cols] go
+// through double-buffered LDS, and the gathered tensor values B[row_k][P]
+// (the A operand, one double per lane, 16 contiguous P per k) are loaded one
+// chunk ahead with their row indices two chunks ahead, so load latency hides
+// under the MFMAs of the current chunk.  One barrier per chunk.
+template <int OUT, int NIB>
 __global__ __launch_bounds__(256) void k_halftrans(HTArgs g)
 {
-    __shared__ double Cs[kHTK][kHTCols + 1];
-    __shared__ int32_t rowS[kHTK];
+    constexpr int KC = 16;
+    constexpr int NCOL = NIB * 16;
+    constexpr int PAD = (16 - NCOL % 32 + 32) % 32;     // k rows of a fragment read land on opposite bank halves
+    constexpr int LDC = NCOL + PAD;
+    constexpr int NLOAD = (KC * NCOL / 2 + 255) / 256;  // double2 loads per thread per chunk
+    __shared__ double Cs[2][KC * LDC];
     const int mu = blockIdx.y;
-    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const int64_t p0 = (int64_t)blockIdx.x * 128;
+    const int ic0 = blockIdx.z * NCOL;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kb = g.hk_off[mu], ke = g.hk_off[mu + 1];
-    const int64_t prow = p0 + 16 * wave + (lane & 15);
+    const int64_t prow = p0 + 32 * wave + (lane & 15);
+    const int kl = lane >> 4;   // k within an MFMA step
 
-    for (int ic0 = 0; ic0 < g.ncol; ic0 += kHTCols) {
-        const int width = min(kHTCols, g.ncol - ic0);
-        const int nib = (width + 15) / 16;
-        f64x4 acc[16];
+    f64x4 acc[2][NIB];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
-        for (int kc = kb; kc < ke; kc += kHTK) {
-            for (int e = tid; e < kHTK * kHTCols; e += 256) {
-                const int kk = e / kHTCols, i = e % kHTCols;
-                double v = 0.0;
-                if (kc + kk < ke && i < width) v = g.C[(int64_t)g.hk_nu[kc + kk] * g.ncol + ic0 + i];
-                Cs[kk][i] = v;
-            }
-            if (tid < kHTK) rowS[tid] = (kc + tid < ke) ? g.hk_row[kc + tid] : -1;
-            __syncthreads();
-            double a[kHTK / 4];
+    for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int ks = 0; ks < kHTK / 4; ++ks) {
-                const int r = rowS[ks * 4 + (lane >> 4)];
-                a[ks] = (r >= 0) ? g.B[(int64_t)r * g.ld + prow] : 0.0;
-            }
+        for (int j = 0; j < NIB; ++j) acc[f][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    auto load_rows = [&](int kc, int (&r)[4]) {
 #pragma unroll
-            for (int ks = 0; ks < kHTK / 4; ++ks) {
-                const double *cs = &Cs[ks * 4 + (lane >> 4)][lane & 15];
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j < nib) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], cs[j * 16], acc[j], 0, 0, 0);
-            }
-            __syncthreads();
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = kc + ks * 4 + kl;
+            r[ks] = (k < ke) ? g.hk_row[k] : -1;
         }
+    };
+    auto load_a = [&](const int (&r)[4], double (&a)[4][2]) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            if (j >= nib) break;
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+                a[ks][f] = (r[ks] >= 0) ? g.B[(int64_t)r[ks] * g.ld + prow + 16 * f] : 0.0;
+    };
+    auto load_c = [&](int kc, double2 (&c)[NLOAD]) {
+#pragma unroll
+        for (int it = 0; it < NLOAD; ++it) {
+            const int e = tid + 256 * it;             // double2 index in the KC x NCOL chunk
+            const int kk = e / (NCOL / 2), cc = (e % (NCOL / 2)) * 2;
+            double2 v{0.0, 0.0};
+            if (e < KC * NCOL / 2 && kc + kk < ke) {
+                const double *src = g.C + (int64_t)g.hk_nu[kc + kk] * g.ncol + ic0 + cc;
+                if (ic0 + cc + 1 < g.ncol) v = double2{src[0], src[1]};
+                else if (ic0 + cc < g.ncol) v.x = src[0];
+            }
+            c[it] = v;
+        }
+    };
+    auto store_c = [&](int buf, const double2 (&c)[NLOAD]) {
+#pragma unroll
+        for (int it = 0; it < NLOAD; ++it) {
+            const int e = tid + 256 * it;
+            if (e < KC * NCOL / 2) {
+                const int kk = e / (NCOL / 2), cc = (e % (NCOL / 2)) * 2;
+                Cs[buf][kk * LDC + cc] = c[it].x;
+                Cs[buf][kk * LDC + cc + 1] = c[it].y;
+            }
+        }
+    };
+
+    int rows_next[4], rows_cur[4];
+    double a_cur[4][2], a_next[4][2];
+    double2 creg[NLOAD];
+    load_rows(kb, rows_cur);
+    load_a(rows_cur, a_cur);
+    load_rows(kb + KC, rows_next);
+    load_c(kb, creg);
+    int buf = 0;
+    for (int kc = kb; kc < ke; kc += KC) {
+        store_c(buf, creg);
+        __syncthreads();
+        const bool more = kc + KC < ke;
+        if (more) {
+            load_c(kc + KC, creg);
+            load_a(rows_next, a_next);
+            load_rows(kc + 2 * KC, rows_next);
+        }
+        const double *cs = Cs[buf] + kl * LDC + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int j = 0; j < NIB; ++j) {
+                const double b = cs[ks * 4 * LDC + j * 16];
+                acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[ks][0], b, acc[0][j], 0, 0, 0);
+                acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[ks][1], b, acc[1][j], 0, 0, 0);
+            }
+        if (more) {
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                a_cur[ks][0] = a_next[ks][0];
+                a_cur[ks][1] = a_next[ks][1];
+            }
+        }
+        buf ^= 1;
+    }
+
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int j = 0; j < NIB; ++j) {
             const int col = ic0 + j * 16 + (lane & 15);
             if (col >= g.ncol) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t P = p0 + 16 * wave + (lane >> 4) + 4 * r;
+                const int64_t P = p0 + 32 * wave + 16 * f + kl + 4 * r;
                 const int64_t o = ((int64_t)mu * g.ld + P) * g.ncol + col;
+                const double v64 = acc[f][j][r];
                 if (OUT == OUT_F64) {
-                    static_cast<double *>(g.X)[o] = acc[j][r];
+                    static_cast<double *>(g.X)[o] = v64;
                 } else if (OUT == OUT_F32) {
-                    static_cast<float *>(g.X)[o] = (float)acc[j][r];
+                    static_cast<float *>(g.X)[o] = (float)v64;
                 } else {
-                    const float v = (float)acc[j][r];
+                    const float v = (float)v64;
                     const unsigned short hi = f32_to_bf16_rne(v);
                     const unsigned short lo = f32_to_bf16_rne(v - bf16_to_f32(hi));
                     static_cast<unsigned short *>(g.X)[o] = hi;
@@ -207,7 +272,22 @@ __global__ __launch_bounds__(256) void k_halftrans(HTArgs g)
                 }
             }
         }
+}
+
+template <int OUT>
+static void launch_halftrans(const HTArgs &h, int64_t nao, hipStream_t s)
+{
+    const int nib_needed = (h.ncol + 15) / 16;
+    const int nib = nib_needed < 16 ? nib_needed : 16;
+    const int passes = (nib_needed + nib - 1) / nib;
+    dim3 grid((unsigned)(h.ld / 128), (unsigned)nao, (unsigned)passes);
+#define HT_CASE(N) \
+    case N: hipLaunchKernelGGL((k_halftrans<OUT, N>), grid, dim3(256), 0, s, h); break;
+    switch (nib) {
+        HT_CASE(1) HT_CASE(2) HT_CASE(3) HT_CASE(4) HT_CASE(5) HT_CASE(6) HT_CASE(7) HT_CASE(8)
+        HT_CASE(9) HT_CASE(10) HT_CASE(11) HT_CASE(12) HT_CASE(13) HT_CASE(14) HT_CASE(15) HT_CASE(16)
     }
+#undef HT_CASE
 }
 
 // Dense expansion for the D route: Bt[mu][P][nu] = B[f(mu,nu)][P] (0 elsewhere).
@@ -293,10 +373,13 @@ __global__ __launch_bounds__(256) void k_energies(const double *__restrict__ c, 
 
 // ---------------------------------------------------------------------------
 
-static int choose_ksplit(int ntiles, int64_t kdim)
+// Split-K count for the K contraction: the largest count whose workgroups
+// (two per CU for these kernels) fit in one round, so no nearly empty last
+// round idles the chip; at least 256 k values per split.
+static int choose_ksplit(int ntiles, int64_t kdim, int num_cus)
 {
-    // aim for >= 1024 workgroups; every split a multiple of 16 in k
-    int ns = (1024 + ntiles - 1) / ntiles;
+    const int slots = 2 * (num_cus > 0 ? num_cus : 256);
+    int ns = ntiles >= slots ? 1 : slots / ntiles;
     const int64_t maxs = kdim / 256;
     if (ns > maxs) ns = (int)(maxs > 0 ? maxs : 1);
     if (ns < 1) ns = 1;
@@ -316,7 +399,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.ntile = (int)((p.nao + kTileK - 1) / kTileK);
     L.kdim = p.naux_pad * L.ncol;
     const int ntiles = L.ntile * (L.ntile + 1) / 2;
-    L.nsplit_k = choose_ksplit(ntiles, L.kdim);
+    L.nsplit_k = choose_ksplit(ntiles, L.kdim, p.num_cus);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         off = align_up(off, 256);
@@ -341,8 +424,8 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
 
 void launch_syrk_mixed(const BuildLayout &L, const void *X, const void *Xlo, double *part, hipStream_t s);
 
-void launch_build(const Plan &p, const BuildLayout &L, const double *C, const double *Din, double *J,
-                  double *K, double *E, char *scratch, hipStream_t s)
+void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *Din, double *J, double *K,
+                  double *E, char *scratch, hipStream_t s)
 {
     const int64_t nao = p.nao, ld = p.naux_pad;
     double *D = reinterpret_cast<double *>(scratch + L.o_D);
@@ -354,15 +437,20 @@ void launch_build(const Plan &p, const BuildLayout &L, const double *C, const do
     double *Bt = L.o_Bfull ? reinterpret_cast<double *>(scratch + L.o_Bfull) : nullptr;
     double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
     double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
+    Profiler &pr = p.prof;
+    pr.stream = s;
 
     // 1. density
+    pr.mark(ST_DENSITY, true);
     if (!L.with_D) {
         dim3 grid((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16));
         hipLaunchKernelGGL(k_density, grid, dim3(256), 0, s, C, nao, (int32_t)L.ncol, D);
     } else {
         (void)hipMemcpyAsync(D, Din, (size_t)nao * nao * 8, hipMemcpyDeviceToDevice, s);
     }
+    pr.mark(ST_DENSITY, false);
     // 2-4. J
+    pr.mark(ST_J, true);
     hipLaunchKernelGGL(k_gather_d, dim3((unsigned)((p.nf_pad + 255) / 256)), dim3(256), 0, s, D, nao, p.d.f_mu,
                        p.d.f_nu, p.d.f_w, p.nf, p.nf_pad, dvec);
     hipLaunchKernelGGL(k_c_partial, dim3((unsigned)((ld + 255) / 256), L.nsplit_c), dim3(256), 0, s, p.d.B, ld,
@@ -373,25 +461,25 @@ void launch_build(const Plan &p, const BuildLayout &L, const double *C, const do
     if (p.nf > 0)
         hipLaunchKernelGGL(k_j_rows, dim3((unsigned)((p.nf + 3) / 4)), dim3(256), 0, s, p.d.B, ld, cvec, p.d.f_mu,
                            p.d.f_nu, p.d.f_w, p.nf, nao, J);
+    pr.mark(ST_J, false);
     // 5. half transform
+    pr.mark(ST_HALFTRANS, true);
     HTArgs h{p.d.B, ld, L.with_D ? Din : C, (int32_t)L.ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo};
-    dim3 hgrid((unsigned)(ld / 64), (unsigned)nao);
-    if (L.precision == DFJK_FP64) hipLaunchKernelGGL(k_halftrans<OUT_F64>, hgrid, dim3(256), 0, s, h);
-    else if (L.precision == DFJK_MIXED_FP32) hipLaunchKernelGGL(k_halftrans<OUT_F32>, hgrid, dim3(256), 0, s, h);
-    else hipLaunchKernelGGL(k_halftrans<OUT_BF16X2>, hgrid, dim3(256), 0, s, h);
+    if (L.precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, nao, s);
+    else if (L.precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, nao, s);
+    else launch_halftrans<OUT_BF16X2>(h, nao, s);
+    if (L.with_D)
+        hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((ld + 255) / 256), (unsigned)nao), dim3(256), 0, s, p.d.B,
+                           ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, Bt);
+    pr.mark(ST_HALFTRANS, false);
     // 6. K
+    pr.mark(ST_K, true);
     const int ntiles = L.ntile * (L.ntile + 1) / 2;
     const int64_t ksplit = align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
     if (L.precision == DFJK_FP64) {
         GemmArgs g{};
         g.A = static_cast<const double *>(X); g.lda = L.kdim;
-        if (L.with_D) {
-            hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((ld + 255) / 256), (unsigned)nao), dim3(256), 0, s,
-                               p.d.B, ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, Bt);
-            g.B = Bt;
-        } else {
-            g.B = static_cast<const double *>(X);
-        }
+        g.B = L.with_D ? Bt : static_cast<const double *>(X);
         g.ldb = L.kdim;
         g.M = g.N = nao;
         g.k_begin = 0; g.k_end = L.kdim; g.ksplit = ksplit;
@@ -400,11 +488,14 @@ void launch_build(const Plan &p, const BuildLayout &L, const double *C, const do
     } else {
         launch_syrk_mixed(L, X, Xlo, Kpart, s);
     }
+    pr.mark(ST_K, false);
+    // 7. split-K sum, mirror, energies
+    pr.mark(ST_KREDUCE, true);
     const double scale = L.with_D ? 1.0 : 2.0;
     hipLaunchKernelGGL(k_k_reduce, dim3(ntiles, kTileK / 16), dim3(256), 0, s, Kpart, L.nsplit_k, L.ntile, nao,
                        scale, D, K, Epart);
-    // 7. energies
     hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)ntiles * (kTileK / 16), E);
+    pr.mark(ST_KREDUCE, false);
 }
 
 }  // namespace dfjk

@@ -152,6 +152,20 @@ class Plan:
         return J, K, E
 
     # -- diagnostics -------------------------------------------------------
+    NSTAGES = 10
+
+    def profile(self, on=True):
+        """Record HIP events around every stage of later setups and builds."""
+        _check(N.lib().dfjk_profile(self._h, int(bool(on))))
+        return self
+
+    def profile_read(self):
+        """{stage name: (summed ms, launches)} since the last read; waits for the events."""
+        ms = np.zeros(self.NSTAGES)
+        cnt = np.zeros(self.NSTAGES, dtype=np.int32)
+        _check(N.lib().dfjk_profile_read(self._h, ms.ctypes.data_as(N.P_dbl), cnt.ctypes.data_as(N.P_i32)))
+        return {N.lib().dfjk_stage_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(self.NSTAGES)}
+
     def export(self, kind, stream=None):
         if kind in (EXPORT_INT3C, EXPORT_B):
             shape = (self.naux, self.nao, self.nao)
