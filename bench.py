@@ -65,7 +65,7 @@ def cpu_baseline(mol, Cs, target_s=20.0):
     import oracle
     t = {}
     nsh = len(mol.aux_l)
-    pick = np.arange(0, nsh, 44)
+    pick = np.arange(0, nsh, 22)
     t0 = time.perf_counter()
     slabs = [oracle.int3c(mol, int(c), int(c) + 1) for c in pick]
     t["int3c"] = (time.perf_counter() - t0) * nsh / len(pick)
@@ -78,13 +78,14 @@ def cpu_baseline(mol, Cs, target_s=20.0):
     nao, naux = mol.nao, mol.naux
     rng = np.random.default_rng(0)
     U = np.concatenate([s.reshape(s.shape[0], -1) for s in slabs])
-    cols = rng.choice(nao * nao, size=4096, replace=False)
-    Ufull = np.zeros((naux, 4096))
+    ncol = 16384
+    cols = rng.choice(nao * nao, size=ncol, replace=False)
+    Ufull = np.zeros((naux, ncol))
     Ufull[: U.shape[0]] = U[:, cols]
     t0 = time.perf_counter()
     oracle.forward_subst(L, Ufull)
-    t["whiten"] = (time.perf_counter() - t0) * (nao * nao) / 4096
-    Bslab = np.concatenate(slabs)[:32]
+    t["whiten"] = (time.perf_counter() - t0) * (nao * nao) / ncol
+    Bslab = np.concatenate(slabs)[:64]
     t0 = time.perf_counter()
     oracle.jk_from_B(Bslab, C=Cs[0])
     t["build"] = (time.perf_counter() - t0) * naux / Bslab.shape[0]
@@ -94,10 +95,10 @@ def cpu_baseline(mol, Cs, target_s=20.0):
         "unit": "builds/s",
         "cores": int(oracle.num_threads()),
         "kind": "oracle",
-        "sample": ("water32 job (setup + 10 builds) timed on a sample: int3c for every 44th aux shell "
-                   "(x%.1f), full metric and Cholesky, forward substitution of 4096 of %d pair columns, "
-                   "J/K of one build over 32 of %d aux functions; each part scaled to the full job"
-                   % (nsh / len(pick), nao * nao, naux)),
+        "sample": ("water32 job (setup + 10 builds) timed on a sample: int3c for every 22nd aux shell "
+                   "(x%.1f), full metric and Cholesky, forward substitution of %d of %d pair columns, "
+                   "J/K of one build over %d of %d aux functions; each part scaled to the full job"
+                   % (nsh / len(pick), ncol, nao * nao, Bslab.shape[0], naux)),
         "seconds_extrapolated": {k: round(v, 3) for k, v in t.items()},
         "job_seconds_extrapolated": round(total, 2),
     }
@@ -110,7 +111,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (scales HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "repeats": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the DF-J/K build would shard).", file=sys.stderr)

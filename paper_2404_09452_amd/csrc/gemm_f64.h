@@ -4,9 +4,11 @@
 //
 // A is row-major with k contiguous.  Bop(k, n) is Bm[n][k] (k contiguous,
 // "NT") or Bm[k][n] (n contiguous, "NN").  A TxT output tile is owned by a
-// 256-thread workgroup: four waves in a 2x2 grid, each wave holding
-// (T/2)x(T/2) of accumulators as 16x16 MFMA blocks.  The k loop walks chunks
-// of 16, staged through LDS with a register prefetch of the next chunk.
+// workgroup of WGM x WGN waves; each wave holds (T/WGM) x (T/WGN) of
+// accumulators as 16x16 MFMA blocks.  The k loop walks chunks of 16 staged
+// through double-buffered LDS (register prefetch of the next chunk, one
+// barrier per chunk); inside a chunk the MFMA fragments of the next k step
+// are read from LDS before the MFMAs of the current one are issued.
 //
 // MFMA f64 16x16x4 operand layout on gfx950 (checked on the device):
 //   lane l supplies A[l%16][l/16] and B[l/16][l%16];
@@ -59,37 +61,44 @@ __device__ __forceinline__ void tile_coords(const GemmArgs &g, int t, int &tm, i
     }
 }
 
-template <int T, bool NN>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g)
+// waves_per_eu 4: at most 128 VGPRs, so two 8-wave workgroups share a CU.
+template <int T, int WGM, int WGN, bool NN>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(4)))
+void k_gemm_f64(GemmArgs g)
 {
-    constexpr int KC = kGemmKC, LDS_K = KC + 1;      // padded k stride in LDS
-    constexpr int WT = T / 2, MB = WT / 16;          // per-wave tile, 16x16 blocks per side
-    constexpr int LOADS = T * KC / 2 / 256;          // double2 loads per thread per operand
+    constexpr int NT = 64 * WGM * WGN;                 // threads
+    constexpr int KC = kGemmKC, LDS_K = KC + 1;        // padded k stride in LDS
+    constexpr int WTM = T / WGM, WTN = T / WGN;        // per-wave tile
+    constexpr int MB = WTM / 16, NB = WTN / 16;        // 16x16 blocks per wave
+    constexpr int LOADS = T * KC / 2 / NT;             // double2 loads per thread per operand
+    static_assert(LOADS * NT * 2 == T * KC, "tile/threads mismatch");
     __shared__ double As[2][T * LDS_K];
     __shared__ double Bs[2][T * LDS_K];
 
+    const int ntiles_all = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntn;
+    const int tile = blockIdx.x, split = blockIdx.y;
     int tm, tn;
-    tile_coords(g, blockIdx.x, tm, tn);
+    tile_coords(g, tile, tm, tn);
     const int64_t m0 = (int64_t)tm * T, n0 = (int64_t)tn * T;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
 
-    int64_t kb = g.k_begin + (int64_t)blockIdx.y * g.ksplit;
+    int64_t kb = g.k_begin + (int64_t)split * g.ksplit;
     int64_t ke = kb + g.ksplit;
     if (ke > g.k_end) ke = g.k_end;
     if (g.tri_k && ke > n0 + T) ke = n0 + T;
 
-    f64x4 acc[MB][MB];
+    f64x4 acc[MB][NB];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < MB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < NB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
     double2 ra[LOADS], rb[LOADS];
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int it = 0; it < LOADS; ++it) {
-            const int idx = tid + 256 * it;
+            const int idx = tid + NT * it;
             {   // A: row idx / (KC/2), k pair idx % (KC/2)
                 const int row = idx / (KC / 2), kp = (idx % (KC / 2)) * 2;
                 const int64_t m = m0 + row;
@@ -113,7 +122,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g)
     auto store = [&](int buf) {
 #pragma unroll
         for (int it = 0; it < LOADS; ++it) {
-            const int idx = tid + 256 * it;
+            const int idx = tid + NT * it;
             const int row = idx / (KC / 2), kp = (idx % (KC / 2)) * 2;
             As[buf][row * LDS_K + kp] = ra[it].x;
             As[buf][row * LDS_K + kp + 1] = ra[it].y;
@@ -136,21 +145,27 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g)
         for (int64_t k0 = kb; k0 < ke; k0 += KC) {
             const bool more = k0 + KC < ke;
             if (more) load(k0 + KC);
-            const double *as = As[buf] + (wm * WT + (lane & 15)) * LDS_K + (lane >> 4);
-            const double *bs = Bs[buf] + (wn * WT + (lane & 15)) * LDS_K + (lane >> 4);
+            const double *as = As[buf] + (wm * WTM + (lane & 15)) * LDS_K + (lane >> 4);
+            const double *bs = Bs[buf] + (wn * WTN + (lane & 15)) * LDS_K + (lane >> 4);
+            double a[2][MB], b[2][NB];
+#pragma unroll
+            for (int i = 0; i < MB; ++i) a[0][i] = as[i * 16 * LDS_K];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) b[0][j] = bs[j * 16 * LDS_K];
 #pragma unroll
             for (int ks = 0; ks < KC / 4; ++ks) {
-                double a[MB], b[MB];
+                const int cur = ks & 1, nxt = cur ^ 1;
+                if (ks + 1 < KC / 4) {
 #pragma unroll
-                for (int i = 0; i < MB; ++i) {
-                    a[i] = as[i * 16 * LDS_K + ks * 4];
-                    b[i] = bs[i * 16 * LDS_K + ks * 4];
+                    for (int i = 0; i < MB; ++i) a[nxt][i] = as[i * 16 * LDS_K + (ks + 1) * 4];
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) b[nxt][j] = bs[j * 16 * LDS_K + (ks + 1) * 4];
                 }
 #pragma unroll
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
-                    for (int j = 0; j < MB; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < NB; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][i], b[cur][j], acc[i][j], 0, 0, 0);
             }
             if (more) {
                 store(buf ^ 1);
@@ -161,16 +176,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g)
     }
 
     if (g.partial) {
-        const int ntiles = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntn;
-        double *dst = g.partial + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * (int64_t)(T * T);
+        double *dst = g.partial + ((int64_t)split * ntiles_all + tile) * (int64_t)(T * T);
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
+            for (int j = 0; j < NB; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = wm * WT + i * 16 + (lane >> 4) + 4 * r;
-                    const int col = wn * WT + j * 16 + (lane & 15);
+                    const int row = wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+                    const int col = wn * WTN + j * 16 + (lane & 15);
                     dst[row * T + col] = acc[i][j][r];
                 }
         return;
@@ -178,11 +192,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g)
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < MB; ++j)
+        for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t m = m0 + wm * WT + i * 16 + (lane >> 4) + 4 * r;
-                const int64_t n = n0 + wn * WT + j * 16 + (lane & 15);
+                const int64_t m = m0 + wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+                const int64_t n = n0 + wn * WTN + j * 16 + (lane & 15);
                 if (m < g.M && n < g.N) {
                     double *c = g.C + m * g.ldc + n;
                     const double v = g.alpha * acc[i][j][r];
@@ -191,6 +205,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g)
             }
 }
 
+// T = 128 uses eight waves (4 x 2, 32x64 per wave) to keep four waves per
+// SIMD resident; T = 64 uses four waves (2 x 2).
 template <int T, bool NN>
 inline void gemm_f64(GemmArgs g, int nsplit, hipStream_t s)
 {
@@ -198,7 +214,10 @@ inline void gemm_f64(GemmArgs g, int nsplit, hipStream_t s)
     g.ntn = (int)((g.N + T - 1) / T);
     const int ntiles = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntn;
     if (ntiles <= 0 || nsplit <= 0) return;
-    hipLaunchKernelGGL((k_gemm_f64<T, NN>), dim3(ntiles, nsplit), dim3(256), 0, s, g);
+    if (T == 128)
+        hipLaunchKernelGGL((k_gemm_f64<128, 4, 2, NN>), dim3(ntiles, nsplit), dim3(512), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm_f64<64, 2, 2, NN>), dim3(ntiles, nsplit), dim3(256), 0, s, g);
 }
 
 }  // namespace dfjk

@@ -7,7 +7,7 @@
 //   4. J[mu_f][nu_f] = sum_P B[f][P] c_P     one wave per row f
 //   5. X[mu][P][i] = sum_nu B[f(mu,nu)][P] C[nu][i]
 //                                            gathered GEMM on FP64 MFMA, one
-//                                            workgroup per (mu, 64 aux rows)
+//                                            workgroup per (mu, 128 aux rows)
 //   6. K = 2 X X^T (C route) or X B~^T (D route) on FP64 MFMA, lower tiles,
 //      split-K into partial tiles summed in a fixed order
 //   7. E_J = 1/2 sum_P c_P^2 (= 1/2 Tr DJ), E_K = -1/4 sum D K
@@ -115,11 +115,9 @@ __global__ __launch_bounds__(256) void k_j_rows(const double *__restrict__ B, in
 }
 
 // ---------------------------------------------------------------------------
-// Half transform.  Workgroup (mu, 64-row P tile); wave w owns rows
-// p0 + 16w .. +15 and every column block of 16 (up to 16 blocks per pass).
-// The gathered coefficient rows C[nu_k][:] for 32 k at a time sit in LDS.
-// MFMA: A = B[row_k][P] (lane: P = l%16, k = l/16), B = Cs[k][i]
-// (lane: k = l/16, i = l%16); accumulator r holds row P = l/16 + 4r.
+// Half transform.  MFMA operands: A = B[row_k][P] (lane: P = l%16,
+// k = l/16), B = Cs[k][i] (lane: k = l/16, i = l%16); accumulator r holds
+// row P = l/16 + 4r.
 
 enum { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2 };
 

@@ -1,0 +1,120 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/dfjk.h declares, and rejects bad input before any
+device work with the documented status codes and messages."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dfjk.h")
+
+N = pytest.importorskip("paper_2404_09452_amd._native")
+if not os.path.exists(N.LIB_PATH):
+    pytest.skip("libdfjk.so not built", allow_module_level=True)
+from paper_2404_09452_amd import dfjk as G  # noqa: E402
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfjk_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(N.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N.SIGNATURES), "binding signatures out of step with the header"
+
+
+def _water():
+    z, x = W.water_monomer()
+    return W.make_molecule(z, x)
+
+
+def test_plan_create_and_info_on_host():
+    plan = G.Plan.from_molecule(_water())
+    info = plan.info()
+    assert info["nao"] == 30 and info["naux"] == 87
+    assert info["naux_pad"] % 128 == 0 and info["naux_pad"] >= 87
+    assert info["nshell_pairs"] == 16 * 17 // 2
+    assert info["stage"] == 0
+    order = plan.aux_order()
+    assert sorted(order.tolist()) == list(range(87))
+    # internal order groups aux functions by angular momentum
+    l_of_fn = np.repeat(_water().aux_l, 2 * _water().aux_l + 1)
+    assert np.all(np.diff(l_of_fn[order]) >= 0)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(ao_l=[3]), "UNSUPPORTED"),
+    (dict(aux_l=[4]), "UNSUPPORTED"),
+    (dict(ao_l=[-1]), "INVALID"),
+    (dict(ao_exp=[0.0]), "INVALID"),
+    (dict(ao_exp=[float("nan")]), "INVALID"),
+    (dict(aux_exp=[-2.0]), "INVALID"),
+    (dict(ao_atom=[5]), "INVALID"),
+    (dict(coords=[[0.0, float("inf"), 0.0]]), "INVALID"),
+    (dict(schwarz_thresh=-1.0), "INVALID"),
+])
+def test_plan_create_rejects_bad_input(bad, code):
+    args = dict(coords=[[0.0, 0.0, 0.0]], ao_atom=[0], ao_l=[0], ao_exp=[1.0],
+                aux_atom=[0], aux_l=[0], aux_exp=[2.0], schwarz_thresh=1e-14)
+    args.update(bad)
+    with pytest.raises(G.DFJKError) as ei:
+        G.Plan(**args)
+    assert ei.value.status == code
+    assert ei.value.message
+
+
+def test_raw_abi_null_arguments():
+    lib = N.lib()
+    out = ctypes.c_void_p()
+    assert lib.dfjk_plan_create(1, None, None, None, None, ctypes.byref(out)) == 1
+    assert b"NULL" in lib.dfjk_last_error() or b"coords" in lib.dfjk_last_error()
+    assert lib.dfjk_options_default(None) == 1
+    assert lib.dfjk_plan_info(None, None) == 1
+    n = ctypes.c_size_t()
+    assert lib.dfjk_screen_bytes(None, ctypes.byref(n)) == 1
+
+
+def test_call_order_is_enforced_without_device():
+    plan = G.Plan.from_molecule(_water())
+    lib = N.lib()
+    n = ctypes.c_size_t()
+    assert lib.dfjk_setup_bytes(plan._h, ctypes.byref(n)) == 7            # STATE: not screened
+    assert lib.dfjk_build(plan._h, ctypes.c_void_p(8), 5, None, 0, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 20, None) == 7
+    assert b"setup" in lib.dfjk_last_error()
+    ms = np.zeros(10)
+    cnt = np.zeros(10, dtype=np.int32)
+    assert lib.dfjk_profile(plan._h, 1) == 0
+    assert lib.dfjk_profile_read(plan._h, ms.ctypes.data_as(N.P_dbl), cnt.ctypes.data_as(N.P_i32)) == 0
+    assert cnt.sum() == 0
+    assert lib.dfjk_stage_name(8) == b"build.K"
+
+
+def test_boys_argument_checks_without_device():
+    lib = N.lib()
+    assert lib.dfjk_boys(17, 4, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == 1
+    assert lib.dfjk_boys(3, -1, None, None, None) == 1
+
+
+def test_no_device_is_reported(monkeypatch):
+    """On a machine without a GPU the device calls say so (skipped on a GPU machine)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    lib = N.lib()
+    T = np.zeros(4)
+    F = np.zeros(4)
+    rc = lib.dfjk_boys(0, 4, ctypes.c_void_p(T.ctypes.data), ctypes.c_void_p(F.ctypes.data), None)
+    assert rc == 6
+    assert b"GPU" in lib.dfjk_last_error()
