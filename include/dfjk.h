@@ -142,6 +142,21 @@ int dfjk_build(dfjk_plan *plan, const double *d_C, int32_t nocc, const double *d
                int32_t precision, double *d_J, double *d_K, double *d_E,
                void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* Incremental build for later SCF iterations, after the proposal of single
+ * precision in later iterations (paper, "Limitations and Future Development:
+ * Mixed Precision").  With D = 2 C C^T and D0 = 2 C0 C0^T,
+ *   D - D0 = U W^T + W U^T,  U = C + C0,  W = C - C0,
+ *   K(D) = K0 + G + G^T,     G = X_U X_W^T,
+ * where K0 = K(D0) comes from an earlier FP64 dfjk_build with C0 on this plan
+ * and X_U, X_W are the half-transforms of U and W.  G is formed in
+ * `precision` (its error scales with |C - C0|); J and both energies are FP64.
+ * d_C, d_C0: nao x nocc; d_K0: nao x nao (read only, must not alias d_K).
+ * d_scratch must hold dfjk_build_delta_bytes(plan, nocc, precision). */
+int dfjk_build_delta_bytes(const dfjk_plan *plan, int32_t nocc, int32_t precision, size_t *bytes);
+int dfjk_build_delta(dfjk_plan *plan, const double *d_C, const double *d_C0, int32_t nocc,
+                     const double *d_K0, int32_t precision, double *d_J, double *d_K, double *d_E,
+                     void *d_scratch, size_t scratch_bytes, void *stream);
+
 /* Diagnostics for tests (valid after setup).  Dense copies of intermediate
  * quantities in the caller's function order:
  *   DFJK_EXPORT_INT3C   (naux x nao x nao) unwhitened (mu nu|P), screened

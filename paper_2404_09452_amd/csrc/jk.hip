@@ -303,6 +303,63 @@ __global__ __launch_bounds__(256) void k_expand_B(const double *__restrict__ B, 
     for (int k = hk_off[mu]; k < hk_off[mu + 1]; ++k) dst[hk_nu[k]] = B[(int64_t)hk_row[k] * ld + P];
 }
 
+// [U | W] = [C + C0 | C - C0] (nao x 2 nocc): 2(C C^T - C0 C0^T) = U W^T + W U^T.
+__global__ void k_uw(const double *__restrict__ C, const double *__restrict__ C0, int64_t nao, int32_t nocc,
+                     double *__restrict__ U, double *__restrict__ W)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nao * nocc) return;
+    const double c = C[e], c0 = C0[e];
+    U[e] = c + c0;
+    W[e] = c - c0;
+}
+
+// Incremental K: K = K0 + G + G^T with G = X_U X_W^T held as split-K partial
+// tiles over every 128x128 tile (rectangular order t = tm + tn * ntm).  One
+// block per lower tile and 16-row chunk sums both G[m][n] and G[n][m] in a
+// fixed order, writes K symmetric, and sums D o K for E_K.
+__global__ __launch_bounds__(256) void k_k_reduce_delta(const double *__restrict__ part, int nsplit, int ntm,
+                                                        int64_t nao, const double *__restrict__ K0,
+                                                        const double *__restrict__ D, double *__restrict__ K,
+                                                        double *__restrict__ Epart)
+{
+    __shared__ double red[256];
+    const int t = blockIdx.x;
+    int tm = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (tm * (tm + 1) / 2 > t) --tm;
+    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+    const int tn = t - tm * (tm + 1) / 2;
+    const int64_t tile_mn = tm + (int64_t)tn * ntm, tile_nm = tn + (int64_t)tm * ntm;
+    const int64_t nt = (int64_t)ntm * ntm, TT = (int64_t)kTileK * kTileK;
+    const int chunk = blockIdx.y;
+    double e = 0.0;
+    for (int q = threadIdx.x; q < 16 * kTileK; q += 256) {
+        const int row = chunk * 16 + q / kTileK, col = q % kTileK;
+        const int64_t m = (int64_t)tm * kTileK + row, n = (int64_t)tn * kTileK + col;
+        if (m >= nao || n >= nao || n > m) continue;
+        double g1 = 0.0, g2 = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) {
+            g1 += part[(sp * nt + tile_mn) * TT + row * kTileK + col];
+            g2 += part[(sp * nt + tile_nm) * TT + col * kTileK + row];
+        }
+        const double v = K0[m * nao + n] + (g1 + g2);
+        K[m * nao + n] = v;
+        double w = 1.0;
+        if (m != n) {
+            K[n * nao + m] = v;
+            w = 2.0;
+        }
+        e += w * D[m * nao + n] * v;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) Epart[(int64_t)t * gridDim.y + chunk] = red[0];
+}
+
 // ---------------------------------------------------------------------------
 // Split-K reduction of the K tiles: K[m][n] = scale * sum_s partial[s][t][..]
 // in a fixed order, mirrored for off-diagonal tiles, plus per-block partial
@@ -374,6 +431,8 @@ __global__ __launch_bounds__(256) void k_energies(const double *__restrict__ c, 
 // Split-K count for the K contraction: the largest count whose workgroups
 // (two per CU for these kernels) fit in one round, so no nearly empty last
 // round idles the chip; at least 256 k values per split.
+int mixed_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus);
+
 static int choose_ksplit(int ntiles, int64_t kdim, int num_cus)
 {
     const int slots = 2 * (num_cus > 0 ? num_cus : 256);
@@ -384,7 +443,7 @@ static int choose_ksplit(int ntiles, int64_t kdim, int num_cus)
     return ns;
 }
 
-BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D)
+BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta)
 {
     BuildLayout L{};
     L.nao = p.nao;
@@ -396,8 +455,10 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.nsplit_c = (int)((p.nf_pad + kCSplitRows - 1) / kCSplitRows);
     L.ntile = (int)((p.nao + kTileK - 1) / kTileK);
     L.kdim = p.naux_pad * L.ncol;
-    const int ntiles = L.ntile * (L.ntile + 1) / 2;
-    L.nsplit_k = choose_ksplit(ntiles, L.kdim, p.num_cus);
+    L.delta = delta;
+    const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
+    L.nsplit_k = (precision == DFJK_FP64) ? choose_ksplit(ntiles, L.kdim, p.num_cus)
+                                          : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         off = align_up(off, 256);
@@ -414,21 +475,54 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.o_X = take(nx * esz);
     L.o_Xlo = precision == DFJK_MIXED_BF16X3 ? take(nx * 2) : 0;
     L.o_Bfull = with_D ? take(nx * 8) : 0;
+    if (delta) {
+        L.o_X2 = take(nx * esz);
+        L.o_X2lo = precision == DFJK_MIXED_BF16X3 ? take(nx * 2) : 0;
+        L.o_U = take((size_t)p.nao * nocc * 8);
+        L.o_W = take((size_t)p.nao * nocc * 8);
+    }
     L.o_Kpart = take((size_t)L.nsplit_k * ntiles * kTileK * kTileK * 8);
-    L.o_Epart = take((size_t)ntiles * (kTileK / 16) * 8);
+    L.o_Epart = take((size_t)L.ntile * (L.ntile + 1) / 2 * (kTileK / 16) * 8);
     L.bytes = align_up(off, 256);
     return L;
 }
 
-void launch_syrk_mixed(const BuildLayout &L, const void *X, const void *Xlo, double *part, hipStream_t s);
+void launch_gemm_mixed(int precision, bool lower, const void *A, const void *Alo, const void *B, const void *Blo,
+                       int64_t nao, int64_t kdim, int nsplit, double *part, hipStream_t s);
+
+// J from the resident B and the density in scratch (steps 2-4).
+static void launch_j(Plan &p, const BuildLayout &L, const double *D, double *J, char *scratch, hipStream_t s)
+{
+    const int64_t nao = p.nao, ld = p.naux_pad;
+    double *dvec = reinterpret_cast<double *>(scratch + L.o_d);
+    double *cpart = reinterpret_cast<double *>(scratch + L.o_cpart);
+    double *cvec = reinterpret_cast<double *>(scratch + L.o_c);
+    hipLaunchKernelGGL(k_gather_d, dim3((unsigned)((p.nf_pad + 255) / 256)), dim3(256), 0, s, D, nao, p.d.f_mu,
+                       p.d.f_nu, p.d.f_w, p.nf, p.nf_pad, dvec);
+    hipLaunchKernelGGL(k_c_partial, dim3((unsigned)((ld + 255) / 256), L.nsplit_c), dim3(256), 0, s, p.d.B, ld,
+                       dvec, p.nf_pad, cpart);
+    hipLaunchKernelGGL(k_c_reduce, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, s, cpart, L.nsplit_c, ld,
+                       cvec);
+    fill(J, nao * nao, 0.0, s);
+    if (p.nf > 0)
+        hipLaunchKernelGGL(k_j_rows, dim3((unsigned)((p.nf + 3) / 4)), dim3(256), 0, s, p.d.B, ld, cvec, p.d.f_mu,
+                           p.d.f_nu, p.d.f_w, p.nf, nao, J);
+}
+
+static void launch_ht(const Plan &p, int precision, const double *C, int32_t ncol, void *X, void *Xlo,
+                      hipStream_t s)
+{
+    HTArgs h{p.d.B, p.naux_pad, C, ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo};
+    if (precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, p.nao, s);
+    else if (precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, p.nao, s);
+    else launch_halftrans<OUT_BF16X2>(h, p.nao, s);
+}
 
 void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *Din, double *J, double *K,
                   double *E, char *scratch, hipStream_t s)
 {
     const int64_t nao = p.nao, ld = p.naux_pad;
     double *D = reinterpret_cast<double *>(scratch + L.o_D);
-    double *dvec = reinterpret_cast<double *>(scratch + L.o_d);
-    double *cpart = reinterpret_cast<double *>(scratch + L.o_cpart);
     double *cvec = reinterpret_cast<double *>(scratch + L.o_c);
     void *X = scratch + L.o_X;
     void *Xlo = L.o_Xlo ? scratch + L.o_Xlo : nullptr;
@@ -446,53 +540,56 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
     } else {
         (void)hipMemcpyAsync(D, Din, (size_t)nao * nao * 8, hipMemcpyDeviceToDevice, s);
     }
+    if (L.delta)
+        hipLaunchKernelGGL(k_uw, dim3((unsigned)((nao * L.ncol + 255) / 256)), dim3(256), 0, s, C, L.C0, nao,
+                           (int32_t)L.ncol, reinterpret_cast<double *>(scratch + L.o_U),
+                           reinterpret_cast<double *>(scratch + L.o_W));
     pr.mark(ST_DENSITY, false);
-    // 2-4. J
+    // 2-4. J (always FP64)
     pr.mark(ST_J, true);
-    hipLaunchKernelGGL(k_gather_d, dim3((unsigned)((p.nf_pad + 255) / 256)), dim3(256), 0, s, D, nao, p.d.f_mu,
-                       p.d.f_nu, p.d.f_w, p.nf, p.nf_pad, dvec);
-    hipLaunchKernelGGL(k_c_partial, dim3((unsigned)((ld + 255) / 256), L.nsplit_c), dim3(256), 0, s, p.d.B, ld,
-                       dvec, p.nf_pad, cpart);
-    hipLaunchKernelGGL(k_c_reduce, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, s, cpart, L.nsplit_c, ld,
-                       cvec);
-    fill(J, nao * nao, 0.0, s);
-    if (p.nf > 0)
-        hipLaunchKernelGGL(k_j_rows, dim3((unsigned)((p.nf + 3) / 4)), dim3(256), 0, s, p.d.B, ld, cvec, p.d.f_mu,
-                           p.d.f_nu, p.d.f_w, p.nf, nao, J);
+    launch_j(p, L, D, J, scratch, s);
     pr.mark(ST_J, false);
-    // 5. half transform
+    // 5. half transform(s)
     pr.mark(ST_HALFTRANS, true);
-    HTArgs h{p.d.B, ld, L.with_D ? Din : C, (int32_t)L.ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo};
-    if (L.precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, nao, s);
-    else if (L.precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, nao, s);
-    else launch_halftrans<OUT_BF16X2>(h, nao, s);
-    if (L.with_D)
-        hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((ld + 255) / 256), (unsigned)nao), dim3(256), 0, s, p.d.B,
-                           ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, Bt);
+    if (!L.delta) {
+        launch_ht(p, L.precision, L.with_D ? Din : C, (int32_t)L.ncol, X, Xlo, s);
+        if (L.with_D)
+            hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((ld + 255) / 256), (unsigned)nao), dim3(256), 0, s,
+                               p.d.B, ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, Bt);
+    } else {
+        launch_ht(p, L.precision, reinterpret_cast<double *>(scratch + L.o_U), (int32_t)L.ncol, X, Xlo, s);
+        launch_ht(p, L.precision, reinterpret_cast<double *>(scratch + L.o_W), (int32_t)L.ncol,
+                  scratch + L.o_X2, L.o_X2lo ? scratch + L.o_X2lo : nullptr, s);
+    }
     pr.mark(ST_HALFTRANS, false);
-    // 6. K
+    // 6. K (lower tiles of 2 X X^T or X Bt^T; every tile of X_U X_W^T for the increment)
     pr.mark(ST_K, true);
-    const int ntiles = L.ntile * (L.ntile + 1) / 2;
-    const int64_t ksplit = align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
+    const bool lower = !L.delta;
+    const void *Bop = L.delta ? (const void *)(scratch + L.o_X2) : (L.with_D ? (const void *)Bt : (const void *)X);
+    const void *Bop_lo = L.delta ? (L.o_X2lo ? (const void *)(scratch + L.o_X2lo) : nullptr) : Xlo;
     if (L.precision == DFJK_FP64) {
         GemmArgs g{};
         g.A = static_cast<const double *>(X); g.lda = L.kdim;
-        g.B = L.with_D ? Bt : static_cast<const double *>(X);
-        g.ldb = L.kdim;
+        g.B = static_cast<const double *>(Bop); g.ldb = L.kdim;
         g.M = g.N = nao;
-        g.k_begin = 0; g.k_end = L.kdim; g.ksplit = ksplit;
-        g.alpha = 1.0; g.lower = 1; g.partial = Kpart;
+        g.k_begin = 0; g.k_end = L.kdim;
+        g.ksplit = align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
+        g.alpha = 1.0; g.lower = lower ? 1 : 0; g.partial = Kpart;
         gemm_f64<kTileK, false>(g, L.nsplit_k, s);
     } else {
-        launch_syrk_mixed(L, X, Xlo, Kpart, s);
+        launch_gemm_mixed(L.precision, lower, X, Xlo, Bop, Bop_lo, nao, L.kdim, L.nsplit_k, Kpart, s);
     }
     pr.mark(ST_K, false);
     // 7. split-K sum, mirror, energies
     pr.mark(ST_KREDUCE, true);
-    const double scale = L.with_D ? 1.0 : 2.0;
-    hipLaunchKernelGGL(k_k_reduce, dim3(ntiles, kTileK / 16), dim3(256), 0, s, Kpart, L.nsplit_k, L.ntile, nao,
-                       scale, D, K, Epart);
-    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)ntiles * (kTileK / 16), E);
+    const int nlower = L.ntile * (L.ntile + 1) / 2;
+    if (L.delta)
+        hipLaunchKernelGGL(k_k_reduce_delta, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, L.nsplit_k,
+                           L.ntile, nao, L.K0, D, K, Epart);
+    else
+        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, L.nsplit_k, L.ntile, nao,
+                           L.with_D ? 1.0 : 2.0, D, K, Epart);
+    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (kTileK / 16), E);
     pr.mark(ST_KREDUCE, false);
 }
 

@@ -1,18 +1,22 @@
-// Mixed-precision K = X X^T on gfx950 matrix cores (lower output tiles,
-// split-K into FP64 partial tiles like the FP64 path).
+// Mixed-precision products for K on gfx950 matrix cores:
+//   syrk mode:    P = A A^T on the lower 128x128 tiles      (direct mixed K)
+//   general mode: P = A B^T on every 128x128 tile          (incremental K)
+// with split-K into FP64 partial tiles summed elsewhere in a fixed order.
 //
-//  FP32:    X stored FP32, v_mfma_f32_16x16x4f32.
-//  BF16x3:  X = hi + lo with hi, lo BF16 (hi = rn(x), lo = rn(x - hi));
-//           X X^T ~ hi hi^T + hi lo^T + lo hi^T on v_mfma_f32_16x16x32_bf16
-//           (the lo lo^T term, ~2^-16 relative, is dropped).
-// In both, products accumulate in FP32 over at most kChunk k values and are
-// then added into FP64 accumulators, so the FP32 rounding error does not
-// grow with the full contraction length (naux * nocc).
+//  FP32:    operands stored FP32, v_mfma_f32_16x16x4f32.
+//  BF16x3:  every operand x stored as hi + lo, both BF16 (hi = rn(x),
+//           lo = rn(x - hi)); a b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on
+//           v_mfma_f32_16x16x32_bf16 (the lo lo term, ~2^-16 relative, is
+//           dropped).
+// Products accumulate in FP32 over at most kChunk k values and are then
+// added into FP64 accumulators, so FP32 rounding does not grow with the full
+// contraction length.  The k loop is pipelined like the FP64 tile GEMM: the
+// next chunk is prefetched into registers while the current one is consumed
+// from double-buffered LDS, one barrier per chunk.
 //
-// f32 MFMA operand layouts (checked on the device):
-//   16x16x4 f32:  lane l supplies A[l%16][l/16], B[l/16][l%16];
-//   16x16x32 bf16: lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and
-//                  B[8(l/16) .. +7][l%16];
+// f32-accumulating MFMA layouts (checked on the device):
+//   16x16x4 f32:   lane l supplies A[l%16][l/16], B[l/16][l%16];
+//   16x16x32 bf16: lane l supplies A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16];
 //   both: accumulator r of lane l is D[4(l/16) + r][l%16].
 #include "dfjk_internal.h"
 
@@ -22,37 +26,60 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4m __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int T = 128;          // output tile
+constexpr int T = 128;          // output tile (four waves, 64x64 each)
 constexpr int kChunk = 512;     // k values per FP32 accumulation chunk
 
-__device__ __forceinline__ void lower_tile(int t, int &tm, int &tn)
+__device__ __forceinline__ void mixed_tile(int t, bool lower, int ntm, int &tm, int &tn)
 {
-    int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while (r * (r + 1) / 2 > t) --r;
-    while ((r + 1) * (r + 2) / 2 <= t) ++r;
-    tm = r;
-    tn = t - r * (r + 1) / 2;
+    if (lower) {
+        int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while (r * (r + 1) / 2 > t) --r;
+        while ((r + 1) * (r + 2) / 2 <= t) ++r;
+        tm = r;
+        tn = t - r * (r + 1) / 2;
+    } else {
+        tm = t % ntm;
+        tn = t / ntm;
+    }
 }
 
-struct SyrkArgs {
-    const void *X, *Xlo;
-    int64_t ld;        // = kdim
-    int64_t M;         // nao
+struct MixedArgs {
+    const void *A, *Alo, *B, *Blo;   // [M][ld] planes (lo planes for BF16x3 only)
+    int64_t ld;                      // = kdim
+    int64_t M;                       // rows of A and of B (nao)
     int64_t kdim, ksplit;
     int ntm;
-    double *partial;
+    int lower;                       // 1: syrk mode (B = A, tiles tn <= tm)
+    double *partial;                 // [split][tile][T][T]
 };
 
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_syrk_f32(SyrkArgs g)
+template <int PREC>
+struct MixStage;   // operand chunk staging per precision
+
+// FP32: chunk of KC = 32 k; A and B tiles 128 x 32 floats each.
+template <>
+struct MixStage<DFJK_MIXED_FP32> {
+    static constexpr int KC = 32, LDK = KC + 4;
+    static constexpr int SMEM = 2 * 2 * T * LDK;     // floats: [buf][A/B][T*LDK]
+};
+// BF16x3: chunk of KC = 32 k; four planes (A hi/lo, B hi/lo) of 128 x 32 bf16.
+template <>
+struct MixStage<DFJK_MIXED_BF16X3> {
+    static constexpr int KC = 32, LDK = KC + 8;
+    static constexpr int SMEM = 2 * 4 * T * LDK;     // bf16: [buf][plane][T*LDK]
+};
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_gemm_mixed(MixedArgs g)
 {
-    constexpr int KC = 32, LDK = KC + 4;
-    __shared__ float As[T * LDK], Bs[T * LDK];
+    constexpr int KC = MixStage<PREC>::KC, LDK = MixStage<PREC>::LDK;
+    using Elem = typename std::conditional<PREC == DFJK_MIXED_FP32, float, unsigned short>::type;
+    __shared__ __attribute__((aligned(16))) Elem sm[MixStage<PREC>::SMEM];
+
     int tm, tn;
-    lower_tile(blockIdx.x, tm, tn);
+    mixed_tile(blockIdx.x, g.lower, g.ntm, tm, tn);
     const int64_t m0 = (int64_t)tm * T, n0 = (int64_t)tn * T;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-    const float *X = static_cast<const float *>(g.X);
     const int64_t kb = (int64_t)blockIdx.y * g.ksplit;
     const int64_t ke = min(kb + g.ksplit, g.kdim);
 
@@ -65,47 +92,116 @@ __global__ __launch_bounds__(256) void k_syrk_f32(SyrkArgs g)
             acc[i][j] = f64x4m{0.0, 0.0, 0.0, 0.0};
             a32[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-    int since = 0;
-    for (int64_t k0 = kb; k0 < ke; k0 += KC) {
+
+    // Each thread moves 16-byte pieces: row = idx / (KC*esz/16), column piece idx % (...).
+    constexpr int PIECES = KC * (int)sizeof(Elem) / 16;    // 16-byte pieces per row
+    constexpr int NP = PREC == DFJK_MIXED_FP32 ? 2 : 4;   // planes
+    constexpr int LOADS = T * PIECES / 256;                // pieces per thread per plane
+    uint4 reg[NP][LOADS];
+    const Elem *src[NP];
+    src[0] = static_cast<const Elem *>(g.A);
+    src[1] = static_cast<const Elem *>(g.lower ? g.A : g.B);
+    if (NP == 4) {
+        src[2] = static_cast<const Elem *>(g.Alo);
+        src[3] = static_cast<const Elem *>(g.lower ? g.Alo : g.Blo);
+    }
+    auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {           // 128 rows x 32 k = 1024 float4 per operand
-            const int idx = tid + 256 * it, row = idx >> 3, kq = (idx & 7) * 4;
-            const int64_t m = m0 + row, n = n0 + row;
-            float4 va = (m < g.M) ? *reinterpret_cast<const float4 *>(X + m * g.ld + k0 + kq) : float4{0, 0, 0, 0};
-            float4 vb = (n < g.M) ? *reinterpret_cast<const float4 *>(X + n * g.ld + k0 + kq) : float4{0, 0, 0, 0};
-            *reinterpret_cast<float4 *>(&As[row * LDK + kq]) = va;
-            *reinterpret_cast<float4 *>(&Bs[row * LDK + kq]) = vb;
-        }
-        __syncthreads();
+        for (int pl = 0; pl < NP; ++pl) {
+            const int64_t r0 = (pl == 1 || pl == 3) ? n0 : m0;
 #pragma unroll
-        for (int ks = 0; ks < KC / 4; ++ks) {
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = As[(wm * 64 + i * 16 + (lane & 15)) * LDK + ks * 4 + (lane >> 4)];
-                b[i] = Bs[(wn * 64 + i * 16 + (lane & 15)) * LDK + ks * 4 + (lane >> 4)];
+            for (int it = 0; it < LOADS; ++it) {
+                const int idx = tid + 256 * it, row = idx / PIECES, pc = idx % PIECES;
+                const int64_t r = r0 + row;
+                reg[pl][it] = (r < g.M)
+                    ? *reinterpret_cast<const uint4 *>(src[pl] + r * g.ld + k0 + pc * (16 / sizeof(Elem)))
+                    : uint4{0, 0, 0, 0};
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], a32[i][j], 0, 0, 0);
         }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int pl = 0; pl < NP; ++pl)
+#pragma unroll
+            for (int it = 0; it < LOADS; ++it) {
+                const int idx = tid + 256 * it, row = idx / PIECES, pc = idx % PIECES;
+                *reinterpret_cast<uint4 *>(&sm[((buf * NP + pl) * T + row) * LDK + pc * (16 / sizeof(Elem))]) =
+                    reg[pl][it];
+            }
+    };
+
+    int since = 0;
+    if (kb < ke) {
+        load(kb);
+        store(0);
         __syncthreads();
-        since += KC;
-        if (since >= kChunk || k0 + KC >= ke) {
+        int buf = 0;
+        for (int64_t k0 = kb; k0 < ke; k0 += KC) {
+            const bool more = k0 + KC < ke;
+            if (more) load(k0 + KC);
+            if constexpr (PREC == DFJK_MIXED_FP32) {
+                const float *As = reinterpret_cast<const float *>(sm) + ((buf * 2 + 0) * T) * LDK;
+                const float *Bs = reinterpret_cast<const float *>(sm) + ((buf * 2 + 1) * T) * LDK;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int ks = 0; ks < KC / 4; ++ks) {
+                    float a[4], b[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                    for (int i = 0; i < 4; ++i) {
+                        a[i] = As[(wm * 64 + i * 16 + (lane & 15)) * LDK + ks * 4 + (lane >> 4)];
+                        b[i] = Bs[(wn * 64 + i * 16 + (lane & 15)) * LDK + ks * 4 + (lane >> 4)];
+                    }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)a32[i][j][r];
-                    a32[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], a32[i][j], 0, 0, 0);
                 }
-            since = 0;
+            } else {
+                const unsigned short *P0 = reinterpret_cast<const unsigned short *>(sm) + (buf * 4) * T * LDK;
+                const unsigned short *Ah = P0, *Bh = P0 + T * LDK, *Al = P0 + 2 * T * LDK, *Bl = P0 + 3 * T * LDK;
+#pragma unroll
+                for (int ks = 0; ks < KC / 32; ++ks) {
+                    bf16x8 ah[4], al[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int o = (wm * 64 + i * 16 + (lane & 15)) * LDK + ks * 32 + 8 * (lane >> 4);
+                        ah[i] = *reinterpret_cast<const bf16x8 *>(&Ah[o]);
+                        al[i] = *reinterpret_cast<const bf16x8 *>(&Al[o]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int o = (wn * 64 + j * 16 + (lane & 15)) * LDK + ks * 32 + 8 * (lane >> 4);
+                        const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&Bh[o]);
+                        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&Bl[o]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, a32[i][j], 0, 0, 0);
+                            a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, a32[i][j], 0, 0, 0);
+                            a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, a32[i][j], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            since += KC;
+            if (since >= kChunk || !more) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)a32[i][j][r];
+                        a32[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+                since = 0;
+            }
+            if (more) {
+                store(buf ^ 1);
+                __syncthreads();
+                buf ^= 1;
+            }
         }
     }
-    const int ntiles = g.ntm * (g.ntm + 1) / 2;
+    const int ntiles = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
     double *dst = g.partial + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * (int64_t)(T * T);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -119,105 +215,39 @@ __global__ __launch_bounds__(256) void k_syrk_f32(SyrkArgs g)
             }
 }
 
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_syrk_bf16x3(SyrkArgs g)
+// Split count: one round of workgroups (two per CU), each split a multiple
+// of the chunk of the precision and at least 512 k long.
+static int mixed_splits(int ntiles, int64_t kdim, int num_cus)
 {
-    constexpr int KC = 32, LDK = KC + 8;   // bf16 elements; row stride 80 bytes
-    __shared__ __attribute__((aligned(16))) unsigned short Ah[T * LDK], Al[T * LDK], Bh[T * LDK], Bl[T * LDK];
-    int tm, tn;
-    lower_tile(blockIdx.x, tm, tn);
-    const int64_t m0 = (int64_t)tm * T, n0 = (int64_t)tn * T;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-    const unsigned short *Xh = static_cast<const unsigned short *>(g.X);
-    const unsigned short *Xl = static_cast<const unsigned short *>(g.Xlo);
-    const int64_t kb = (int64_t)blockIdx.y * g.ksplit;
-    const int64_t ke = min(kb + g.ksplit, g.kdim);
-
-    f64x4m acc[4][4];
-    f32x4 a32[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc[i][j] = f64x4m{0.0, 0.0, 0.0, 0.0};
-            a32[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-    int since = 0;
-    for (int64_t k0 = kb; k0 < ke; k0 += KC) {
-#pragma unroll
-        for (int it = 0; it < 2; ++it) {           // 128 rows x 32 k = 512 x 16 bytes per plane
-            const int idx = tid + 256 * it, row = idx >> 2, kq = (idx & 3) * 8;
-            const int64_t m = m0 + row, n = n0 + row;
-            const uint4 z{0, 0, 0, 0};
-            uint4 ah = (m < g.M) ? *reinterpret_cast<const uint4 *>(Xh + m * g.ld + k0 + kq) : z;
-            uint4 al = (m < g.M) ? *reinterpret_cast<const uint4 *>(Xl + m * g.ld + k0 + kq) : z;
-            uint4 bh = (n < g.M) ? *reinterpret_cast<const uint4 *>(Xh + n * g.ld + k0 + kq) : z;
-            uint4 bl = (n < g.M) ? *reinterpret_cast<const uint4 *>(Xl + n * g.ld + k0 + kq) : z;
-            *reinterpret_cast<uint4 *>(&Ah[row * LDK + kq]) = ah;
-            *reinterpret_cast<uint4 *>(&Al[row * LDK + kq]) = al;
-            *reinterpret_cast<uint4 *>(&Bh[row * LDK + kq]) = bh;
-            *reinterpret_cast<uint4 *>(&Bl[row * LDK + kq]) = bl;
-        }
-        __syncthreads();
-        bf16x8 ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ra = (wm * 64 + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
-            const int rb = (wn * 64 + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4);
-            ah[i] = *reinterpret_cast<const bf16x8 *>(&Ah[ra]);
-            al[i] = *reinterpret_cast<const bf16x8 *>(&Al[ra]);
-            bh[i] = *reinterpret_cast<const bf16x8 *>(&Bh[rb]);
-            bl[i] = *reinterpret_cast<const bf16x8 *>(&Bl[rb]);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], a32[i][j], 0, 0, 0);
-                a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], a32[i][j], 0, 0, 0);
-                a32[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], a32[i][j], 0, 0, 0);
-            }
-        __syncthreads();
-        since += KC;
-        if (since >= kChunk || k0 + KC >= ke) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)a32[i][j][r];
-                    a32[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
-            since = 0;
-        }
-    }
-    const int ntiles = g.ntm * (g.ntm + 1) / 2;
-    double *dst = g.partial + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * (int64_t)(T * T);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-                const int col = wn * 64 + j * 16 + (lane & 15);
-                dst[row * T + col] = acc[i][j][r];
-            }
+    const int slots = 2 * (num_cus > 0 ? num_cus : 256);
+    int ns = ntiles >= slots ? 1 : slots / ntiles;
+    const int64_t maxs = kdim / 512;
+    if (ns > maxs) ns = (int)(maxs > 0 ? maxs : 1);
+    return ns < 1 ? 1 : ns;
 }
 
-void launch_syrk_mixed(const BuildLayout &L, const void *X, const void *Xlo, double *part, hipStream_t s)
+int mixed_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus)
 {
-    SyrkArgs g{};
-    g.X = X; g.Xlo = Xlo;
-    g.ld = L.kdim; g.M = L.nao; g.kdim = L.kdim;
-    g.ksplit = (int64_t)align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 32);
-    g.ntm = L.ntile;
+    const int ntm = (int)((nao + T - 1) / T);
+    return mixed_splits(lower ? ntm * (ntm + 1) / 2 : ntm * ntm, kdim, num_cus);
+}
+
+void launch_gemm_mixed(int precision, bool lower, const void *A, const void *Alo, const void *B, const void *Blo,
+                       int64_t nao, int64_t kdim, int nsplit, double *part, hipStream_t s)
+{
+    MixedArgs g{};
+    g.A = A; g.Alo = Alo; g.B = B; g.Blo = Blo;
+    g.ld = kdim; g.M = nao; g.kdim = kdim;
+    g.ntm = (int)((nao + T - 1) / T);
+    g.lower = lower ? 1 : 0;
+    const int kc = precision == DFJK_MIXED_FP32 ? MixStage<DFJK_MIXED_FP32>::KC : MixStage<DFJK_MIXED_BF16X3>::KC;
+    g.ksplit = (int64_t)align_up((size_t)((kdim + nsplit - 1) / nsplit), kc);
     g.partial = part;
-    const int ntiles = L.ntile * (L.ntile + 1) / 2;
-    if (L.precision == DFJK_MIXED_FP32)
-        hipLaunchKernelGGL(k_syrk_f32, dim3(ntiles, L.nsplit_k), dim3(256), 0, s, g);
+    const int ntiles = lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
+    if (precision == DFJK_MIXED_FP32)
+        hipLaunchKernelGGL(k_gemm_mixed<DFJK_MIXED_FP32>, dim3(ntiles, nsplit), dim3(256), 0, s, g);
     else
-        hipLaunchKernelGGL(k_syrk_bf16x3, dim3(ntiles, L.nsplit_k), dim3(256), 0, s, g);
+        hipLaunchKernelGGL(k_gemm_mixed<DFJK_MIXED_BF16X3>, dim3(ntiles, nsplit), dim3(256), 0, s, g);
 }
 
 }  // namespace dfjk

@@ -151,6 +151,38 @@ class Plan:
                                   _ptr(K), _ptr(E), _ptr(scr), scr.numel(), _stream_handle(stream)))
         return J, K, E
 
+    def build_delta_bytes(self, nocc, precision="fp32"):
+        n = ctypes.c_size_t()
+        _check(N.lib().dfjk_build_delta_bytes(self._h, int(nocc), PRECISION[precision], ctypes.byref(n)))
+        return n.value
+
+    def build_delta(self, C, C0, K0, precision="fp32", out=None, stream=None):
+        """K = K0 + K(D - D0) with the correction in `precision`; J, E in FP64.
+        K0 must be the FP64 K of C0 from build() on this plan."""
+        dev = torch.device("cuda")
+        C = torch.as_tensor(C, dtype=torch.float64, device=dev).contiguous()
+        C0 = torch.as_tensor(C0, dtype=torch.float64, device=dev).contiguous()
+        K0 = torch.as_tensor(K0, dtype=torch.float64, device=dev).contiguous()
+        if C.shape != C0.shape or C.dim() != 2 or C.shape[0] != self.nao:
+            raise ValueError("C and C0 must both be (nao, nocc)")
+        if tuple(K0.shape) != (self.nao, self.nao):
+            raise ValueError("K0 must be (nao, nao)")
+        nocc = C.shape[1]
+        if out is None:
+            J = torch.empty((self.nao, self.nao), dtype=torch.float64, device=dev)
+            K = torch.empty_like(J)
+            E = torch.empty(2, dtype=torch.float64, device=dev)
+        else:
+            J, K, E = out
+        key = ("delta", int(nocc), precision)
+        if key not in self._scratch:
+            self._scratch[key] = torch.empty(self.build_delta_bytes(nocc, precision), dtype=torch.uint8,
+                                             device=dev)
+        scr = self._scratch[key]
+        _check(N.lib().dfjk_build_delta(self._h, _ptr(C), _ptr(C0), int(nocc), _ptr(K0), PRECISION[precision],
+                                        _ptr(J), _ptr(K), _ptr(E), _ptr(scr), scr.numel(), _stream_handle(stream)))
+        return J, K, E
+
     # -- diagnostics -------------------------------------------------------
     NSTAGES = 10
 

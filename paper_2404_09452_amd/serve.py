@@ -1,0 +1,220 @@
+"""Continuous-batching server for DF-J/K requests on one GPU.
+
+A request is one molecule plus a sequence of occupied-orbital matrices (an
+SCF-like run): setup once, then one J/K build per matrix.  Requests arrive
+over time; the scheduler admits the head of the queue as soon as a slot is
+free and its exact device-memory need (known after the Schwarz screening)
+fits in the HBM budget.  Every admitted request runs on its own HIP stream,
+so setups and builds of different molecules overlap on the device, and
+memory is returned to the budget when a request completes.  Latency is
+measured from arrival to the completion of the request's last build.
+
+The scheduling logic is independent of the GPU: `Executor` objects do the
+work, and `GpuExecutor` is the one that drives the library.
+"""
+from __future__ import annotations
+
+import dataclasses
+import queue
+import threading
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    mol: object                 # anything with coords / ao_* / aux_* (workload.Molecule)
+    orbitals: List[np.ndarray]  # one (nao, nocc) matrix per build
+    arrival: float = 0.0        # seconds after the stream start
+    precision: str = "fp64"
+    # filled by the server
+    admitted: float = float("nan")
+    done: float = float("nan")
+    bytes_needed: int = 0
+    energies: Optional[np.ndarray] = None    # (nbuilds, 2)
+    K_last: Optional[np.ndarray] = None
+    J_last: Optional[np.ndarray] = None
+    error: Optional[str] = None
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+class Executor:
+    """What the server needs from a backend."""
+
+    def prepare(self, req: Request) -> int:
+        """Host preparation and screening; returns the device bytes the request needs."""
+        raise NotImplementedError
+
+    def run(self, req: Request) -> None:
+        """Setup and every build of the request (blocking until finished)."""
+        raise NotImplementedError
+
+    def release(self, req: Request) -> None:
+        """Free whatever the request holds."""
+
+
+class GpuExecutor(Executor):
+    """Runs requests through the DF-J/K library, one HIP stream per request."""
+
+    def __init__(self, keep_results=True, schwarz_thresh=1e-14):
+        import torch
+
+        from .dfjk import Plan
+        self.torch = torch
+        self.Plan = Plan
+        self.keep = keep_results
+        self.thresh = schwarz_thresh
+        self._plans = {}
+
+    def prepare(self, req):
+        torch = self.torch
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            plan = self.Plan.from_molecule(req.mol, schwarz_thresh=self.thresh)
+            plan.screen(stream=stream)
+            nocc = req.orbitals[0].shape[1]
+            need = plan.setup_bytes() + plan.build_bytes(nocc, "fp64")
+            if req.precision.endswith("_incr"):
+                need += plan.build_delta_bytes(nocc, req.precision[:-5])
+            elif req.precision != "fp64":
+                need += plan.build_bytes(nocc, req.precision)
+            need += 4 * plan.nao * plan.nao * 8 + nocc * plan.nao * 8 * len(req.orbitals)
+        self._plans[req.rid] = (plan, stream)
+        return int(need)
+
+    def run(self, req):
+        torch = self.torch
+        plan, stream = self._plans[req.rid]
+        with torch.cuda.stream(stream):
+            plan.setup(stream=stream)
+            nao = plan.nao
+            J = torch.empty((nao, nao), dtype=torch.float64, device="cuda")
+            K = torch.empty_like(J)
+            Es = torch.empty((len(req.orbitals), 2), dtype=torch.float64, device="cuda")
+            Cs = [torch.as_tensor(C, device="cuda") for C in req.orbitals]
+            if req.precision.endswith("_incr"):
+                # first build in FP64, later ones as increments on it
+                K0 = torch.empty_like(J)
+                plan.build(C=Cs[0], precision="fp64", out=(J, K0, Es[0]), stream=stream)
+                K.copy_(K0)
+                for k in range(1, len(Cs)):
+                    plan.build_delta(Cs[k], Cs[0], K0, precision=req.precision[:-5], out=(J, K, Es[k]),
+                                     stream=stream)
+            else:
+                for k, Cd in enumerate(Cs):
+                    plan.build(C=Cd, precision=req.precision, out=(J, K, Es[k]), stream=stream)
+            stream.synchronize()
+            req.energies = Es.cpu().numpy()
+            if self.keep:
+                req.K_last = K.cpu().numpy()
+                req.J_last = J.cpu().numpy()
+
+    def release(self, req):
+        entry = self._plans.pop(req.rid, None)
+        if entry is not None:
+            entry[0].close()
+
+
+class Server:
+    """Admission by slots and an HBM byte budget; FIFO order."""
+
+    def __init__(self, executor: Executor, max_active=4, hbm_budget_bytes=64 << 30,
+                 clock: Callable[[], float] = time.perf_counter):
+        if max_active < 1:
+            raise ValueError("max_active must be >= 1")
+        self.ex = executor
+        self.max_active = max_active
+        self.budget = int(hbm_budget_bytes)
+        self.clock = clock
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.active = 0
+        self.peak_active = 0
+        self._cv = threading.Condition()
+        self._errors = []
+
+    def _worker(self, req):
+        try:
+            self.ex.run(req)
+        except Exception as e:  # reported per request, the server keeps going
+            req.error = repr(e)
+        finally:
+            req.done = self.clock() - self._t0
+            self.ex.release(req)
+            with self._cv:
+                self.in_use -= req.bytes_needed
+                self.active -= 1
+                self._cv.notify_all()
+
+    def serve(self, requests: List[Request]) -> List[Request]:
+        """Feed `requests` at their arrival times and return them completed."""
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        arrived = queue.deque()
+        threads = []
+        self._t0 = self.clock()
+        i = 0
+        while i < len(pending) or arrived:
+            now = self.clock() - self._t0
+            while i < len(pending) and pending[i].arrival <= now:
+                arrived.append(pending[i])
+                i += 1
+            if not arrived:
+                time.sleep(max(0.0, min(0.002, pending[i].arrival - now)))
+                continue
+            head = arrived[0]
+            if head.bytes_needed == 0:
+                try:
+                    head.bytes_needed = max(1, self.ex.prepare(head))
+                except Exception as e:
+                    head.error = repr(e)
+                    head.done = self.clock() - self._t0
+                    self.ex.release(head)
+                    arrived.popleft()
+                    continue
+                if head.bytes_needed > self.budget:
+                    head.error = "needs %d bytes, more than the whole budget %d" % (head.bytes_needed, self.budget)
+                    head.done = self.clock() - self._t0
+                    self.ex.release(head)
+                    arrived.popleft()
+                    continue
+            with self._cv:
+                while not (self.active < self.max_active and self.in_use + head.bytes_needed <= self.budget):
+                    self._cv.wait(timeout=0.002)
+                    now = self.clock() - self._t0
+                    while i < len(pending) and pending[i].arrival <= now:
+                        arrived.append(pending[i])
+                        i += 1
+                self.in_use += head.bytes_needed
+                self.active += 1
+                self.peak_in_use = max(self.peak_in_use, self.in_use)
+                self.peak_active = max(self.peak_active, self.active)
+            arrived.popleft()
+            head.admitted = self.clock() - self._t0
+            th = threading.Thread(target=self._worker, args=(head,), daemon=True)
+            th.start()
+            threads.append(th)
+        for th in threads:
+            th.join()
+        return requests
+
+
+def summarize(requests: List[Request], wall_s: float):
+    ok = [r for r in requests if r.error is None]
+    lat = np.array([r.latency for r in ok]) if ok else np.array([np.nan])
+    builds = sum(len(r.orbitals) for r in ok)
+    return {
+        "requests": len(requests),
+        "failed": len(requests) - len(ok),
+        "builds": builds,
+        "wall_s": wall_s,
+        "builds_per_s": builds / wall_s if wall_s > 0 else float("nan"),
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(np.mean(lat)),
+    }

@@ -125,6 +125,42 @@ def test_jk_clusters(n):
     assert abs(E[1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
 
 
+@pytest.fixture(scope="module")
+def cluster3_seq():
+    mol, S, C0 = case(3)
+    C1 = W.perturbed_orbitals(C0, S, 1, eps=1e-2, seed=1000)
+    plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
+    _, K0, _ = plan.build(C=C0)
+    ref = [t.cpu().numpy() for t in plan.build(C=C1)]
+    return dict(mol=mol, C0=C0, C1=C1, plan=plan, K0=K0, ref=ref)
+
+
+def test_delta_build_fp64_reproduces_direct_build(cluster3_seq):
+    """K0 + G + G^T with G = X_U X_W^T in FP64 equals K(D) built directly."""
+    d = cluster3_seq
+    J, K, E = (t.cpu().numpy() for t in d["plan"].build_delta(d["C1"], d["C0"], d["K0"], precision="fp64"))
+    J1, K1, E1 = d["ref"]
+    assert np.array_equal(J, J1)
+    assert rel(K, K1) <= 1e-12
+    assert abs(E[1] - E1[1]) <= 1e-12 * abs(E1[1])
+    # and against the oracle for D(C1)
+    r = oracle.dfjk(d["mol"], C=d["C1"])
+    assert rel(K, r["K"]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_delta_build_mixed_error_shrinks_with_the_step(cluster3_seq, prec):
+    d = cluster3_seq
+    J1, K1, E1 = d["ref"]
+    _, Kd, Ed = (t.cpu().numpy() for t in d["plan"].build_delta(d["C1"], d["C0"], d["K0"], precision=prec))
+    _, Km, Em = (t.cpu().numpy() for t in d["plan"].build(C=d["C1"], precision=prec))
+    err_delta, err_direct = abs(Ed[1] - E1[1]), abs(Em[1] - E1[1])
+    print("%s: |dE_K| direct %.3e  incremental %.3e" % (prec, err_direct, err_delta))
+    assert Ed[0] == E1[0]
+    assert err_delta <= 0.05 * err_direct + 1e-12
+    assert np.abs(Kd - Kd.T).max() == 0.0
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_mixed_precision_error_is_reported(prec):
     mol, S, C = case(3)

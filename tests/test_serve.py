@@ -1,0 +1,123 @@
+"""Serving loop: admission logic on the CPU with a stub executor, and on the
+GPU the same results for a request alone and in a concurrent mix."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2404_09452_amd.serve import Executor, Request, Server, summarize
+
+
+class StubExecutor(Executor):
+    """Sleeps instead of computing; records what ran concurrently."""
+
+    def __init__(self, sizes, work_s=0.02, fail=()):
+        self.sizes = sizes
+        self.work_s = work_s
+        self.fail = set(fail)
+        self.lock = threading.Lock()
+        self.running = set()
+        self.max_bytes_seen = 0
+        self.order = []
+        self.released = []
+
+    def prepare(self, req):
+        return self.sizes[req.rid]
+
+    def run(self, req):
+        with self.lock:
+            self.running.add(req.rid)
+            self.order.append(req.rid)
+            self.max_bytes_seen = max(self.max_bytes_seen, sum(self.sizes[r] for r in self.running))
+        time.sleep(self.work_s)
+        with self.lock:
+            self.running.discard(req.rid)
+        if req.rid in self.fail:
+            raise RuntimeError("planted failure")
+        req.energies = np.zeros((len(req.orbitals), 2))
+
+    def release(self, req):
+        self.released.append(req.rid)
+
+
+def _reqs(n, gap=0.0):
+    return [Request(rid=i, mol=None, orbitals=[np.zeros((1, 1))] * 2, arrival=i * gap) for i in range(n)]
+
+
+def test_admission_respects_budget_and_slots():
+    sizes = {i: (i % 4 + 1) * 10 for i in range(16)}
+    ex = StubExecutor(sizes)
+    srv = Server(ex, max_active=3, hbm_budget_bytes=50)
+    reqs = srv.serve(_reqs(16))
+    assert all(r.error is None for r in reqs)
+    assert srv.peak_in_use <= 50 and ex.max_bytes_seen <= 50
+    assert srv.peak_active <= 3
+    assert ex.order == sorted(ex.order)                # FIFO admission
+    assert sorted(ex.released) == list(range(16))
+    assert srv.in_use == 0 and srv.active == 0
+
+
+def test_tiny_budget_serialises_and_latency_includes_queueing():
+    sizes = {i: 10 for i in range(5)}
+    ex = StubExecutor(sizes, work_s=0.03)
+    srv = Server(ex, max_active=4, hbm_budget_bytes=10)
+    t0 = time.perf_counter()
+    reqs = srv.serve(_reqs(5))
+    wall = time.perf_counter() - t0
+    assert srv.peak_active == 1
+    lat = sorted(r.latency for r in reqs)
+    assert lat[-1] >= 4 * 0.03                        # the last one waited for four others
+    s = summarize(reqs, wall)
+    assert s["builds"] == 10 and s["failed"] == 0
+    assert s["p99_latency_s"] >= s["p50_latency_s"]
+
+
+def test_oversize_and_failing_requests_are_reported_not_fatal():
+    sizes = {0: 5, 1: 500, 2: 5, 3: 5}
+    ex = StubExecutor(sizes, fail={2})
+    srv = Server(ex, max_active=2, hbm_budget_bytes=100)
+    reqs = srv.serve(_reqs(4))
+    assert "budget" in reqs[1].error
+    assert "planted" in reqs[2].error
+    assert reqs[0].error is None and reqs[3].error is None
+    assert srv.in_use == 0
+
+
+def test_arrivals_are_honoured():
+    sizes = {i: 1 for i in range(4)}
+    ex = StubExecutor(sizes, work_s=0.001)
+    srv = Server(ex, max_active=4, hbm_budget_bytes=100)
+    reqs = srv.serve(_reqs(4, gap=0.02))
+    for r in reqs:
+        assert r.admitted >= r.arrival - 1e-6
+
+
+@pytest.mark.gpu
+def test_results_identical_alone_and_in_the_mix():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import workload as W
+    from paper_2404_09452_amd.serve import GpuExecutor
+
+    def make(rid, n, arrival):
+        z, x = W.water_cluster(n, W.cluster_box(n), 500 + rid) if n > 1 else W.water_monomer()
+        mol = W.make_molecule(z, x)
+        S = W.overlap_by_quadrature(mol)
+        C0 = W.occupied_orbitals(S, mol.nelec // 2, rid)
+        orbs = [W.perturbed_orbitals(C0, S, k, seed=77 + rid) for k in range(3)]
+        return Request(rid=rid, mol=mol, orbitals=orbs, arrival=arrival)
+
+    sizes = [1, 3, 2, 4, 1, 5]
+    mix = [make(i, n, 0.005 * i) for i, n in enumerate(sizes)]
+    srv = Server(GpuExecutor(), max_active=3, hbm_budget_bytes=8 << 30)
+    srv.serve(mix)
+    assert srv.peak_active >= 2, "the mix never overlapped"
+    for r in mix:
+        assert r.error is None, r.error
+        alone = make(r.rid, sizes[r.rid], 0.0)
+        Server(GpuExecutor(), max_active=1, hbm_budget_bytes=8 << 30).serve([alone])
+        assert np.array_equal(alone.energies, r.energies)
+        assert np.array_equal(alone.K_last, r.K_last)
+        assert np.array_equal(alone.J_last, r.J_last)

@@ -155,7 +155,7 @@ def _shapes(l, x, y, z):
     raise ValueError("l > 3")
 
 
-_GH_T, _GH_W = np.polynomial.hermite.hermgauss(6)   # exact for degree <= 11 per axis
+_GH_T, _GH_W = np.polynomial.hermite.hermgauss(4)   # exact for degree <= 7 per axis (f x f is 6)
 
 
 def _pair_raw(la, ea, A, lb, eb, B):
@@ -201,21 +201,26 @@ def overlap_by_quadrature(mol: Molecule) -> np.ndarray:
             norms[offs[sh]:offs[sh + 1]] = np.sqrt(np.diag(blk[k]))
     S = np.zeros((mol.nao, mol.nao))
     ia, ib = np.tril_indices(nsh)
+    # pairs of distant shells overlap below 1e-300 and are skipped
+    d2 = np.sum((A_all[ia] - A_all[ib]) ** 2, axis=1)
+    mu = mol.ao_exp[ia] * mol.ao_exp[ib] / (mol.ao_exp[ia] + mol.ao_exp[ib])
+    near = mu * d2 < 690.0
+    ia, ib = ia[near], ib[near]
     for la in np.unique(mol.ao_l):
         for lb in np.unique(mol.ao_l):
             sel = (mol.ao_l[ia] == la) & (mol.ao_l[ib] == lb)
             if not np.any(sel):
                 continue
             a, b = ia[sel], ib[sel]
+            na, nb = 2 * la + 1, 2 * lb + 1
             for c0 in range(0, len(a), 4096):
                 aa, bb = a[c0:c0 + 4096], b[c0:c0 + 4096]
                 blk = _pair_raw(la, mol.ao_exp[aa], A_all[aa], lb, mol.ao_exp[bb], A_all[bb])
-                for k in range(len(aa)):
-                    sa = slice(offs[aa[k]], offs[aa[k] + 1])
-                    sb = slice(offs[bb[k]], offs[bb[k] + 1])
-                    v = blk[k] / np.outer(norms[sa], norms[sb])
-                    S[sa, sb] = v
-                    S[sb, sa] = v.T
+                rows = offs[aa][:, None] + np.arange(na)[None, :]          # (npair, na)
+                cols = offs[bb][:, None] + np.arange(nb)[None, :]          # (npair, nb)
+                v = blk / (norms[rows][:, :, None] * norms[cols][:, None, :])
+                S[rows[:, :, None], cols[:, None, :]] = v
+                S[cols[:, None, :], rows[:, :, None]] = v
     return S
 
 
