@@ -140,54 +140,57 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float x)
 }
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-// Workgroup (mu, 128-row P tile, column pass of NIB*16 columns).  Wave w owns
-// rows p0 + 32w .. +31 as two 16-row MFMA fragments.  The k list of mu is
-// walked in chunks of 16: the gathered coefficient rows C[nu_k][cols] go
-// through double-buffered LDS, and the gathered tensor values B[row_k][P]
-// (the A operand, one double per lane, 16 contiguous P per k) are loaded one
-// chunk ahead with their row indices two chunks ahead, so load latency hides
-// under the MFMAs of the current chunk.  One barrier per chunk.
+// Workgroup (mu, 128-row P tile, column pass of NIB*16 columns) of eight
+// waves; wave w owns rows p0 + 16w .. +15 (one MFMA fragment).  The k list
+// of mu is walked in chunks of 16.  Both operands of a chunk go through
+// double-buffered LDS: the gathered tensor rows B[row_k][p0 .. p0+127]
+// (1 KB contiguous per k) and the gathered coefficient rows C[nu_k][cols].
+// The next chunk is loaded into registers while the current one feeds the
+// MFMAs, with its row indices read one chunk earlier; one barrier per chunk.
+// Eight single-fragment waves keep four waves per SIMD for up to 160 columns.
 template <int OUT, int NIB>
-__global__ __launch_bounds__(256) void k_halftrans(HTArgs g)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NIB <= 10 ? 4 : 2)))
+void k_halftrans(HTArgs g)
 {
-    constexpr int KC = 16;
+    constexpr int NT = 512, KC = 16;
     constexpr int NCOL = NIB * 16;
     constexpr int PAD = (16 - NCOL % 32 + 32) % 32;     // k rows of a fragment read land on opposite bank halves
     constexpr int LDC = NCOL + PAD;
-    constexpr int NLOAD = (KC * NCOL / 2 + 255) / 256;  // double2 loads per thread per chunk
+    constexpr int LDA = 128 + 16;                       // same for the 128-wide tensor rows
+    constexpr int NLC = (KC * NCOL / 2 + NT - 1) / NT;  // double2 loads per thread per chunk (C)
+    constexpr int NLA = KC * 128 / 2 / NT;              // double2 loads per thread per chunk (B) = 2
     __shared__ double Cs[2][KC * LDC];
+    __shared__ double As[2][KC * LDA];
     const int mu = blockIdx.y;
     const int64_t p0 = (int64_t)blockIdx.x * 128;
     const int ic0 = blockIdx.z * NCOL;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kb = g.hk_off[mu], ke = g.hk_off[mu + 1];
-    const int64_t prow = p0 + 32 * wave + (lane & 15);
     const int kl = lane >> 4;   // k within an MFMA step
 
-    f64x4 acc[2][NIB];
+    f64x4 acc[NIB];
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int j = 0; j < NIB; ++j) acc[f][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NIB; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    auto load_rows = [&](int kc, int (&r)[4]) {
+    auto load_rows = [&](int kc, int (&r)[NLA]) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k = kc + ks * 4 + kl;
-            r[ks] = (k < ke) ? g.hk_row[k] : -1;
+        for (int it = 0; it < NLA; ++it) {
+            const int k = kc + (tid + NT * it) / 64;
+            r[it] = (k < ke) ? g.hk_row[k] : -1;
         }
     };
-    auto load_a = [&](const int (&r)[4], double (&a)[4][2]) {
+    auto load_a = [&](const int (&r)[NLA], double2 (&a)[NLA]) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-            for (int f = 0; f < 2; ++f)
-                a[ks][f] = (r[ks] >= 0) ? g.B[(int64_t)r[ks] * g.ld + prow + 16 * f] : 0.0;
+        for (int it = 0; it < NLA; ++it) {
+            const int pp = ((tid + NT * it) % 64) * 2;
+            a[it] = (r[it] >= 0) ? *reinterpret_cast<const double2 *>(g.B + (int64_t)r[it] * g.ld + p0 + pp)
+                                 : double2{0.0, 0.0};
+        }
     };
-    auto load_c = [&](int kc, double2 (&c)[NLOAD]) {
+    auto load_c = [&](int kc, double2 (&c)[NLC]) {
 #pragma unroll
-        for (int it = 0; it < NLOAD; ++it) {
-            const int e = tid + 256 * it;             // double2 index in the KC x NCOL chunk
+        for (int it = 0; it < NLC; ++it) {
+            const int e = tid + NT * it;              // double2 index in the KC x NCOL chunk
             const int kk = e / (NCOL / 2), cc = (e % (NCOL / 2)) * 2;
             double2 v{0.0, 0.0};
             if (e < KC * NCOL / 2 && kc + kk < ke) {
@@ -198,10 +201,15 @@ __global__ __launch_bounds__(256) void k_halftrans(HTArgs g)
             c[it] = v;
         }
     };
-    auto store_c = [&](int buf, const double2 (&c)[NLOAD]) {
+    auto store = [&](int buf, const double2 (&a)[NLA], const double2 (&c)[NLC]) {
 #pragma unroll
-        for (int it = 0; it < NLOAD; ++it) {
-            const int e = tid + 256 * it;
+        for (int it = 0; it < NLA; ++it) {
+            const int e = tid + NT * it, kk = e / 64, pp = (e % 64) * 2;
+            *reinterpret_cast<double2 *>(&As[buf][kk * LDA + pp]) = a[it];
+        }
+#pragma unroll
+        for (int it = 0; it < NLC; ++it) {
+            const int e = tid + NT * it;
             if (e < KC * NCOL / 2) {
                 const int kk = e / (NCOL / 2), cc = (e % (NCOL / 2)) * 2;
                 Cs[buf][kk * LDC + cc] = c[it].x;
@@ -210,66 +218,56 @@ __global__ __launch_bounds__(256) void k_halftrans(HTArgs g)
         }
     };
 
-    int rows_next[4], rows_cur[4];
-    double a_cur[4][2], a_next[4][2];
-    double2 creg[NLOAD];
-    load_rows(kb, rows_cur);
-    load_a(rows_cur, a_cur);
-    load_rows(kb + KC, rows_next);
+    int rows[NLA];
+    double2 areg[NLA], creg[NLC];
+    load_rows(kb, rows);
+    load_a(rows, areg);
     load_c(kb, creg);
+    load_rows(kb + KC, rows);
     int buf = 0;
     for (int kc = kb; kc < ke; kc += KC) {
-        store_c(buf, creg);
+        store(buf, areg, creg);
         __syncthreads();
         const bool more = kc + KC < ke;
         if (more) {
+            load_a(rows, areg);
             load_c(kc + KC, creg);
-            load_a(rows_next, a_next);
-            load_rows(kc + 2 * KC, rows_next);
+            load_rows(kc + 2 * KC, rows);
         }
+        const double *as = As[buf] + kl * LDA + 16 * wave + (lane & 15);
         const double *cs = Cs[buf] + kl * LDC + (lane & 15);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
+        for (int ks = 0; ks < 4; ++ks) {
+            const double a = as[ks * 4 * LDA];
 #pragma unroll
-            for (int j = 0; j < NIB; ++j) {
-                const double b = cs[ks * 4 * LDC + j * 16];
-                acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[ks][0], b, acc[0][j], 0, 0, 0);
-                acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[ks][1], b, acc[1][j], 0, 0, 0);
-            }
-        if (more) {
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                a_cur[ks][0] = a_next[ks][0];
-                a_cur[ks][1] = a_next[ks][1];
-            }
+            for (int j = 0; j < NIB; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cs[ks * 4 * LDC + j * 16], acc[j], 0, 0, 0);
         }
         buf ^= 1;
     }
 
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+    for (int j = 0; j < NIB; ++j) {
+        const int col = ic0 + j * 16 + (lane & 15);
+        if (col >= g.ncol) continue;
 #pragma unroll
-        for (int j = 0; j < NIB; ++j) {
-            const int col = ic0 + j * 16 + (lane & 15);
-            if (col >= g.ncol) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t P = p0 + 32 * wave + 16 * f + kl + 4 * r;
-                const int64_t o = ((int64_t)mu * g.ld + P) * g.ncol + col;
-                const double v64 = acc[f][j][r];
-                if (OUT == OUT_F64) {
-                    static_cast<double *>(g.X)[o] = v64;
-                } else if (OUT == OUT_F32) {
-                    static_cast<float *>(g.X)[o] = (float)v64;
-                } else {
-                    const float v = (float)v64;
-                    const unsigned short hi = f32_to_bf16_rne(v);
-                    const unsigned short lo = f32_to_bf16_rne(v - bf16_to_f32(hi));
-                    static_cast<unsigned short *>(g.X)[o] = hi;
-                    static_cast<unsigned short *>(g.Xlo)[o] = lo;
-                }
+        for (int r = 0; r < 4; ++r) {
+            const int64_t P = p0 + 16 * wave + kl + 4 * r;
+            const int64_t o = ((int64_t)mu * g.ld + P) * g.ncol + col;
+            const double v64 = acc[j][r];
+            if (OUT == OUT_F64) {
+                static_cast<double *>(g.X)[o] = v64;
+            } else if (OUT == OUT_F32) {
+                static_cast<float *>(g.X)[o] = (float)v64;
+            } else {
+                const float v = (float)v64;
+                const unsigned short hi = f32_to_bf16_rne(v);
+                const unsigned short lo = f32_to_bf16_rne(v - bf16_to_f32(hi));
+                static_cast<unsigned short *>(g.X)[o] = hi;
+                static_cast<unsigned short *>(g.Xlo)[o] = lo;
             }
         }
+    }
 }
 
 template <int OUT>
@@ -280,7 +278,7 @@ static void launch_halftrans(const HTArgs &h, int64_t nao, hipStream_t s)
     const int passes = (nib_needed + nib - 1) / nib;
     dim3 grid((unsigned)(h.ld / 128), (unsigned)nao, (unsigned)passes);
 #define HT_CASE(N) \
-    case N: hipLaunchKernelGGL((k_halftrans<OUT, N>), grid, dim3(256), 0, s, h); break;
+    case N: hipLaunchKernelGGL((k_halftrans<OUT, N>), grid, dim3(512), 0, s, h); break;
     switch (nib) {
         HT_CASE(1) HT_CASE(2) HT_CASE(3) HT_CASE(4) HT_CASE(5) HT_CASE(6) HT_CASE(7) HT_CASE(8)
         HT_CASE(9) HT_CASE(10) HT_CASE(11) HT_CASE(12) HT_CASE(13) HT_CASE(14) HT_CASE(15) HT_CASE(16)
