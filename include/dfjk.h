@@ -82,6 +82,13 @@ typedef struct {
                                     Q the Schwarz factors sqrt|(ab|ab)|,
                                     sqrt (P|P); 0 keeps everything.  Default
                                     1e-14.                                    */
+    int32_t aux_slab;            /* aux functions per slab of the K build
+                                    (rounded up to 128): the half-transformed
+                                    tensor X is formed and contracted one aux
+                                    slab at a time, so its memory is
+                                    nao * slab * nocc elements.  0 = automatic
+                                    (one slab while X stays under 48 GB,
+                                    else 1024).                                */
 } dfjk_options;
 
 typedef struct dfjk_plan dfjk_plan;

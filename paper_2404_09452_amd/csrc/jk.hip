@@ -127,8 +127,9 @@ struct HTArgs {
     const double *C;          // [nao][ncol]
     int32_t ncol;
     const int32_t *hk_off, *hk_row, *hk_nu;
-    void *X;                  // [nao][ld][ncol]
+    void *X;                  // [nao][plen][ncol]: aux rows p_begin .. p_begin + plen - 1
     void *Xlo;                // second plane for the BF16 split
+    int64_t p_begin, plen;    // aux slab (multiples of 128)
 };
 
 
@@ -162,7 +163,7 @@ void k_halftrans(HTArgs g)
     __shared__ double Cs[2][KC * LDC];
     __shared__ double As[2][KC * LDA];
     const int mu = blockIdx.y;
-    const int64_t p0 = (int64_t)blockIdx.x * 128;
+    const int64_t p0 = g.p_begin + (int64_t)blockIdx.x * 128;
     const int ic0 = blockIdx.z * NCOL;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kb = g.hk_off[mu], ke = g.hk_off[mu + 1];
@@ -253,7 +254,7 @@ void k_halftrans(HTArgs g)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t P = p0 + 16 * wave + kl + 4 * r;
-            const int64_t o = ((int64_t)mu * g.ld + P) * g.ncol + col;
+            const int64_t o = ((int64_t)mu * g.plen + (P - g.p_begin)) * g.ncol + col;
             const double v64 = acc[j][r];
             if (OUT == OUT_F64) {
                 static_cast<double *>(g.X)[o] = v64;
@@ -276,7 +277,7 @@ static void launch_halftrans(const HTArgs &h, int64_t nao, hipStream_t s)
     const int nib_needed = (h.ncol + 15) / 16;
     const int nib = nib_needed < 16 ? nib_needed : 16;
     const int passes = (nib_needed + nib - 1) / nib;
-    dim3 grid((unsigned)(h.ld / 128), (unsigned)nao, (unsigned)passes);
+    dim3 grid((unsigned)(h.plen / 128), (unsigned)nao, (unsigned)passes);
 #define HT_CASE(N) \
     case N: hipLaunchKernelGGL((k_halftrans<OUT, N>), grid, dim3(512), 0, s, h); break;
     switch (nib) {
@@ -291,12 +292,13 @@ __global__ __launch_bounds__(256) void k_expand_B(const double *__restrict__ B, 
                                                   const int32_t *__restrict__ hk_off,
                                                   const int32_t *__restrict__ hk_row,
                                                   const int32_t *__restrict__ hk_nu, int64_t nao,
-                                                  double *__restrict__ Bt)
+                                                  int64_t p_begin, int64_t plen, double *__restrict__ Bt)
 {
     const int mu = blockIdx.y;
-    const int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (P >= ld) return;
-    double *dst = Bt + ((int64_t)mu * ld + P) * nao;
+    const int64_t pl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pl >= plen) return;
+    const int64_t P = p_begin + pl;
+    double *dst = Bt + ((int64_t)mu * plen + pl) * nao;
     for (int64_t n = 0; n < nao; ++n) dst[n] = 0.0;
     for (int k = hk_off[mu]; k < hk_off[mu + 1]; ++k) dst[hk_nu[k]] = B[(int64_t)hk_row[k] * ld + P];
 }
@@ -452,8 +454,15 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.with_D = with_D;
     L.nsplit_c = (int)((p.nf_pad + kCSplitRows - 1) / kCSplitRows);
     L.ntile = (int)((p.nao + kTileK - 1) / kTileK);
-    L.kdim = p.naux_pad * L.ncol;
     L.delta = delta;
+    // aux slab of the K build: X = nao x slab x ncol elements per operand
+    const size_t esz = precision == DFJK_FP64 ? 8 : (precision == DFJK_MIXED_FP32 ? 4 : 2);
+    int64_t slab = p.aux_slab > 0 ? (int64_t)align_up((size_t)p.aux_slab, kPadAux) : p.naux_pad;
+    if (p.aux_slab == 0 && (double)p.nao * p.naux_pad * L.ncol * esz > 48e9) slab = 1024;
+    if (slab > p.naux_pad) slab = p.naux_pad;
+    L.slab = slab;
+    L.nslab = (p.naux_pad + slab - 1) / slab;
+    L.kdim = slab * L.ncol;
     const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
     L.nsplit_k = (precision == DFJK_FP64) ? choose_ksplit(ntiles, L.kdim, p.num_cus)
                                           : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
@@ -469,7 +478,6 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.o_cpart = take((size_t)L.nsplit_c * p.naux_pad * 8);
     L.o_c = take((size_t)p.naux_pad * 8);
     const size_t nx = (size_t)p.nao * L.kdim;
-    const size_t esz = precision == DFJK_FP64 ? 8 : (precision == DFJK_MIXED_FP32 ? 4 : 2);
     L.o_X = take(nx * esz);
     L.o_Xlo = precision == DFJK_MIXED_BF16X3 ? take(nx * 2) : 0;
     L.o_Bfull = with_D ? take(nx * 8) : 0;
@@ -479,7 +487,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
         L.o_U = take((size_t)p.nao * nocc * 8);
         L.o_W = take((size_t)p.nao * nocc * 8);
     }
-    L.o_Kpart = take((size_t)L.nsplit_k * ntiles * kTileK * kTileK * 8);
+    L.o_Kpart = take((size_t)L.nslab * L.nsplit_k * ntiles * kTileK * kTileK * 8);
     L.o_Epart = take((size_t)L.ntile * (L.ntile + 1) / 2 * (kTileK / 16) * 8);
     L.bytes = align_up(off, 256);
     return L;
@@ -507,10 +515,10 @@ static void launch_j(Plan &p, const BuildLayout &L, const double *D, double *J, 
                            p.d.f_nu, p.d.f_w, p.nf, nao, J);
 }
 
-static void launch_ht(const Plan &p, int precision, const double *C, int32_t ncol, void *X, void *Xlo,
-                      hipStream_t s)
+static void launch_ht(const Plan &p, int precision, const double *C, int32_t ncol, int64_t p_begin, int64_t plen,
+                      void *X, void *Xlo, hipStream_t s)
 {
-    HTArgs h{p.d.B, p.naux_pad, C, ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo};
+    HTArgs h{p.d.B, p.naux_pad, C, ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen};
     if (precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, p.nao, s);
     else if (precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, p.nao, s);
     else launch_halftrans<OUT_BF16X2>(h, p.nao, s);
@@ -547,45 +555,57 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
     pr.mark(ST_J, true);
     launch_j(p, L, D, J, scratch, s);
     pr.mark(ST_J, false);
-    // 5. half transform(s)
-    pr.mark(ST_HALFTRANS, true);
-    if (!L.delta) {
-        launch_ht(p, L.precision, L.with_D ? Din : C, (int32_t)L.ncol, X, Xlo, s);
-        if (L.with_D)
-            hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((ld + 255) / 256), (unsigned)nao), dim3(256), 0, s,
-                               p.d.B, ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, Bt);
-    } else {
-        launch_ht(p, L.precision, reinterpret_cast<double *>(scratch + L.o_U), (int32_t)L.ncol, X, Xlo, s);
-        launch_ht(p, L.precision, reinterpret_cast<double *>(scratch + L.o_W), (int32_t)L.ncol,
-                  scratch + L.o_X2, L.o_X2lo ? scratch + L.o_X2lo : nullptr, s);
-    }
-    pr.mark(ST_HALFTRANS, false);
-    // 6. K (lower tiles of 2 X X^T or X Bt^T; every tile of X_U X_W^T for the increment)
-    pr.mark(ST_K, true);
+    // 5-6. per aux slab: half transform(s), then the slab's K contribution into its own
+    // split-K partials (lower tiles of 2 X X^T or X Bt^T; every tile of X_U X_W^T for the
+    // increment). Slabs reuse the X buffers; the stream orders them.
     const bool lower = !L.delta;
-    const void *Bop = L.delta ? (const void *)(scratch + L.o_X2) : (L.with_D ? (const void *)Bt : (const void *)X);
-    const void *Bop_lo = L.delta ? (L.o_X2lo ? (const void *)(scratch + L.o_X2lo) : nullptr) : Xlo;
-    if (L.precision == DFJK_FP64) {
-        GemmArgs g{};
-        g.A = static_cast<const double *>(X); g.lda = L.kdim;
-        g.B = static_cast<const double *>(Bop); g.ldb = L.kdim;
-        g.M = g.N = nao;
-        g.k_begin = 0; g.k_end = L.kdim;
-        g.ksplit = align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
-        g.alpha = 1.0; g.lower = lower ? 1 : 0; g.partial = Kpart;
-        gemm_f64<kTileK, false>(g, L.nsplit_k, s);
-    } else {
-        launch_gemm_mixed(L.precision, lower, X, Xlo, Bop, Bop_lo, nao, L.kdim, L.nsplit_k, Kpart, s);
+    const int ntiles = lower ? L.ntile * (L.ntile + 1) / 2 : L.ntile * L.ntile;
+    const size_t slab_part = (size_t)L.nsplit_k * ntiles * kTileK * kTileK;
+    double *U = reinterpret_cast<double *>(scratch + L.o_U), *W = reinterpret_cast<double *>(scratch + L.o_W);
+    void *X2 = L.delta ? scratch + L.o_X2 : nullptr;
+    void *X2lo = L.o_X2lo ? scratch + L.o_X2lo : nullptr;
+    for (int64_t sl = 0; sl < L.nslab; ++sl) {
+        const int64_t pb = sl * L.slab, plen = (ld - pb < L.slab) ? ld - pb : L.slab;
+        const int64_t kdim = plen * L.ncol;
+        pr.mark(ST_HALFTRANS, true);
+        if (!L.delta) {
+            launch_ht(p, L.precision, L.with_D ? Din : C, (int32_t)L.ncol, pb, plen, X, Xlo, s);
+            if (L.with_D)
+                hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((plen + 255) / 256), (unsigned)nao), dim3(256), 0,
+                                   s, p.d.B, ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, pb, plen, Bt);
+        } else {
+            launch_ht(p, L.precision, U, (int32_t)L.ncol, pb, plen, X, Xlo, s);
+            launch_ht(p, L.precision, W, (int32_t)L.ncol, pb, plen, X2, X2lo, s);
+        }
+        pr.mark(ST_HALFTRANS, false);
+        pr.mark(ST_K, true);
+        const void *Bop = L.delta ? (const void *)X2 : (L.with_D ? (const void *)Bt : (const void *)X);
+        const void *Bop_lo = L.delta ? (const void *)X2lo : Xlo;
+        double *part = Kpart + sl * slab_part;
+        if (L.precision == DFJK_FP64) {
+            GemmArgs g{};
+            g.A = static_cast<const double *>(X); g.lda = kdim;
+            g.B = static_cast<const double *>(Bop); g.ldb = kdim;
+            g.M = g.N = nao;
+            g.k_begin = 0; g.k_end = kdim;
+            g.ksplit = align_up((size_t)((kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
+            g.alpha = 1.0; g.lower = lower ? 1 : 0; g.partial = part;
+            gemm_f64<kTileK, false>(g, L.nsplit_k, s);
+        } else {
+            launch_gemm_mixed(L.precision, lower, X, Xlo, Bop, Bop_lo, nao, kdim, L.nsplit_k, part, s);
+        }
+        pr.mark(ST_K, false);
     }
-    pr.mark(ST_K, false);
     // 7. split-K sum, mirror, energies
     pr.mark(ST_KREDUCE, true);
     const int nlower = L.ntile * (L.ntile + 1) / 2;
     if (L.delta)
-        hipLaunchKernelGGL(k_k_reduce_delta, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, L.nsplit_k,
+        hipLaunchKernelGGL(k_k_reduce_delta, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart,
+                           (int)(L.nslab * L.nsplit_k),
                            L.ntile, nao, L.K0, D, K, Epart);
     else
-        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, L.nsplit_k, L.ntile, nao,
+        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
+                           L.ntile, nao,
                            L.with_D ? 1.0 : 2.0, D, K, Epart);
     hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (kTileK / 16), E);
     pr.mark(ST_KREDUCE, false);

@@ -51,7 +51,8 @@ class Plan:
 
     coords: (natm, 3) Bohr; ao and aux: (atom, l, exponent) arrays."""
 
-    def __init__(self, coords, ao_atom, ao_l, ao_exp, aux_atom, aux_l, aux_exp, schwarz_thresh=1e-14):
+    def __init__(self, coords, ao_atom, ao_l, ao_exp, aux_atom, aux_l, aux_exp, schwarz_thresh=1e-14,
+                 aux_slab=0):
         L = N.lib()
         self._keep = []
         coords = np.ascontiguousarray(coords, dtype=np.float64)
@@ -66,7 +67,7 @@ class Plan:
 
         ao = basis(ao_atom, ao_l, ao_exp)
         aux = basis(aux_atom, aux_l, aux_exp)
-        opt = N.Options(float(schwarz_thresh))
+        opt = N.Options(float(schwarz_thresh), int(aux_slab))
         h = ctypes.c_void_p()
         _check(L.dfjk_plan_create(len(coords), coords.ctypes.data_as(N.P_dbl), ctypes.byref(ao),
                                   ctypes.byref(aux), ctypes.byref(opt), ctypes.byref(h)))
@@ -77,9 +78,9 @@ class Plan:
         self.nao, self.naux = inf["nao"], inf["naux"]
 
     @classmethod
-    def from_molecule(cls, mol, schwarz_thresh=1e-14):
+    def from_molecule(cls, mol, schwarz_thresh=1e-14, aux_slab=0):
         return cls(mol.coords, mol.ao_atom, mol.ao_l, mol.ao_exp, mol.aux_atom, mol.aux_l, mol.aux_exp,
-                   schwarz_thresh=schwarz_thresh)
+                   schwarz_thresh=schwarz_thresh, aux_slab=aux_slab)
 
     # -- facts -------------------------------------------------------------
     def info(self):

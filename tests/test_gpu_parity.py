@@ -173,3 +173,41 @@ def test_mixed_precision_error_is_reported(prec):
     assert dEJ == 0.0
     bound = 1e-5 if prec == "fp32" else 1e-3
     assert dEK <= bound * abs(E64[1])
+
+
+@pytest.fixture(scope="module")
+def cluster5():
+    mol, S, C = case(5)
+    ref = oracle.dfjk(mol, C=C)
+    one = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
+    return dict(mol=mol, S=S, C=C, ref=ref, one=one,
+                base=[t.cpu().numpy() for t in one.build(C=C)])
+
+
+@pytest.mark.parametrize("slab", [128, 384])
+def test_aux_slabs_match_one_slab(cluster5, slab):
+    """Streaming the K build over aux slabs (naux_pad 512: 4 slabs, or 384 + a ragged 128)
+    changes only the order of the split-K sum."""
+    d = cluster5
+    plan = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU, aux_slab=slab).screen().setup().profile()
+    assert plan.info()["naux_pad"] == 512
+    J, K, E = (t.cpu().numpy() for t in plan.build(C=d["C"]))
+    nslab = (512 + slab - 1) // slab
+    assert plan.profile_read()["build.halftransform"][1] == nslab
+    J1, K1, E1 = d["base"]
+    assert np.array_equal(J, J1)
+    assert rel(K, K1) <= 1e-13
+    assert abs(E[1] - E1[1]) <= 1e-13 * abs(E1[1])
+    assert rel(K, d["ref"]["K"]) <= 1e-10
+    # density route through the same slabs
+    D = 2.0 * d["C"] @ d["C"].T
+    _, KD, ED = (t.cpu().numpy() for t in plan.build(D=D))
+    assert rel(KD, d["ref"]["K"]) <= 1e-10
+    # mixed and incremental builds keep their error bounds across slabs
+    _, Km, Em = (t.cpu().numpy() for t in plan.build(C=d["C"], precision="fp32"))
+    assert abs(Em[1] - E1[1]) <= 1e-5 * abs(E1[1])
+    C1 = W.perturbed_orbitals(d["C"], d["S"], 1, eps=1e-2, seed=1000)
+    K0 = d["one"].build(C=d["C"])[1]
+    _, Kd, Ed = (t.cpu().numpy() for t in plan.build_delta(C1, d["C"], K0, precision="fp64"))
+    _, Kr, Er = (t.cpu().numpy() for t in d["one"].build(C=C1))
+    assert rel(Kd, Kr) <= 1e-12
