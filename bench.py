@@ -163,6 +163,79 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6):
     return out
 
 
+def large_bench(nbuild=2):
+    """The 128-water cluster (3,840 AO, 11,136 aux, nocc 640, 16 A box, geometry
+    seed 4, Schwarz 1e-10): one setup, then `nbuild` builds per precision with
+    the K build streamed over aux slabs.  Reports ms per build, the K
+    contraction's MFMA rate against each precision's peak, the integral and
+    whitening times of the setup, and the energy error of the mixed builds
+    (direct, and incremental from the first FP64 build) against FP64."""
+    import numpy as np
+    import torch
+    import workload as W
+    from paper_2404_09452_amd.dfjk import Plan
+
+    z, x = W.water_cluster(128, 16.0, 4)
+    mol = W.make_molecule(z, x)
+    S = W.overlap_by_quadrature(mol)
+    C0 = W.occupied_orbitals(S, mol.nelec // 2, 4)
+    Cs = [torch.as_tensor(W.perturbed_orbitals(C0, S, k, eps=1e-2, seed=1000), device="cuda")
+          for k in range(nbuild)]
+    nao, naux, nocc = mol.nao, mol.naux, mol.nelec // 2
+    plan = Plan.from_molecule(mol, schwarz_thresh=1e-10).profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.screen().setup()
+    torch.cuda.synchronize()
+    setup_wall = time.perf_counter() - t0
+    st = plan.profile_read()
+    info = plan.info()
+    k_flops = float(nao) * (nao + 1) * naux * nocc
+    out = {"workload": "water128: 128-water cluster, 16 A box, 3840 AO / 11136 aux / nocc 640, Schwarz 1e-10",
+           "screening": {k: info[k] for k in ("sig_shell_pairs", "nshell_pairs", "nf", "triplets_kept")},
+           "setup_s": round(setup_wall, 4),
+           "setup_stage_ms": {k: round(v[0], 3) for k, v in st.items() if k.startswith("setup.")},
+           "B_resident_GB": round(info["nf"] * info["naux_pad"] * 8 / 1e9, 2)}
+    ref = None
+    for prec, peak in (("fp64", PEAK_F64_TFLOPS), ("fp32", PEAK_F32_TFLOPS), ("bf16x3", PEAK_BF16_TFLOPS / 3.0),
+                       ("fp32_incr", PEAK_F32_TFLOPS)):
+        incr = prec.endswith("_incr")
+        Es = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, C in enumerate(Cs):
+            if incr and k > 0:
+                J, K, E = plan.build_delta(C, Cs[0], K0, precision="fp32")
+            else:
+                J, K, E = plan.build(C=C, precision="fp64" if incr else prec)
+                if incr:
+                    K0 = K
+            Es.append(E)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = plan.profile_read()
+        E = np.array([e.cpu().numpy() for e in Es])
+        kms = st["build.K"][0] / max(nbuild - (1 if incr else 0), 1)
+        r = {"ms_per_build": round(1000.0 * wall / nbuild, 2),
+             "stage_ms_per_build": {k: round(v[0] / nbuild, 3) for k, v in st.items() if k.startswith("build.")},
+             "E": E.tolist()}
+        if not incr:
+            r["K_tflops"] = round(k_flops / (kms * 1e-3) / 1e12, 2)
+            r["K_frac_of_peak"] = round(k_flops / (kms * 1e-3) / 1e12 / peak, 4)
+        if prec == "fp64":
+            ref = E
+        else:
+            r["max_abs_dE_J"] = float(np.abs(E[:, 0] - ref[:, 0]).max())
+            r["max_abs_dE_K"] = float(np.abs(E[:, 1] - ref[:, 1]).max())
+            r["meets_1e-6_Eh"] = bool(max(r["max_abs_dE_J"], r["max_abs_dE_K"]) <= 1e-6)
+        out[prec] = r
+        plan._scratch = {}
+        print("bench: water128 %s %.1f ms/build" % (prec, r["ms_per_build"]), file=sys.stderr, flush=True)
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +246,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-max-waters", type=int, default=32)
+    ap.add_argument("--no-large", action="store_true", help="skip the 128-water leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -264,6 +338,13 @@ def main():
             results[prec]["K_tflops"] = round(k_flops / (ms * 1e-3) / 1e12, 2)
             results[prec]["K_frac_of_peak"] = round(k_flops / (ms * 1e-3) / 1e12 / peak, 4)
 
+    del bufs, Cd
+    torch.cuda.empty_cache()
+    large = None
+    if not args.no_large:
+        print("bench: 128-water cluster", file=sys.stderr, flush=True)
+        large = large_bench()
+
     serving = None
     if not args.no_serve:
         print("bench: serving stream", file=sys.stderr, flush=True)
@@ -296,6 +377,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": {k: v for k, v in results.items() if k != "fp64"},
         "serving": serving,
+        "water128": large,
         "fp64_detail": {k: v for k, v in f64.items() if k not in ("E_J", "E_K")},
         "device": torch.cuda.get_device_name(0),
     }

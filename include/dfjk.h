@@ -86,9 +86,12 @@ typedef struct {
                                     (rounded up to 128): the half-transformed
                                     tensor X is formed and contracted one aux
                                     slab at a time, so its memory is
-                                    nao * slab * nocc elements.  0 = automatic
-                                    (one slab while X stays under 48 GB,
-                                    else 1024).                                */
+                                    nao * slab * nocc elements.  0 = automatic:
+                                    the largest multiple of 128 whose
+                                    slab-sized buffers (X, the expanded tensor
+                                    of the density route, the second operand
+                                    of dfjk_build_delta) stay within 48 GB.
+                                    Negative values are DFJK_INVALID.         */
 } dfjk_options;
 
 typedef struct dfjk_plan dfjk_plan;
@@ -184,7 +187,10 @@ typedef enum {
 int dfjk_export(const dfjk_plan *plan, int32_t kind, double *d_out, void *stream);
 
 /* Sampled values of the unwhitened (kind 0) or whitened (kind 1) tensor:
- * d_idx holds n triples (P, mu, nu) in caller order, d_out receives n values. */
+ * d_idx holds n triples (P, mu, nu), d_out receives n values.  mu, nu follow
+ * the caller's AO order; P the caller's aux order for kind 0 and the internal
+ * aux order (dfjk_plan_aux_order) for kind 1.  Pairs that screening dropped
+ * read 0; a triple with an index out of range reads NaN. */
 int dfjk_sample(const dfjk_plan *plan, int32_t kind, int64_t n, const int32_t *d_idx,
                 double *d_out, void *stream);
 

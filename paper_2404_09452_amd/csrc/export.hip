@@ -61,12 +61,16 @@ void launch_export(const Plan &p, int kind, double *out, hipStream_t s)
 
 // Sampled (P, mu, nu) -> value through the dense pair map fmap[mu][nu] = f or -1.
 __global__ void k_sample(const double *__restrict__ T, int64_t ld, const int32_t *__restrict__ fmap,
-                         const int32_t *__restrict__ fn_internal, int64_t nao, int64_t n,
+                         const int32_t *__restrict__ fn_internal, int64_t naux, int64_t nao, int64_t n,
                          const int32_t *__restrict__ idx, double *__restrict__ out)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t Pc = idx[3 * i], mu = idx[3 * i + 1], nu = idx[3 * i + 2];
+    if (Pc < 0 || Pc >= naux || mu < 0 || mu >= nao || nu < 0 || nu >= nao) {
+        out[i] = __builtin_nan("");   // index out of range
+        return;
+    }
     const int32_t f = fmap[(int64_t)mu * nao + nu];
     out[i] = (f < 0) ? 0.0 : T[(int64_t)f * ld + (fn_internal ? fn_internal[Pc] : Pc)];
 }
@@ -76,7 +80,7 @@ void launch_sample(const Plan &p, int kind, int64_t n, const int32_t *idx, doubl
     const double *T = kind == DFJK_EXPORT_INT3C ? p.d.U : p.d.B;
     const int32_t *to_internal = kind == DFJK_EXPORT_INT3C ? p.d.ax_fn_internal : nullptr;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, p.naux_pad, p.d.fmap,
-                       to_internal, p.nao, n, idx, out);
+                       to_internal, p.naux, p.nao, n, idx, out);
 }
 
 }  // namespace dfjk

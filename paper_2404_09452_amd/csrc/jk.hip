@@ -19,6 +19,7 @@ namespace dfjk {
 
 constexpr int kTileK = 128;      // syrk output tile
 constexpr int kCSplitRows = 512; // f rows per partial of c
+constexpr double kAutoSlabBytes = 48e9;  // automatic aux slab: slab-sized K buffers up to this
 
 // ---------------------------------------------------------------------------
 __global__ void k_fill(double *p, int64_t n, double v)
@@ -457,8 +458,15 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.delta = delta;
     // aux slab of the K build: X = nao x slab x ncol elements per operand
     const size_t esz = precision == DFJK_FP64 ? 8 : (precision == DFJK_MIXED_FP32 ? 4 : 2);
-    int64_t slab = p.aux_slab > 0 ? (int64_t)align_up((size_t)p.aux_slab, kPadAux) : p.naux_pad;
-    if (p.aux_slab == 0 && (double)p.nao * p.naux_pad * L.ncol * esz > 48e9) slab = 1024;
+    // automatic: the largest multiple of 128 whose slab-sized buffers (X, its low part,
+    // the expanded B of the density route, the second operand of the increment) stay
+    // within kAutoSlabBytes
+    const double per_aux = (double)p.nao * L.ncol *
+                           ((double)esz + (precision == DFJK_MIXED_BF16X3 ? 2 : 0) + (with_D ? 8 : 0)) *
+                           (delta ? 2 : 1);
+    int64_t slab = p.aux_slab > 0 ? (int64_t)align_up((size_t)p.aux_slab, kPadAux)
+                                  : (int64_t)(kAutoSlabBytes / per_aux) / kPadAux * kPadAux;
+    if (slab < kPadAux) slab = kPadAux;
     if (slab > p.naux_pad) slab = p.naux_pad;
     L.slab = slab;
     L.nslab = (p.naux_pad + slab - 1) / slab;
