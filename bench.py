@@ -14,6 +14,10 @@ The roofline entry is the dominant kernel (the FP64 K contraction, X X^T on
 FP64 MFMA), timed live by HIP events the library records on its own stream.
 The CPU baseline is the FP64 oracle timed on a bounded sample of the same
 job and scaled to builds per second (see cpu_baseline.sample).
+
+Beside the headline line the JSON carries the 128-water cluster (3,840 AO,
+11,136 aux, nocc 640, Schwarz 1e-10, K streamed over aux slabs; `water128`,
+skipped with --no-large) and a continuous-batching serving stream (`serving`).
 """
 import argparse
 import json
@@ -28,6 +32,26 @@ NBUILDS = 10
 PEAK_F64_TFLOPS = 78.6
 PEAK_F32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
+
+
+def committed_traffic():
+    """HBM bytes per launch of the FP64 K kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source changed
+    since those counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_gemm_f64_water32.md")
+    src = os.path.join(ROOT, "paper_2404_09452_amd", "csrc", "gemm_f64.h")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    if not b or not h or h.group(1) != sha:
+        return None
+    return int(b.group(1))
 
 
 def make_inputs(n=32, box=10.0, geom_seed=1, cocc_seed=1):
@@ -247,6 +271,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-max-waters", type=int, default=32)
     ap.add_argument("--no-large", action="store_true", help="skip the 128-water leg")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the 128-water leg and print its JSON (for profiling)")
+    ap.add_argument("--large-builds", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -263,6 +290,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the DF-J/K build would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.only_large:
+        print(json.dumps({"water128": large_bench(args.large_builds)}))
+        return
     import numpy as np
     import torch
     from paper_2404_09452_amd.dfjk import Plan
@@ -330,7 +360,8 @@ def main():
     achieved = k_flops / (k_ms * 1e-3) / 1e12
     roofline = {"kernel": "build.K (FP64 MFMA X X^T, k_gemm_f64<128>)", "bound": "mfma",
                 "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": committed_traffic(),
+                "traffic_source": "profiles/k_gemm_f64_water32.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
                 "flops_per_launch": k_flops, "ms_per_launch": k_ms}
     for prec, peak in (("fp32", PEAK_F32_TFLOPS), ("bf16x3", PEAK_BF16_TFLOPS / 3.0)):
         if prec in results:
@@ -343,7 +374,7 @@ def main():
     large = None
     if not args.no_large:
         print("bench: 128-water cluster", file=sys.stderr, flush=True)
-        large = large_bench()
+        large = large_bench(args.large_builds)
 
     serving = None
     if not args.no_serve:

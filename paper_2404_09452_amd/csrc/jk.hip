@@ -381,14 +381,15 @@ __global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ par
     for (int q = threadIdx.x; q < 16 * kTileK; q += 256) {
         const int row = chunk * 16 + q / kTileK, col = q % kTileK;
         const int64_t m = (int64_t)tm * kTileK + row, n = (int64_t)tn * kTileK + col;
-        if (m >= nao || n >= nao) continue;
+        // the upper half of a diagonal tile is mirrored from its lower half
+        if (m >= nao || n >= nao || n > m) continue;
         const int64_t off = (int64_t)t * kTileK * kTileK + row * kTileK + col;
         double s = 0.0;
         for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t)sp * ntiles * kTileK * kTileK + off];
         s *= scale;
         K[m * nao + n] = s;
         double w = 1.0;
-        if (tm != tn) {
+        if (m != n) {
             K[n * nao + m] = s;
             w = 2.0;
         }
