@@ -167,6 +167,23 @@ int dfjk_build_delta(dfjk_plan *plan, const double *d_C, const double *d_C0, int
                      const double *d_K0, int32_t precision, double *d_J, double *d_K, double *d_E,
                      void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* Open-shell (unrestricted) build, one of the methods the paper lists as
+ * optimised for the GPU (paper, "Accelerated Functionalities", table of
+ * functionalities: unrestricted SCF).  Per spin s (alpha, beta):
+ *   D_s = C_s C_s^T,  K_s = sum_P B_P D_s B_P = X_s X_s^T,
+ * J from D = D_a + D_b, and d_E[2] = {E_J, E_K} with
+ *   E_J = 1/2 Tr(D J),  E_K = -1/2 (Tr(D_a K_a) + Tr(D_b K_b)).
+ * d_Ca: nao x nocc_a, d_Cb: nao x nocc_b (0 <= nocc_b, nocc_a <= nao, at
+ * least one positive; a spin with no electrons may pass NULL and gets K_s = 0).
+ * The K contractions run in `precision`; J and the energies stay FP64.
+ * Outputs d_J, d_Ka, d_Kb: nao x nao, full symmetric.
+ * d_scratch must hold dfjk_build_uks_bytes(plan, nocc_a, nocc_b, precision). */
+int dfjk_build_uks_bytes(const dfjk_plan *plan, int32_t nocc_a, int32_t nocc_b, int32_t precision,
+                         size_t *bytes);
+int dfjk_build_uks(dfjk_plan *plan, const double *d_Ca, int32_t nocc_a, const double *d_Cb,
+                   int32_t nocc_b, int32_t precision, double *d_J, double *d_Ka, double *d_Kb,
+                   double *d_E, void *d_scratch, size_t scratch_bytes, void *stream);
+
 /* Diagnostics for tests (valid after setup).  Dense copies of intermediate
  * quantities in the caller's function order:
  *   DFJK_EXPORT_INT3C   (naux x nao x nao) unwhitened (mu nu|P), screened

@@ -207,6 +207,36 @@ def dfjk(mol, C=None, D=None):
     return jk_from_B(B, C=C, D=D)
 
 
+def uks_from_B(B, Ca, Cb):
+    """Open-shell (unrestricted) J/K from B: per spin D_s = C_s C_s^T and
+    K_s = sum_P B_P D_s B_P; J from D = D_a + D_b; E_J = 1/2 Tr(D J),
+    E_K = -1/2 (Tr D_a K_a + Tr D_b K_b).  The paper lists unrestricted SCF
+    among the GPU-optimised methods (Section "Accelerated Functionalities",
+    table of functionalities); the formulas are the standard spin-unrestricted
+    Coulomb and exchange terms."""
+    naux, nao, _ = B.shape
+    Bm = B.reshape(naux, nao * nao)
+    Ds = [C @ C.T for C in (Ca, Cb)]
+    D = Ds[0] + Ds[1]
+    c = Bm @ D.ravel()
+    J = (c @ Bm).reshape(nao, nao)
+    Ks = []
+    for Dsp in Ds:
+        K = np.zeros((nao, nao))
+        for P in range(naux):
+            K += B[P] @ Dsp @ B[P]
+        Ks.append(K)
+    EJ = 0.5 * float(np.sum(D * J))
+    EK = -0.5 * float(np.sum(Ds[0] * Ks[0]) + np.sum(Ds[1] * Ks[1]))
+    return {"J": J, "Ka": Ks[0], "Kb": Ks[1], "EJ": EJ, "EK": EK}
+
+
+def dfjk_uks(mol, Ca, Cb):
+    """Unrestricted DF-J/K for a molecule (unscreened)."""
+    B, _ = whitened_3c(mol)
+    return uks_from_B(B, Ca, Cb)
+
+
 def exact_jk(mol, D):
     """Exact (non-fitted) J and K from four-centre integrals (tiny systems)."""
     eri = int4c(mol)

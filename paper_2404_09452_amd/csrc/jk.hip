@@ -32,9 +32,9 @@ static void fill(double *p, int64_t n, double v, hipStream_t s)
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
 }
 
-// D = 2 C C^T, one thread per element of a 16x16 output block.
+// D = scale C C^T, one thread per element of a 16x16 output block.
 __global__ __launch_bounds__(256) void k_density(const double *__restrict__ C, int64_t nao, int32_t nocc,
-                                                 double *__restrict__ D)
+                                                 double scale, double *__restrict__ D)
 {
     __shared__ double Ca[16][65], Cb[16][65];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -52,7 +52,14 @@ __global__ __launch_bounds__(256) void k_density(const double *__restrict__ C, i
         for (int c = 0; c < 64; ++c) s += Ca[ty][c] * Cb[tx][c];
         __syncthreads();
     }
-    if (m0 + ty < nao && n0 + tx < nao) D[(m0 + ty) * nao + n0 + tx] = 2.0 * s;
+    if (m0 + ty < nao && n0 + tx < nao) D[(m0 + ty) * nao + n0 + tx] = scale * s;
+}
+
+__global__ void k_add(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+                      double *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + b[i];
 }
 
 __global__ void k_gather_d(const double *__restrict__ D, int64_t nao, const int32_t *__restrict__ fmu,
@@ -405,7 +412,7 @@ __global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ par
 }
 
 __global__ __launch_bounds__(256) void k_energies(const double *__restrict__ c, int64_t naux,
-                                                  const double *__restrict__ Epart, int64_t nEpart,
+                                                  const double *__restrict__ Epart, int64_t nEpart, double fk,
                                                   double *__restrict__ E)
 {
     __shared__ double r1[256], r2[256];
@@ -424,7 +431,7 @@ __global__ __launch_bounds__(256) void k_energies(const double *__restrict__ c, 
     }
     if (threadIdx.x == 0) {
         E[0] = 0.5 * r1[0];
-        E[1] = -0.25 * r2[0];
+        E[1] = fk * r2[0];
     }
 }
 
@@ -533,59 +540,35 @@ static void launch_ht(const Plan &p, int precision, const double *C, int32_t nco
     else launch_halftrans<OUT_BF16X2>(h, p.nao, s);
 }
 
-void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *Din, double *J, double *K,
-                  double *E, char *scratch, hipStream_t s)
+// Steps 5-6 for every aux slab: the half transform of C1 (and of C2 for the
+// increment, which contracts X(C1) with X(C2) over all tiles), then the slab's
+// K contribution into its own split-K partials: lower tiles of X X^T (C route),
+// X B~^T (density route, B~ the expanded tensor) or every tile of X1 X2^T.
+// ncol <= L.ncol columns; slabs reuse the X buffers and the stream orders them.
+static void contract_slabs(Plan &p, const BuildLayout &L, const double *C1, const double *C2, int64_t ncol,
+                           char *scratch, hipStream_t s)
 {
     const int64_t nao = p.nao, ld = p.naux_pad;
-    double *D = reinterpret_cast<double *>(scratch + L.o_D);
-    double *cvec = reinterpret_cast<double *>(scratch + L.o_c);
+    Profiler &pr = p.prof;
     void *X = scratch + L.o_X;
     void *Xlo = L.o_Xlo ? scratch + L.o_Xlo : nullptr;
     double *Bt = L.o_Bfull ? reinterpret_cast<double *>(scratch + L.o_Bfull) : nullptr;
     double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
-    double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
-    Profiler &pr = p.prof;
-    pr.stream = s;
-
-    // 1. density
-    pr.mark(ST_DENSITY, true);
-    if (!L.with_D) {
-        dim3 grid((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16));
-        hipLaunchKernelGGL(k_density, grid, dim3(256), 0, s, C, nao, (int32_t)L.ncol, D);
-    } else {
-        (void)hipMemcpyAsync(D, Din, (size_t)nao * nao * 8, hipMemcpyDeviceToDevice, s);
-    }
-    if (L.delta)
-        hipLaunchKernelGGL(k_uw, dim3((unsigned)((nao * L.ncol + 255) / 256)), dim3(256), 0, s, C, L.C0, nao,
-                           (int32_t)L.ncol, reinterpret_cast<double *>(scratch + L.o_U),
-                           reinterpret_cast<double *>(scratch + L.o_W));
-    pr.mark(ST_DENSITY, false);
-    // 2-4. J (always FP64)
-    pr.mark(ST_J, true);
-    launch_j(p, L, D, J, scratch, s);
-    pr.mark(ST_J, false);
-    // 5-6. per aux slab: half transform(s), then the slab's K contribution into its own
-    // split-K partials (lower tiles of 2 X X^T or X Bt^T; every tile of X_U X_W^T for the
-    // increment). Slabs reuse the X buffers; the stream orders them.
     const bool lower = !L.delta;
     const int ntiles = lower ? L.ntile * (L.ntile + 1) / 2 : L.ntile * L.ntile;
     const size_t slab_part = (size_t)L.nsplit_k * ntiles * kTileK * kTileK;
-    double *U = reinterpret_cast<double *>(scratch + L.o_U), *W = reinterpret_cast<double *>(scratch + L.o_W);
     void *X2 = L.delta ? scratch + L.o_X2 : nullptr;
     void *X2lo = L.o_X2lo ? scratch + L.o_X2lo : nullptr;
     for (int64_t sl = 0; sl < L.nslab; ++sl) {
         const int64_t pb = sl * L.slab, plen = (ld - pb < L.slab) ? ld - pb : L.slab;
-        const int64_t kdim = plen * L.ncol;
+        const int64_t kdim = plen * ncol;
         pr.mark(ST_HALFTRANS, true);
-        if (!L.delta) {
-            launch_ht(p, L.precision, L.with_D ? Din : C, (int32_t)L.ncol, pb, plen, X, Xlo, s);
-            if (L.with_D)
-                hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((plen + 255) / 256), (unsigned)nao), dim3(256), 0,
-                                   s, p.d.B, ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, pb, plen, Bt);
-        } else {
-            launch_ht(p, L.precision, U, (int32_t)L.ncol, pb, plen, X, Xlo, s);
-            launch_ht(p, L.precision, W, (int32_t)L.ncol, pb, plen, X2, X2lo, s);
-        }
+        launch_ht(p, L.precision, C1, (int32_t)ncol, pb, plen, X, Xlo, s);
+        if (L.delta)
+            launch_ht(p, L.precision, C2, (int32_t)ncol, pb, plen, X2, X2lo, s);
+        else if (L.with_D)
+            hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((plen + 255) / 256), (unsigned)nao), dim3(256), 0, s,
+                               p.d.B, ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, pb, plen, Bt);
         pr.mark(ST_HALFTRANS, false);
         pr.mark(ST_K, true);
         const void *Bop = L.delta ? (const void *)X2 : (L.with_D ? (const void *)Bt : (const void *)X);
@@ -605,6 +588,42 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
         }
         pr.mark(ST_K, false);
     }
+}
+
+void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *Din, double *J, double *K,
+                  double *E, char *scratch, hipStream_t s)
+{
+    const int64_t nao = p.nao, ld = p.naux_pad;
+    double *D = reinterpret_cast<double *>(scratch + L.o_D);
+    double *cvec = reinterpret_cast<double *>(scratch + L.o_c);
+    double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
+    double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
+    Profiler &pr = p.prof;
+    pr.stream = s;
+
+    // 1. density
+    pr.mark(ST_DENSITY, true);
+    if (!L.with_D) {
+        dim3 grid((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16));
+        hipLaunchKernelGGL(k_density, grid, dim3(256), 0, s, C, nao, (int32_t)L.ncol, 2.0, D);
+    } else {
+        (void)hipMemcpyAsync(D, Din, (size_t)nao * nao * 8, hipMemcpyDeviceToDevice, s);
+    }
+    if (L.delta)
+        hipLaunchKernelGGL(k_uw, dim3((unsigned)((nao * L.ncol + 255) / 256)), dim3(256), 0, s, C, L.C0, nao,
+                           (int32_t)L.ncol, reinterpret_cast<double *>(scratch + L.o_U),
+                           reinterpret_cast<double *>(scratch + L.o_W));
+    pr.mark(ST_DENSITY, false);
+    // 2-4. J (always FP64)
+    pr.mark(ST_J, true);
+    launch_j(p, L, D, J, scratch, s);
+    pr.mark(ST_J, false);
+    // 5-6. per aux slab: half transform(s) and the slab's K contribution
+    if (!L.delta)
+        contract_slabs(p, L, L.with_D ? Din : C, nullptr, L.ncol, scratch, s);
+    else
+        contract_slabs(p, L, reinterpret_cast<double *>(scratch + L.o_U),
+                       reinterpret_cast<double *>(scratch + L.o_W), L.ncol, scratch, s);
     // 7. split-K sum, mirror, energies
     pr.mark(ST_KREDUCE, true);
     const int nlower = L.ntile * (L.ntile + 1) / 2;
@@ -616,7 +635,76 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
         hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
                            L.ntile, nao,
                            L.with_D ? 1.0 : 2.0, D, K, Epart);
-    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (kTileK / 16), E);
+    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (kTileK / 16), -0.25,
+                       E);
+    pr.mark(ST_KREDUCE, false);
+}
+
+BuildLayout build_layout_uks(const Plan &p, int32_t nocc_a, int32_t nocc_b, int32_t precision)
+{
+    BuildLayout L = build_layout(p, nocc_a > nocc_b ? nocc_a : nocc_b, precision, false);
+    L.uks = true;
+    L.nocc_a = nocc_a;
+    L.nocc_b = nocc_b;
+    size_t off = L.bytes;
+    auto take = [&](size_t bytes) {
+        off = align_up(off, 256);
+        const size_t o = off;
+        off += bytes;
+        return o;
+    };
+    L.o_Da = take((size_t)p.nao * p.nao * 8);
+    L.o_Db = take((size_t)p.nao * p.nao * 8);
+    L.o_Epart = take((size_t)2 * L.ntile * (L.ntile + 1) / 2 * (kTileK / 16) * 8);   // one block per spin
+    L.bytes = align_up(off, 256);
+    return L;
+}
+
+// Open-shell build: D_s = C_s C_s^T for s = alpha, beta; J from D = D_a + D_b;
+// K_s = sum_P B_P D_s B_P = X_s X_s^T; E_J = 1/2 Tr D J = 1/2 sum_P c_P^2,
+// E_K = -1/2 (Tr D_a K_a + Tr D_b K_b).
+void launch_build_uks(Plan &p, const BuildLayout &L, const double *Ca, const double *Cb, double *J, double *Ka,
+                      double *Kb, double *E, char *scratch, hipStream_t s)
+{
+    const int64_t nao = p.nao, ld = p.naux_pad;
+    double *D = reinterpret_cast<double *>(scratch + L.o_D);
+    double *Ds[2] = {reinterpret_cast<double *>(scratch + L.o_Da), reinterpret_cast<double *>(scratch + L.o_Db)};
+    const double *Cs[2] = {Ca, Cb};
+    double *Ks[2] = {Ka, Kb};
+    const int32_t nocc[2] = {L.nocc_a, L.nocc_b};
+    double *cvec = reinterpret_cast<double *>(scratch + L.o_c);
+    double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
+    double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
+    const int nlower = L.ntile * (L.ntile + 1) / 2;
+    const int64_t nep = (int64_t)nlower * (kTileK / 16);
+    Profiler &pr = p.prof;
+    pr.stream = s;
+
+    pr.mark(ST_DENSITY, true);
+    const dim3 grid((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16));
+    for (int sp = 0; sp < 2; ++sp) {
+        if (nocc[sp] > 0) hipLaunchKernelGGL(k_density, grid, dim3(256), 0, s, Cs[sp], nao, nocc[sp], 1.0, Ds[sp]);
+        else fill(Ds[sp], nao * nao, 0.0, s);
+    }
+    hipLaunchKernelGGL(k_add, dim3((unsigned)((nao * nao + 255) / 256)), dim3(256), 0, s, Ds[0], Ds[1], nao * nao, D);
+    pr.mark(ST_DENSITY, false);
+    pr.mark(ST_J, true);
+    launch_j(p, L, D, J, scratch, s);
+    pr.mark(ST_J, false);
+    for (int sp = 0; sp < 2; ++sp) {
+        if (nocc[sp] == 0) {
+            fill(Ks[sp], nao * nao, 0.0, s);
+            fill(Epart + sp * nep, nep, 0.0, s);
+            continue;
+        }
+        contract_slabs(p, L, Cs[sp], nullptr, nocc[sp], scratch, s);
+        pr.mark(ST_KREDUCE, true);
+        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
+                           L.ntile, nao, 1.0, Ds[sp], Ks[sp], Epart + sp * nep);
+        pr.mark(ST_KREDUCE, false);
+    }
+    pr.mark(ST_KREDUCE, true);
+    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, 2 * nep, -0.5, E);
     pr.mark(ST_KREDUCE, false);
 }
 

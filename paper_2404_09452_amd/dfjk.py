@@ -184,6 +184,35 @@ class Plan:
                                         _ptr(J), _ptr(K), _ptr(E), _ptr(scr), scr.numel(), _stream_handle(stream)))
         return J, K, E
 
+    def build_uks(self, Ca, Cb, precision="fp64", out=None, stream=None):
+        """Open-shell build: J (from D_a + D_b), K_a, K_b and E = [E_J, E_K] with
+        D_s = C_s C_s^T; Cb (or Ca) may have zero columns."""
+        dev = torch.device("cuda")
+        Cs = []
+        for C in (Ca, Cb):
+            C = torch.as_tensor(C, dtype=torch.float64, device=dev).contiguous()
+            if C.dim() != 2 or C.shape[0] != self.nao:
+                raise ValueError("C_a and C_b must be (nao, nocc_s)")
+            Cs.append(C)
+        na, nb = Cs[0].shape[1], Cs[1].shape[1]
+        if out is None:
+            J = torch.empty((self.nao, self.nao), dtype=torch.float64, device=dev)
+            Ka, Kb = torch.empty_like(J), torch.empty_like(J)
+            E = torch.empty(2, dtype=torch.float64, device=dev)
+        else:
+            J, Ka, Kb, E = out
+        key = ("uks", int(na), int(nb), precision)
+        if key not in self._scratch:
+            n = ctypes.c_size_t()
+            _check(N.lib().dfjk_build_uks_bytes(self._h, int(na), int(nb), PRECISION[precision], ctypes.byref(n)))
+            self._scratch[key] = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        scr = self._scratch[key]
+        _check(N.lib().dfjk_build_uks(self._h, _ptr(Cs[0]) if na else ctypes.c_void_p(0), int(na),
+                                      _ptr(Cs[1]) if nb else ctypes.c_void_p(0), int(nb), PRECISION[precision],
+                                      _ptr(J), _ptr(Ka), _ptr(Kb), _ptr(E), _ptr(scr), scr.numel(),
+                                      _stream_handle(stream)))
+        return J, Ka, Kb, E
+
     # -- diagnostics -------------------------------------------------------
     NSTAGES = 10
 

@@ -211,3 +211,67 @@ def test_aux_slabs_match_one_slab(cluster5, slab):
     _, Kd, Ed = (t.cpu().numpy() for t in plan.build_delta(C1, d["C"], K0, precision="fp64"))
     _, Kr, Er = (t.cpu().numpy() for t in d["one"].build(C=C1))
     assert rel(Kd, Kr) <= 1e-12
+
+
+@pytest.mark.parametrize("n,nb", [(1, 4), (1, 0), (3, 14)])
+def test_uks_against_oracle(n, nb):
+    """Open-shell build: alpha = the occupied orbitals, beta = nb columns of a
+    second orthonormal set (0: no beta electrons)."""
+    mol, S, Ca = case(n)
+    Cb = W.occupied_orbitals(S, max(nb, 1), 99 + n)[:, :nb]
+    ref = oracle.dfjk_uks(mol, Ca, Cb)
+    plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
+    J, Ka, Kb, E = (t.cpu().numpy() for t in plan.build_uks(Ca, Cb))
+    assert rel(J, ref["J"]) <= 1e-10
+    assert rel(Ka, ref["Ka"]) <= 1e-10
+    if nb:
+        assert rel(Kb, ref["Kb"]) <= 1e-10
+    else:
+        assert np.all(Kb == 0.0)
+    assert abs(E[0] - ref["EJ"]) <= 1e-10 * abs(ref["EJ"])
+    assert abs(E[1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
+    # mixed-precision exchange, FP64 J
+    J32, Ka32, Kb32, E32 = (t.cpu().numpy() for t in plan.build_uks(Ca, Cb, precision="fp32"))
+    assert np.array_equal(J32, J) and E32[0] == E[0]
+    assert abs(E32[1] - E[1]) <= 1e-5 * abs(E[1])
+
+
+def test_uks_closed_shell_matches_rks(cluster5):
+    d = cluster5
+    J, Ka, Kb, E = (t.cpu().numpy() for t in d["one"].build_uks(d["C"], d["C"]))
+    J1, K1, E1 = d["base"]
+    assert np.array_equal(Ka, Kb)
+    assert rel(2.0 * Ka, K1) <= 1e-13
+    assert rel(J, J1) <= 1e-13
+    assert abs(E[1] - E1[1]) <= 1e-13 * abs(E1[1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_build_replays_in_a_hip_graph(cluster3_seq, prec):
+    """A whole build captured once in a HIP graph and replayed with new orbitals
+    written into the captured input: every replay equals an eager build bitwise
+    (eager builds and synchronisations run between the replays)."""
+    d = cluster3_seq
+    plan = d["plan"]
+    C0 = torch.as_tensor(d["C0"], device="cuda")
+    C1 = torch.as_tensor(d["C1"], device="cuda")
+    nao, nocc = C0.shape
+    Cbuf = C0.clone()
+    out = (torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+           torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+           torch.empty(2, dtype=torch.float64, device="cuda"))
+    plan.build(C=Cbuf, precision=prec, out=out)           # scratch allocated outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.build(C=Cbuf, precision=prec, out=out)
+    torch.cuda.synchronize()
+    for C in (C1, C0, C1, C1):
+        Cbuf.copy_(C)
+        g.replay()
+        torch.cuda.synchronize()
+        got = [t.cpu().numpy().copy() for t in out]
+        ref = [t.cpu().numpy() for t in plan.build(C=C, precision=prec)]
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)

@@ -370,3 +370,58 @@ def test_far_dimer_exchange_approaches_additivity():
         diffs.append(abs(oracle.dfjk(dim, C=C)["EK"] - 2 * EK1))
     assert diffs[0] > diffs[1] > diffs[2]
     assert diffs[2] < 1e-3 * abs(EK1)
+
+
+# --------------------------------------------------------------------------
+# Open shell (unrestricted)
+
+def test_uks_closed_shell_reduction(water):
+    """C_a = C_b = C gives the closed-shell result: K_a = K_b = K / 2, same J and energies."""
+    mol, _, C = water
+    B, _ = oracle.whitened_3c(mol)
+    r = oracle.jk_from_B(B, C=C)
+    u = oracle.uks_from_B(B, C, C)
+    s = np.abs(r["K"]).max()
+    assert np.abs(u["J"] - r["J"]).max() <= 1e-13 * np.abs(r["J"]).max()
+    assert np.abs(u["Ka"] - 0.5 * r["K"]).max() <= 1e-13 * s
+    assert np.abs(u["Kb"] - 0.5 * r["K"]).max() <= 1e-13 * s
+    assert abs(u["EJ"] - r["EJ"]) <= 1e-13 * abs(r["EJ"])
+    assert abs(u["EK"] - r["EK"]) <= 1e-13 * abs(r["EK"])
+
+
+def test_uks_one_electron_has_no_self_interaction(water):
+    """One electron (one alpha orbital, no beta): E_J + E_K = 0, as Coulomb and
+    exchange of a single orbital density cancel term by term in P."""
+    mol, _, C = water
+    B, _ = oracle.whitened_3c(mol)
+    u = oracle.uks_from_B(B, C[:, :1], C[:, :0])
+    assert u["EJ"] > 0
+    assert abs(u["EJ"] + u["EK"]) <= 1e-13 * u["EJ"]
+    assert np.all(u["Kb"] == 0.0)
+
+
+def test_uks_exact_two_centre_against_brute_force():
+    """With an aux set spanning every AO product, each spin's K equals the exact
+    four-centre exchange of its own density (brute-force (ss|ss))."""
+    A, Bc = np.array([0.0, 0.0, 0.0]), np.array([0.4, -0.3, 0.5])
+    a, b = 0.9, 1.6
+    P = (a * A + b * Bc) / (a + b)
+    mol = _mol([(0, 0, a), (1, 0, b)], [(0, 0, 2 * a), (1, 0, 2 * b), (2, 0, a + b)], [A, Bc, P])
+    rng = np.random.default_rng(5)
+    Ca, Cb = rng.standard_normal((2, 2)), rng.standard_normal((2, 1))
+    u = oracle.dfjk_uks(mol, Ca, Cb)
+    cen, ex = [A, Bc], [a, b]
+    eri = np.zeros((2, 2, 2, 2))
+    for i in range(2):
+        for j in range(2):
+            for k in range(2):
+                for l in range(2):
+                    eri[i, j, k, l] = brute.ssss(ex[i], cen[i], ex[j], cen[j], ex[k], cen[k], ex[l], cen[l])
+    Da, Db = Ca @ Ca.T, Cb @ Cb.T
+    J = np.einsum("ijkl,kl->ij", eri, Da + Db)
+    Ka, Kb = np.einsum("ikjl,kl->ij", eri, Da), np.einsum("ikjl,kl->ij", eri, Db)
+    assert np.abs(u["J"] - J).max() <= 1e-12 * np.abs(J).max()
+    assert np.abs(u["Ka"] - Ka).max() <= 1e-12 * np.abs(Ka).max()
+    assert np.abs(u["Kb"] - Kb).max() <= 1e-12 * np.abs(Kb).max()
+    EK = -0.5 * (np.sum(Da * Ka) + np.sum(Db * Kb))
+    assert abs(u["EK"] - EK) <= 1e-12 * abs(EK)
