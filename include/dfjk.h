@@ -167,6 +167,25 @@ int dfjk_build_delta(dfjk_plan *plan, const double *d_C, const double *d_C0, int
                      const double *d_K0, int32_t precision, double *d_J, double *d_K, double *d_E,
                      void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* A batch of n closed-shell builds (molecules of any sizes, each with its own
+ * set-up plan, all on the current device) on one stream: the same results as
+ * n dfjk_build calls with d_C[i] (nao_i x nocc[i]), up to the order of the
+ * split-K sums, but the K contractions of all FP64 molecules whose
+ * half-transformed tensor fits one aux slab share one grouped launch (16
+ * molecules per launch), with split counts chosen together to fill the chip,
+ * and the split-K reductions and energies run as grouped launches too.  This
+ * is the serving form for many small molecules, where per-launch overhead
+ * dominates.  plans, d_C, nocc, d_J, d_K, d_E are host arrays of n entries;
+ * outputs as for dfjk_build.  d_scratch must hold dfjk_build_batch_bytes
+ * (per-molecule regions, 256-byte aligned, in order).  No host
+ * synchronisation; safe to capture in a HIP graph.  A plan may appear more
+ * than once. */
+int dfjk_build_batch_bytes(int32_t n, dfjk_plan *const *plans, const int32_t *nocc, int32_t precision,
+                           size_t *bytes);
+int dfjk_build_batch(int32_t n, dfjk_plan *const *plans, const double *const *d_C, const int32_t *nocc,
+                     int32_t precision, double *const *d_J, double *const *d_K, double *const *d_E,
+                     void *d_scratch, size_t scratch_bytes, void *stream);
+
 /* Open-shell (unrestricted) build, one of the methods the paper lists as
  * optimised for the GPU (paper, "Accelerated Functionalities", table of
  * functionalities: unrestricted SCF).  Per spin s (alpha, beta):

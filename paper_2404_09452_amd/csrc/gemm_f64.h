@@ -61,10 +61,9 @@ __device__ __forceinline__ void tile_coords(const GemmArgs &g, int t, int &tm, i
     }
 }
 
-// waves_per_eu 4: at most 128 VGPRs, so two 8-wave workgroups share a CU.
+// One output tile (tile, split) of the GEMM g, computed by the calling workgroup.
 template <int T, int WGM, int WGN, bool NN>
-__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(4)))
-void k_gemm_f64(GemmArgs g)
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, const int tile, const int split)
 {
     constexpr int NT = 64 * WGM * WGN;                 // threads
     constexpr int KC = kGemmKC, LDS_K = KC + 1;        // padded k stride in LDS
@@ -76,7 +75,6 @@ void k_gemm_f64(GemmArgs g)
     __shared__ double Bs[2][T * LDS_K];
 
     const int ntiles_all = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntn;
-    const int tile = blockIdx.x, split = blockIdx.y;
     int tm, tn;
     tile_coords(g, tile, tm, tn);
     const int64_t m0 = (int64_t)tm * T, n0 = (int64_t)tn * T;
@@ -205,6 +203,38 @@ void k_gemm_f64(GemmArgs g)
             }
 }
 
+// waves_per_eu 4: at most 128 VGPRs, so two 8-wave workgroups share a CU.
+template <int T, int WGM, int WGN, bool NN>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(4)))
+void k_gemm_f64(GemmArgs g)
+{
+    gemm_tile<T, WGM, WGN, NN>(g, blockIdx.x, blockIdx.y);
+}
+
+// Grouped form: up to kGemmGroupMax independent GEMMs (one per molecule of a
+// batch) in one launch.  Workgroup b belongs to GEMM p with
+// wg_start[p] <= b < wg_start[p + 1] and takes its (tile, split) from the
+// local index, tiles fastest.  The descriptors travel by value in the kernel
+// arguments, so the launch needs no device-side table (and can be captured).
+constexpr int kGemmGroupMax = 16;
+struct GemmGroup {
+    int32_t n;
+    int32_t wg_start[kGemmGroupMax + 1];
+    int32_t ntiles[kGemmGroupMax];
+    GemmArgs g[kGemmGroupMax];
+};
+
+template <int T, int WGM, int WGN, bool NN>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(4)))
+void k_gemm_f64_grouped(GemmGroup grp)
+{
+    const int b = blockIdx.x;
+    int p = 0;
+    while (p + 1 < grp.n && b >= grp.wg_start[p + 1]) ++p;
+    const int local = b - grp.wg_start[p];
+    gemm_tile<T, WGM, WGN, NN>(grp.g[p], local % grp.ntiles[p], local / grp.ntiles[p]);
+}
+
 // T = 128 uses eight waves (4 x 2, 32x64 per wave) to keep four waves per
 // SIMD resident; T = 64 uses four waves (2 x 2).
 template <int T, bool NN>
@@ -218,6 +248,31 @@ inline void gemm_f64(GemmArgs g, int nsplit, hipStream_t s)
         hipLaunchKernelGGL((k_gemm_f64<128, 4, 2, NN>), dim3(ntiles, nsplit), dim3(512), 0, s, g);
     else
         hipLaunchKernelGGL((k_gemm_f64<64, 2, 2, NN>), dim3(ntiles, nsplit), dim3(256), 0, s, g);
+}
+
+// n GEMMs with 128-wide tiles (NT operand order), gs[i] split nsplit[i] ways
+// into its partial buffer, in launches of at most kGemmGroupMax GEMMs.
+inline void gemm_f64_grouped(const GemmArgs *gs, const int *nsplit, int n, hipStream_t s)
+{
+    for (int first = 0; first < n; first += kGemmGroupMax) {
+        GemmGroup grp{};
+        grp.n = 0;
+        int total = 0;
+        for (int i = first; i < n && grp.n < kGemmGroupMax; ++i) {
+            GemmArgs g = gs[i];
+            g.ntm = (int)((g.M + 127) / 128);
+            g.ntn = (int)((g.N + 127) / 128);
+            const int nt = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntn;
+            grp.g[grp.n] = g;
+            grp.ntiles[grp.n] = nt;
+            grp.wg_start[grp.n] = total;
+            total += nt * nsplit[i];
+            ++grp.n;
+        }
+        grp.wg_start[grp.n] = total;
+        if (total > 0)
+            hipLaunchKernelGGL((k_gemm_f64_grouped<128, 4, 2, false>), dim3(total), dim3(512), 0, s, grp);
+    }
 }
 
 }  // namespace dfjk

@@ -372,18 +372,16 @@ __global__ __launch_bounds__(256) void k_k_reduce_delta(const double *__restrict
 // Split-K reduction of the K tiles: K[m][n] = scale * sum_s partial[s][t][..]
 // in a fixed order, mirrored for off-diagonal tiles, plus per-block partial
 // sums of D[m][n] K[m][n] (weight 2 off the diagonal tiles) for E_K.
-__global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ part, int nsplit, int ntm,
-                                                  int64_t nao, double scale, const double *__restrict__ D,
-                                                  double *__restrict__ K, double *__restrict__ Epart)
+__device__ __forceinline__ void reduce_tile(const double *__restrict__ part, int nsplit, int ntm, int64_t nao,
+                                            double scale, const double *__restrict__ D, double *__restrict__ K,
+                                            double *__restrict__ Epart, const int t, const int chunk)
 {
     __shared__ double red[256];
-    const int t = blockIdx.x;
     const int ntiles = ntm * (ntm + 1) / 2;
     int tm = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (tm * (tm + 1) / 2 > t) --tm;
     while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
     const int tn = t - tm * (tm + 1) / 2;
-    const int chunk = blockIdx.y;   // 16 rows of the tile per block
     double e = 0.0;
     for (int q = threadIdx.x; q < 16 * kTileK; q += 256) {
         const int row = chunk * 16 + q / kTileK, col = q % kTileK;
@@ -408,12 +406,41 @@ __global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ par
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) Epart[(int64_t)t * gridDim.y + chunk] = red[0];
+    if (threadIdx.x == 0) Epart[(int64_t)t * (kTileK / 16) + chunk] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_energies(const double *__restrict__ c, int64_t naux,
-                                                  const double *__restrict__ Epart, int64_t nEpart, double fk,
-                                                  double *__restrict__ E)
+// block (t, chunk): lower tile t, rows 16 chunk .. 16 chunk + 15
+__global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ part, int nsplit, int ntm,
+                                                  int64_t nao, double scale, const double *__restrict__ D,
+                                                  double *__restrict__ K, double *__restrict__ Epart)
+{
+    reduce_tile(part, nsplit, ntm, nao, scale, D, K, Epart, blockIdx.x, blockIdx.y);
+}
+
+// Grouped reduction for a batch: blocks blk_start[p] .. blk_start[p+1]-1 (times
+// kTileK / 16 chunks in y) reduce molecule p.  Descriptors by value.
+constexpr int kReduceGroupMax = 16;
+struct ReduceGroup {
+    int32_t n;
+    int32_t blk_start[kReduceGroupMax + 1];
+    int32_t nsplit[kReduceGroupMax], ntm[kReduceGroupMax];
+    int64_t nao[kReduceGroupMax];
+    const double *part[kReduceGroupMax], *D[kReduceGroupMax];
+    double *K[kReduceGroupMax], *Epart[kReduceGroupMax];
+};
+
+__global__ __launch_bounds__(256) void k_k_reduce_grouped(ReduceGroup grp, double scale)
+{
+    const int b = blockIdx.x;
+    int p = 0;
+    while (p + 1 < grp.n && b >= grp.blk_start[p + 1]) ++p;
+    reduce_tile(grp.part[p], grp.nsplit[p], grp.ntm[p], grp.nao[p], scale, grp.D[p], grp.K[p], grp.Epart[p],
+                b - grp.blk_start[p], blockIdx.y);
+}
+
+__device__ __forceinline__ void energies_body(const double *__restrict__ c, int64_t naux,
+                                              const double *__restrict__ Epart, int64_t nEpart, double fk,
+                                              double *__restrict__ E)
 {
     __shared__ double r1[256], r2[256];
     double a = 0.0, b = 0.0;
@@ -435,6 +462,27 @@ __global__ __launch_bounds__(256) void k_energies(const double *__restrict__ c, 
     }
 }
 
+__global__ __launch_bounds__(256) void k_energies(const double *__restrict__ c, int64_t naux,
+                                                  const double *__restrict__ Epart, int64_t nEpart, double fk,
+                                                  double *__restrict__ E)
+{
+    energies_body(c, naux, Epart, nEpart, fk, E);
+}
+
+// one block per molecule of a batch
+constexpr int kEnergyGroupMax = 64;
+struct EnergyGroup {
+    const double *c[kEnergyGroupMax], *Epart[kEnergyGroupMax];
+    int64_t naux[kEnergyGroupMax], nEpart[kEnergyGroupMax];
+    double *E[kEnergyGroupMax];
+};
+
+__global__ __launch_bounds__(256) void k_energies_grouped(EnergyGroup grp, double fk)
+{
+    const int p = blockIdx.x;
+    energies_body(grp.c[p], grp.naux[p], grp.Epart[p], grp.nEpart[p], fk, grp.E[p]);
+}
+
 // ---------------------------------------------------------------------------
 
 // Split-K count for the K contraction: the largest count whose workgroups
@@ -452,7 +500,7 @@ static int choose_ksplit(int ntiles, int64_t kdim, int num_cus)
     return ns;
 }
 
-BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta)
+BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta, int nsplit)
 {
     BuildLayout L{};
     L.nao = p.nao;
@@ -482,6 +530,10 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
     L.nsplit_k = (precision == DFJK_FP64) ? choose_ksplit(ntiles, L.kdim, p.num_cus)
                                           : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
+    if (nsplit > 0) {   // a batch chooses the split count for all its molecules together
+        const int64_t maxs = L.kdim / 256 > 0 ? L.kdim / 256 : 1;
+        L.nsplit_k = nsplit < maxs ? nsplit : (int)maxs;
+    }
     size_t off = 0;
     auto take = [&](size_t bytes) {
         off = align_up(off, 256);
@@ -706,6 +758,95 @@ void launch_build_uks(Plan &p, const BuildLayout &L, const double *Ca, const dou
     pr.mark(ST_KREDUCE, true);
     hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, 2 * nep, -0.5, E);
     pr.mark(ST_KREDUCE, false);
+}
+
+// Split count shared by the molecules of a batch: enough workgroups over all
+// their lower K tiles to fill one round of the chip.
+int batch_nsplit(const Plan *const *plans, int n)
+{
+    int tiles = 0, cus = 256;
+    for (int i = 0; i < n; ++i) {
+        const int nt = (int)((plans[i]->nao + kTileK - 1) / kTileK);
+        tiles += nt * (nt + 1) / 2;
+        cus = plans[i]->num_cus;
+    }
+    return choose_ksplit(tiles > 0 ? tiles : 1, (int64_t)1 << 40, cus);
+}
+
+// A batch of closed-shell builds on one stream.  Per molecule: density, J and
+// the half transform; then one grouped FP64 K launch over every molecule
+// whose X fits one slab, one grouped split-K reduction and one grouped energy
+// launch.  Mixed precision and multi-slab molecules contract on their own.
+void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const double *const *C, double *const *J,
+                        double *const *K, double *const *E, char *const *scratch, hipStream_t s)
+{
+    std::vector<GemmArgs> gs;
+    std::vector<int> ns;
+    for (int i = 0; i < n; ++i) {
+        Plan &p = *plans[i];
+        const BuildLayout &L = Ls[i];
+        char *sc = scratch[i];
+        const int64_t nao = p.nao;
+        double *D = reinterpret_cast<double *>(sc + L.o_D);
+        p.prof.stream = s;
+        p.prof.mark(ST_DENSITY, true);
+        hipLaunchKernelGGL(k_density, dim3((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16)), dim3(256), 0,
+                           s, C[i], nao, (int32_t)L.ncol, 2.0, D);
+        p.prof.mark(ST_DENSITY, false);
+        p.prof.mark(ST_J, true);
+        launch_j(p, L, D, J[i], sc, s);
+        p.prof.mark(ST_J, false);
+        if (L.nslab == 1 && L.precision == DFJK_FP64) {
+            p.prof.mark(ST_HALFTRANS, true);
+            launch_ht(p, DFJK_FP64, C[i], (int32_t)L.ncol, 0, p.naux_pad, sc + L.o_X, nullptr, s);
+            p.prof.mark(ST_HALFTRANS, false);
+            GemmArgs g{};
+            g.A = reinterpret_cast<const double *>(sc + L.o_X); g.lda = L.kdim;
+            g.B = g.A; g.ldb = L.kdim;
+            g.M = g.N = nao;
+            g.k_begin = 0; g.k_end = L.kdim;
+            g.ksplit = align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
+            g.alpha = 1.0; g.lower = 1;
+            g.partial = reinterpret_cast<double *>(sc + L.o_Kpart);
+            gs.push_back(g);
+            ns.push_back(L.nsplit_k);
+        } else {
+            contract_slabs(p, L, C[i], nullptr, L.ncol, sc, s);
+        }
+    }
+    gemm_f64_grouped(gs.data(), ns.data(), (int)gs.size(), s);
+    for (int first = 0; first < n; first += kReduceGroupMax) {
+        ReduceGroup grp{};
+        int total = 0;
+        for (int i = first; i < n && grp.n < kReduceGroupMax; ++i) {
+            const BuildLayout &L = Ls[i];
+            const int q = grp.n++;
+            grp.blk_start[q] = total;
+            grp.nsplit[q] = (int32_t)(L.nslab * L.nsplit_k);
+            grp.ntm[q] = L.ntile;
+            grp.nao[q] = L.nao;
+            grp.part[q] = reinterpret_cast<const double *>(scratch[i] + L.o_Kpart);
+            grp.D[q] = reinterpret_cast<const double *>(scratch[i] + L.o_D);
+            grp.K[q] = K[i];
+            grp.Epart[q] = reinterpret_cast<double *>(scratch[i] + L.o_Epart);
+            total += L.ntile * (L.ntile + 1) / 2;
+        }
+        grp.blk_start[grp.n] = total;
+        hipLaunchKernelGGL(k_k_reduce_grouped, dim3(total, kTileK / 16), dim3(256), 0, s, grp, 2.0);
+    }
+    for (int first = 0; first < n; first += kEnergyGroupMax) {
+        EnergyGroup grp{};
+        int m = 0;
+        for (int i = first; i < n && m < kEnergyGroupMax; ++i, ++m) {
+            const BuildLayout &L = Ls[i];
+            grp.c[m] = reinterpret_cast<const double *>(scratch[i] + L.o_c);
+            grp.naux[m] = L.naux_pad;
+            grp.Epart[m] = reinterpret_cast<const double *>(scratch[i] + L.o_Epart);
+            grp.nEpart[m] = (int64_t)L.ntile * (L.ntile + 1) / 2 * (kTileK / 16);
+            grp.E[m] = E[i];
+        }
+        hipLaunchKernelGGL(k_energies_grouped, dim3(m), dim3(256), 0, s, grp, -0.25);
+    }
 }
 
 }  // namespace dfjk

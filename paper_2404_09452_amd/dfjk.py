@@ -258,6 +258,45 @@ class Plan:
             pass
 
 
+class Batch:
+    """Closed-shell builds of several set-up plans in one dfjk_build_batch call:
+    grouped K, reduction and energy launches across the molecules.  The scratch
+    is kept for the same (plans, nocc, precision)."""
+
+    def __init__(self, plans, noccs, precision="fp64"):
+        self.plans = list(plans)
+        self.noccs = [int(n) for n in noccs]
+        self.precision = precision
+        n = len(self.plans)
+        self._h = (ctypes.c_void_p * n)(*[p._h.value for p in self.plans])
+        self._nocc = (ctypes.c_int32 * n)(*self.noccs)
+        nb = ctypes.c_size_t()
+        _check(N.lib().dfjk_build_batch_bytes(n, self._h, self._nocc, PRECISION[precision], ctypes.byref(nb)))
+        self.scratch = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
+
+    def build(self, Cs, outs=None, stream=None):
+        """Cs: list of (nao_i, nocc_i) orbitals; returns [(J, K, E), ...]."""
+        dev = torch.device("cuda")
+        n = len(self.plans)
+        if len(Cs) != n:
+            raise ValueError("one C per plan")
+        Cs = [torch.as_tensor(C, dtype=torch.float64, device=dev).contiguous() for C in Cs]
+        for C, p, k in zip(Cs, self.plans, self.noccs):
+            if tuple(C.shape) != (p.nao, k):
+                raise ValueError("C must be (nao, nocc) of its plan")
+        if outs is None:
+            outs = []
+            for p in self.plans:
+                J = torch.empty((p.nao, p.nao), dtype=torch.float64, device=dev)
+                outs.append((J, torch.empty_like(J), torch.empty(2, dtype=torch.float64, device=dev)))
+        arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])   # noqa: E731
+        _check(N.lib().dfjk_build_batch(n, self._h, arr(Cs), self._nocc, PRECISION[self.precision],
+                                        arr([o[0] for o in outs]), arr([o[1] for o in outs]),
+                                        arr([o[2] for o in outs]), _ptr(self.scratch), self.scratch.numel(),
+                                        _stream_handle(stream)))
+        return outs
+
+
 def boys(mmax, T, stream=None):
     """F_0..F_mmax at the points T (CUDA float64 tensor) with the device routine."""
     T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()

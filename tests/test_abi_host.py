@@ -97,6 +97,10 @@ def test_call_order_is_enforced_without_device():
                               ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(8), ctypes.c_void_p(8),
                               1 << 20, None) == 7
     assert lib.dfjk_build_uks_bytes(plan._h, 3, 2, 0, ctypes.byref(n)) == 7
+    hs = (ctypes.c_void_p * 1)(plan._h.value)
+    nocc = (ctypes.c_int32 * 1)(5)
+    assert lib.dfjk_build_batch_bytes(1, hs, nocc, 0, ctypes.byref(n)) == 7     # not screened
+    assert lib.dfjk_build_batch_bytes(0, hs, nocc, 0, ctypes.byref(n)) == 1     # empty batch
     ms = np.zeros(10)
     cnt = np.zeros(10, dtype=np.int32)
     assert lib.dfjk_profile(plan._h, 1) == 0

@@ -275,3 +275,60 @@ def test_build_replays_in_a_hip_graph(cluster3_seq, prec):
         torch.cuda.synchronize()
         for a, b in zip(got, ref):
             assert np.array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def batch_set():
+    cases = [case(1), case(2), case(3), case(5)]
+    plans = [G.Plan.from_molecule(m, schwarz_thresh=TAU).screen().setup() for m, _, _ in cases]
+    # the monomer appears twice, with two different orbital sets
+    S1 = cases[0][1]
+    cases.append((cases[0][0], S1, W.occupied_orbitals(S1, 5, 1234)))
+    plans.append(plans[0])
+    return cases, plans
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_batch_matches_single_builds(batch_set, prec):
+    cases, plans = batch_set
+    Cs = [C for _, _, C in cases]
+    batch = G.Batch(plans, [C.shape[1] for C in Cs], precision=prec)
+    outs = batch.build(Cs)
+    torch.cuda.synchronize()
+    for (mol, _, C), plan, (J, K, E) in zip(cases, plans, outs):
+        J1, K1, E1 = (t.cpu().numpy() for t in plan.build(C=C, precision=prec))
+        J, K, E = J.cpu().numpy(), K.cpu().numpy(), E.cpu().numpy()
+        assert np.array_equal(J, J1) and E[0] == E1[0]
+        if prec == "fp64":
+            # only the split-K summation order differs from the single build
+            assert rel(K, K1) <= 1e-13
+            assert abs(E[1] - E1[1]) <= 1e-13 * abs(E1[1])
+        else:
+            assert np.array_equal(K, K1) and E[1] == E1[1]
+    if prec == "fp64":   # one molecule against the oracle
+        mol, _, C = cases[2]
+        ref = oracle.dfjk(mol, C=C)
+        assert rel(outs[2][1].cpu().numpy(), ref["K"]) <= 1e-10
+
+
+def test_batch_replays_in_a_hip_graph(batch_set):
+    cases, plans = batch_set
+    Cs = [torch.as_tensor(C, device="cuda") for _, _, C in cases]
+    bufs = [C.clone() for C in Cs]
+    batch = G.Batch(plans, [C.shape[1] for C in Cs])
+    outs = batch.build(bufs)
+    torch.cuda.synchronize()
+    ref = [[t.cpu().numpy().copy() for t in o] for o in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.build(bufs, outs=outs)
+    for rep in range(3):
+        for o in outs:
+            for t in o:
+                t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            for t, x in zip(o, r):
+                assert np.array_equal(t.cpu().numpy(), x)
