@@ -136,17 +136,19 @@ def cpu_baseline(mol, Cs, target_s=20.0):
     }
 
 
-def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6):
+def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, loads=(0.8,)):
     """Continuous-batching serving of water clusters of 1..nmax molecules
     (NBUILDS SCF-like builds each): a closed-loop run (every request queued at
-    t = 0) gives the saturation rate mu; then a seeded Poisson stream at
-    0.8 mu gives p50/p99 latency.  One molecule per size (geometry seed
-    10000 + n, box for the water32 density) serves every request of that size."""
+    t = 0) gives the saturation rate mu; then seeded Poisson streams at
+    load x mu for each load give p50/p99 latency.  One molecule per size
+    (geometry seed 10000 + n, box for the water32 density) serves every
+    request of that size.  A mode is a precision ("fp64", "bf16x3_incr", ...),
+    with "+batched" for the step-batched executor (grouped launches)."""
     import numpy as np
     import torch
 
     import workload as W
-    from paper_2404_09452_amd.serve import GpuExecutor, Request, Server, summarize
+    from paper_2404_09452_amd.serve import BatchedGpuExecutor, GpuExecutor, Request, Server, summarize
     _, sizes = W.poisson_stream(nreq, 1.0, seed, 1, nmax)
     pool = {}
     for n in sorted(set(int(s) for s in sizes)):
@@ -155,35 +157,53 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6):
         S = W.overlap_by_quadrature(mol)
         C0 = W.occupied_orbitals(S, mol.nelec // 2, n)
         pool[n] = (mol, [W.perturbed_orbitals(C0, S, k, eps=1e-2, seed=1000) for k in range(NBUILDS)])
+    # Cap torch's caching allocator below the device size: cached blocks of
+    # finished molecules of other sizes would otherwise fill HBM and leave the
+    # runtime no room for its own allocations (spill scratch per queue).
+    torch.cuda.set_per_process_memory_fraction(0.85)
     free, _ = torch.cuda.mem_get_info()
     budget = int(budget_frac * free)
     out = {"requests": nreq, "sizes": "uniform 1..%d waters" % nmax, "builds_per_request": NBUILDS,
            "max_active": max_active, "hbm_budget_GB": round(budget / 1e9, 1)}
     for mode in modes:
+        prec, batched = mode.split("+")[0], mode.endswith("+batched")
+
         def reqs(arrivals):
             return [Request(rid=i, mol=pool[int(n)][0], orbitals=pool[int(n)][1], arrival=float(a),
-                            precision=mode) for i, (n, a) in enumerate(zip(sizes, arrivals))]
-        srv = Server(GpuExecutor(keep_results=False), max_active=max_active, hbm_budget_bytes=budget)
+                            precision=prec) for i, (n, a) in enumerate(zip(sizes, arrivals))]
+
+        def executor():
+            return BatchedGpuExecutor(keep_results=False) if batched else GpuExecutor(keep_results=False)
+        srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget)
         t0 = time.perf_counter()
         closed = srv.serve(reqs(np.zeros(nreq)))
         wall = time.perf_counter() - t0
         sat = summarize(closed, wall)
         mu = nreq / wall
-        arr, _ = W.poisson_stream(nreq, 0.8 * mu, seed, 1, nmax)
-        srv = Server(GpuExecutor(keep_results=False), max_active=max_active, hbm_budget_bytes=budget)
-        t0 = time.perf_counter()
-        done = srv.serve(reqs(arr))
-        wall = time.perf_counter() - t0
-        st = summarize(done, wall)
-        out[mode] = {"saturation_requests_per_s": round(mu, 3),
-                     "saturation_builds_per_s": round(sat["builds_per_s"], 2),
-                     "poisson_rate_per_s": round(0.8 * mu, 3),
-                     "builds_per_s": round(st["builds_per_s"], 2),
-                     "p50_latency_s": round(st["p50_latency_s"], 4),
-                     "p99_latency_s": round(st["p99_latency_s"], 4),
-                     "failed": st["failed"], "peak_active": srv.peak_active}
-        print("bench: serving %s mu %.2f req/s, p50 %.3f s, p99 %.3f s" %
-              (mode, mu, st["p50_latency_s"], st["p99_latency_s"]), file=sys.stderr, flush=True)
+        print("bench: serving %s closed loop: %.2f req/s, %d failed" % (mode, mu, sat["failed"]), file=sys.stderr,
+              flush=True)
+        r = {"saturation_requests_per_s": round(mu, 3), "saturation_builds_per_s": round(sat["builds_per_s"], 2),
+             "saturation_failed": sat["failed"]}
+        if sat["errors"]:
+            r["saturation_errors"] = sat["errors"]
+        for load in loads:
+            arr, _ = W.poisson_stream(nreq, load * mu, seed, 1, nmax)
+            srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget)
+            t0 = time.perf_counter()
+            done = srv.serve(reqs(arr))
+            wall = time.perf_counter() - t0
+            st = summarize(done, wall)
+            key = "" if len(loads) == 1 else "load_%.2f_" % load
+            r.update({key + "poisson_rate_per_s": round(load * mu, 3),
+                      key + "builds_per_s": round(st["builds_per_s"], 2),
+                      key + "p50_latency_s": round(st["p50_latency_s"], 4),
+                      key + "p99_latency_s": round(st["p99_latency_s"], 4),
+                      key + "failed": st["failed"], key + "peak_active": srv.peak_active})
+            if st["errors"]:
+                r[key + "errors"] = st["errors"]
+            print("bench: serving %s mu %.2f req/s, load %.2f: p50 %.3f s, p99 %.3f s" %
+                  (mode, mu, load, st["p50_latency_s"], st["p99_latency_s"]), file=sys.stderr, flush=True)
+        out[mode] = r
     return out
 
 
@@ -271,6 +291,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-max-waters", type=int, default=32)
     ap.add_argument("--no-large", action="store_true", help="skip the 128-water leg")
+    ap.add_argument("--serve-modes", default="fp64,fp64+batched,bf16x3_incr")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="only run the serving stream: --serve-requests requests of 1..64 waters, Poisson "
+                         "loads 0.5..1.1 x saturation, for each of --serve-modes; print its JSON")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 128-water leg and print its JSON (for profiling)")
     ap.add_argument("--large-builds", type=int, default=2)
@@ -290,6 +314,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the DF-J/K build would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.serve_sweep:
+        print(json.dumps({"serving_sweep": serving_bench(args.serve_modes.split(","), args.serve_requests, 64,
+                                                         loads=(0.5, 0.75, 0.9, 1.1))}))
+        return
     if args.only_large:
         print(json.dumps({"water128": large_bench(args.large_builds)}))
         return
@@ -379,7 +407,8 @@ def main():
     serving = None
     if not args.no_serve:
         print("bench: serving stream", file=sys.stderr, flush=True)
-        serving = serving_bench(["fp64", "bf16x3_incr"], args.serve_requests, args.serve_max_waters)
+        serving = serving_bench(["fp64", "fp64+batched", "bf16x3_incr"], args.serve_requests,
+                                args.serve_max_waters)
 
     cpu = None
     if not args.no_cpu:

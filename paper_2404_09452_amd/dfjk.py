@@ -263,16 +263,29 @@ class Batch:
     grouped K, reduction and energy launches across the molecules.  The scratch
     is kept for the same (plans, nocc, precision)."""
 
-    def __init__(self, plans, noccs, precision="fp64"):
+    @staticmethod
+    def bytes_needed(plans, noccs, precision="fp64"):
+        n = len(plans)
+        h = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+        k = (ctypes.c_int32 * n)(*[int(x) for x in noccs])
+        nb = ctypes.c_size_t()
+        _check(N.lib().dfjk_build_batch_bytes(n, h, k, PRECISION[precision], ctypes.byref(nb)))
+        return nb.value
+
+    def __init__(self, plans, noccs, precision="fp64", scratch=None):
+        """scratch: an optional uint8 CUDA tensor to use when it is large enough."""
         self.plans = list(plans)
         self.noccs = [int(n) for n in noccs]
         self.precision = precision
         n = len(self.plans)
         self._h = (ctypes.c_void_p * n)(*[p._h.value for p in self.plans])
         self._nocc = (ctypes.c_int32 * n)(*self.noccs)
-        nb = ctypes.c_size_t()
-        _check(N.lib().dfjk_build_batch_bytes(n, self._h, self._nocc, PRECISION[precision], ctypes.byref(nb)))
-        self.scratch = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
+        self.bytes = self.bytes_needed(self.plans, self.noccs, precision)
+        nb = ctypes.c_size_t(self.bytes)
+        if scratch is not None and scratch.numel() >= nb.value:
+            self.scratch = scratch
+        else:
+            self.scratch = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
 
     def build(self, Cs, outs=None, stream=None):
         """Cs: list of (nao_i, nocc_i) orbitals; returns [(J, K, E), ...]."""

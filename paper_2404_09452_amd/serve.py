@@ -10,7 +10,9 @@ memory is returned to the budget when a request completes.  Latency is
 measured from arrival to the completion of the request's last build.
 
 The scheduling logic is independent of the GPU: `Executor` objects do the
-work, and `GpuExecutor` is the one that drives the library.
+work.  `GpuExecutor` drives the library with one stream per request;
+`BatchedGpuExecutor` runs the builds of all set-up requests step by step as
+batched calls (grouped launches across molecules).
 """
 from __future__ import annotations
 
@@ -121,6 +123,98 @@ class GpuExecutor(Executor):
             entry[0].close()
 
 
+class BatchedGpuExecutor(GpuExecutor):
+    """Step-level batching of the builds.  Each admitted request sets up on its
+    own stream as before; once set up it joins a build loop that, at every
+    step, issues the next build of every joined request as one batched call
+    (grouped K, reduction and energy launches across the molecules).
+    Requests join and leave between steps, so a molecule that arrives while
+    others are mid-run rides along from its first build.  Direct precisions
+    only (fp64, fp32, bf16x3)."""
+
+    def __init__(self, keep_results=True, schwarz_thresh=1e-14):
+        super().__init__(keep_results, schwarz_thresh)
+        from .dfjk import Batch
+        self.Batch = Batch
+        self._cv = threading.Condition()
+        self._joined = []
+        self._loop = None
+        self._stream = None
+        self.steps = 0
+        self.batch_sizes = []
+        self._arena = None          # batch scratch, grown to the largest step so far
+
+    def run(self, req):
+        torch = self.torch
+        if req.precision not in ("fp64", "fp32", "bf16x3"):
+            raise ValueError("the batched executor runs direct builds only")
+        plan, stream = self._plans[req.rid]
+        with torch.cuda.stream(stream):
+            plan.setup(stream=stream)
+            nao = plan.nao
+            st = {"req": req, "plan": plan, "k": 0, "done": threading.Event(),
+                  "Cs": [torch.as_tensor(C, device="cuda") for C in req.orbitals],
+                  "J": torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                  "Es": torch.empty((len(req.orbitals), 2), dtype=torch.float64, device="cuda")}
+            st["K"] = torch.empty_like(st["J"])
+        stream.synchronize()
+        with self._cv:
+            if self._loop is None:
+                self._stream = torch.cuda.Stream()
+                self._loop = threading.Thread(target=self._build_loop, daemon=True)
+                self._loop.start()
+            self._joined.append(st)
+            self._cv.notify_all()
+        st["done"].wait()
+        if "error" in st:
+            raise RuntimeError(st["error"])
+        req.energies = st["Es"].cpu().numpy()
+        if self.keep:
+            req.K_last = st["K"].cpu().numpy()
+            req.J_last = st["J"].cpu().numpy()
+
+    def _build_loop(self):
+        torch = self.torch
+        while True:
+            with self._cv:
+                while not self._joined:
+                    self._cv.wait()
+                group = list(self._joined)
+            finished = []
+            by_prec = {}
+            for st in group:
+                by_prec.setdefault(st["req"].precision, []).append(st)
+            try:
+                with torch.cuda.stream(self._stream):
+                    for prec, sts in by_prec.items():
+                        plans = [st["plan"] for st in sts]
+                        noccs = [st["Cs"][0].shape[1] for st in sts]
+                        need = self.Batch.bytes_needed(plans, noccs, prec)
+                        if self._arena is None or self._arena.numel() < need:
+                            self._arena = None          # drop the old arena before the larger one
+                            self._arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+                        b = self.Batch(plans, noccs, prec, scratch=self._arena)
+                        b.build([st["Cs"][st["k"]] for st in sts],
+                                outs=[(st["J"], st["K"], st["Es"][st["k"]]) for st in sts], stream=self._stream)
+                        del b
+                    self._stream.synchronize()
+                for st in group:
+                    st["k"] += 1
+                    if st["k"] == len(st["Cs"]):
+                        finished.append(st)
+            except Exception as e:  # fail every request of the step, keep serving
+                for st in group:
+                    st["error"] = repr(e)
+                finished = group
+            self.steps += 1
+            self.batch_sizes.append(len(group))
+            with self._cv:
+                for st in finished:
+                    self._joined.remove(st)
+            for st in finished:
+                st["done"].set()
+
+
 class Server:
     """Admission by slots and an HBM byte budget; FIFO order."""
 
@@ -217,4 +311,5 @@ def summarize(requests: List[Request], wall_s: float):
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
         "mean_latency_s": float(np.mean(lat)),
+        "errors": sorted(set(r.error for r in requests if r.error is not None))[:3],
     }

@@ -121,3 +121,39 @@ def test_results_identical_alone_and_in_the_mix():
         assert np.array_equal(alone.energies, r.energies)
         assert np.array_equal(alone.K_last, r.K_last)
         assert np.array_equal(alone.J_last, r.J_last)
+
+
+@pytest.mark.gpu
+def test_batched_serving_matches_requests_alone():
+    """Step-batched builds: a request's results in the mix equal its results
+    served alone (J, E_J bitwise; K and E_K to 1e-13, the batch only changes the
+    split-K summation order), and the mix really ran batched steps."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import workload as W
+    from paper_2404_09452_amd.serve import BatchedGpuExecutor, GpuExecutor
+
+    def make(rid, n, arrival):
+        z, x = W.water_cluster(n, W.cluster_box(n), 700 + rid) if n > 1 else W.water_monomer()
+        mol = W.make_molecule(z, x)
+        S = W.overlap_by_quadrature(mol)
+        C0 = W.occupied_orbitals(S, mol.nelec // 2, rid)
+        orbs = [W.perturbed_orbitals(C0, S, k, seed=91 + rid) for k in range(4)]
+        return Request(rid=rid, mol=mol, orbitals=orbs, arrival=arrival)
+
+    sizes = [2, 1, 4, 3, 1, 6, 2]
+    mix = [make(i, n, 0.003 * i) for i, n in enumerate(sizes)]
+    ex = BatchedGpuExecutor()
+    srv = Server(ex, max_active=4, hbm_budget_bytes=8 << 30)
+    srv.serve(mix)
+    assert max(ex.batch_sizes) >= 2, "no step batched two requests"
+    for r in mix:
+        assert r.error is None, r.error
+        alone = make(r.rid, sizes[r.rid], 0.0)
+        Server(GpuExecutor(), max_active=1, hbm_budget_bytes=8 << 30).serve([alone])
+        assert np.array_equal(alone.J_last, r.J_last)
+        assert np.array_equal(alone.energies[:, 0], r.energies[:, 0])
+        s = np.abs(alone.K_last).max()
+        assert np.abs(alone.K_last - r.K_last).max() <= 1e-13 * s
+        assert np.allclose(alone.energies[:, 1], r.energies[:, 1], rtol=1e-13, atol=0)
