@@ -88,10 +88,10 @@ def run_job(Plan, mol, Cd, precision, bufs, profile):
 def cpu_baseline(mol, Cs, target_s=20.0):
     """The FP64 oracle on a bounded sample of the same job, scaled to builds/s.
 
-    Sample: (a) three-centre integrals for every 44th aux shell (all AO pairs),
+    Sample: (a) three-centre integrals for every 22nd aux shell (all AO pairs),
     scaled by the shell count; (b) the full metric; (c) the full Cholesky;
-    (d) forward substitution of 4096 of the nao^2 pair columns, scaled;
-    (e) one build's J and K over a slab of 32 aux functions, scaled by naux
+    (d) forward substitution of 16384 of the nao^2 pair columns, scaled;
+    (e) one build's J and K over a slab of 64 aux functions, scaled by naux
     and by 10 builds."""
     import numpy as np
     import oracle

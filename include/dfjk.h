@@ -186,6 +186,17 @@ int dfjk_build_batch(int32_t n, dfjk_plan *const *plans, const double *const *d_
                      int32_t precision, double *const *d_J, double *const *d_K, double *const *d_E,
                      void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* Convenience for callers that hold host arrays and want one answer: plan
+ * creation, screening, setup and one build (the C or the D route, as in
+ * dfjk_build) on the current device, with J, K (nao x nao) and E[2] copied
+ * back to host memory before it returns.  C (nao x nocc) or D (nao x nao),
+ * J, K, E are HOST pointers.  Unlike every other call, this one allocates
+ * and frees its own device memory and stream, so it is not for the SCF loop
+ * (use a plan there).  Errors as for the calls it makes. */
+int dfjk_build_host(int32_t natm, const double *coords, const dfjk_basis *ao, const dfjk_basis *aux,
+                    const dfjk_options *opt, const double *C, int32_t nocc, const double *D,
+                    int32_t precision, double *J, double *K, double *E);
+
 /* Open-shell (unrestricted) build, one of the methods the paper lists as
  * optimised for the GPU (paper, "Accelerated Functionalities", table of
  * functionalities: unrestricted SCF).  Per spin s (alpha, beta):

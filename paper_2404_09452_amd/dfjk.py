@@ -310,6 +310,43 @@ class Batch:
         return outs
 
 
+def build_host(coords, ao_atom, ao_l, ao_exp, aux_atom, aux_l, aux_exp, C=None, D=None, precision="fp64",
+               schwarz_thresh=1e-14):
+    """One synchronous build from host arrays (dfjk_build_host): returns numpy
+    J, K and E = [E_J, E_K].  The library allocates its own device memory for
+    the call; use Plan for repeated builds."""
+    if (C is None) == (D is None):
+        raise ValueError("give exactly one of C and D")
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    def basis(atom, l, e):
+        a, ll, ee = arr(atom, np.int32), arr(l, np.int32), arr(e, np.float64)
+        return N.Basis(len(ll), a.ctypes.data_as(N.P_i32), ll.ctypes.data_as(N.P_i32), ee.ctypes.data_as(N.P_dbl))
+
+    xyz = arr(coords, np.float64)
+    ao, aux = basis(ao_atom, ao_l, ao_exp), basis(aux_atom, aux_l, aux_exp)
+    nao = int(np.sum(2 * np.asarray(ao_l) + 1))
+    opt = N.Options(float(schwarz_thresh), 0)
+    Cin = arr(C, np.float64) if C is not None else None
+    Din = arr(D, np.float64) if D is not None else None
+    nocc = Cin.shape[1] if Cin is not None else 0
+    J = np.zeros((nao, nao))
+    K = np.zeros((nao, nao))
+    E = np.zeros(2)
+    nul = ctypes.POINTER(ctypes.c_double)()
+    _check(N.lib().dfjk_build_host(len(xyz), xyz.ctypes.data_as(N.P_dbl), ctypes.byref(ao), ctypes.byref(aux),
+                                   ctypes.byref(opt), Cin.ctypes.data_as(N.P_dbl) if Cin is not None else nul,
+                                   int(nocc), Din.ctypes.data_as(N.P_dbl) if Din is not None else nul,
+                                   PRECISION[precision], J.ctypes.data_as(N.P_dbl), K.ctypes.data_as(N.P_dbl),
+                                   E.ctypes.data_as(N.P_dbl)))
+    return J, K, E
+
+
 def boys(mmax, T, stream=None):
     """F_0..F_mmax at the points T (CUDA float64 tensor) with the device routine."""
     T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()

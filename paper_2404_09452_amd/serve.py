@@ -142,7 +142,7 @@ class BatchedGpuExecutor(GpuExecutor):
         self._stream = None
         self.steps = 0
         self.batch_sizes = []
-        self._arena = None          # batch scratch, grown to the largest step so far
+        self._arena = None          # batch scratch of the current step
 
     def run(self, req):
         torch = self.torch
@@ -190,8 +190,10 @@ class BatchedGpuExecutor(GpuExecutor):
                         plans = [st["plan"] for st in sts]
                         noccs = [st["Cs"][0].shape[1] for st in sts]
                         need = self.Batch.bytes_needed(plans, noccs, prec)
-                        if self._arena is None or self._arena.numel() < need:
-                            self._arena = None          # drop the old arena before the larger one
+                        # the arena is exactly this step's need, which stays within the build
+                        # scratch the joined requests were admitted with
+                        if self._arena is None or self._arena.numel() != need:
+                            self._arena = None          # drop the old arena before the new one
                             self._arena = torch.empty(need, dtype=torch.uint8, device="cuda")
                         b = self.Batch(plans, noccs, prec, scratch=self._arena)
                         b.build([st["Cs"][st["k"]] for st in sts],

@@ -115,6 +115,15 @@ def test_boys_argument_checks_without_device():
     assert lib.dfjk_boys(3, -1, None, None, None) == 1
 
 
+def test_build_host_rejects_bad_input_before_device_work():
+    lib = N.lib()
+    z = ctypes.POINTER(ctypes.c_double)()
+    out = (ctypes.c_double * 4)()
+    # neither C nor D
+    assert lib.dfjk_build_host(1, out, None, None, None, z, 0, z, 0, out, out, out) == 1
+    assert b"exactly one of C and D" in lib.dfjk_last_error()
+
+
 def test_no_device_is_reported(monkeypatch):
     """On a machine without a GPU the device calls say so (skipped on a GPU machine)."""
     import torch

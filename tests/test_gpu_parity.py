@@ -332,3 +332,16 @@ def test_batch_replays_in_a_hip_graph(batch_set):
         for o, r in zip(outs, ref):
             for t, x in zip(o, r):
                 assert np.array_equal(t.cpu().numpy(), x)
+
+
+def test_build_host_convenience(water1):
+    """Host arrays in, host arrays out: the same J, K, E as the plan path."""
+    mol, C = water1["mol"], water1["C"]
+    J, K, E = G.build_host(mol.coords, mol.ao_atom, mol.ao_l, mol.ao_exp, mol.aux_atom, mol.aux_l, mol.aux_exp,
+                           C=C, schwarz_thresh=TAU)
+    J1, K1, E1 = (t.cpu().numpy() for t in water1["plan"].build(C=C))
+    assert np.array_equal(J, J1) and np.array_equal(K, K1) and np.array_equal(E, E1)
+    D = 2.0 * C @ C.T
+    _, KD, _ = G.build_host(mol.coords, mol.ao_atom, mol.ao_l, mol.ao_exp, mol.aux_atom, mol.aux_l, mol.aux_exp,
+                            D=D, schwarz_thresh=TAU)
+    assert rel(KD, water1["ref"]["K"]) <= 1e-10
