@@ -106,11 +106,13 @@ def test_results_identical_alone_and_in_the_mix():
         mol = W.make_molecule(z, x)
         S = W.overlap_by_quadrature(mol)
         C0 = W.occupied_orbitals(S, mol.nelec // 2, rid)
-        orbs = [W.perturbed_orbitals(C0, S, k, seed=77 + rid) for k in range(3)]
+        orbs = [W.perturbed_orbitals(C0, S, k, seed=77 + rid) for k in range(8)]
         return Request(rid=rid, mol=mol, orbitals=orbs, arrival=arrival)
 
-    sizes = [1, 3, 2, 4, 1, 5]
-    mix = [make(i, n, 0.005 * i) for i, n in enumerate(sizes)]
+    # all queued at once, with runs long enough (8 builds of 2-8 waters) that the
+    # next admission happens while earlier requests are still on the GPU
+    sizes = [6, 3, 8, 4, 2, 5]
+    mix = [make(i, n, 0.0) for i, n in enumerate(sizes)]
     srv = Server(GpuExecutor(), max_active=3, hbm_budget_bytes=8 << 30)
     srv.serve(mix)
     assert srv.peak_active >= 2, "the mix never overlapped"
