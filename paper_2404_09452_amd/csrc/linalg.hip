@@ -1,7 +1,7 @@
 // Dense FP64 linear algebra on the auxiliary metric, gfx950:
 //   - blocked right-looking Cholesky V = L L^T (64-wide panels; the diagonal
-//     block is factored in LDS by one workgroup, the panel below it is solved
-//     row by row, the trailing matrix is updated on FP64 MFMA),
+//     block is factored in registers by one wave, the panel below it is
+//     solved row by row, the trailing matrix is updated on FP64 MFMA),
 //   - L^{-1} by blocked forward substitution on the identity,
 //   - the whitening B = U L^{-T}-transposed product, i.e. B[f][P] =
 //     sum_{Q<=P} U[f][Q] Linv[P][Q], as one MFMA GEMM that stops each output
@@ -32,62 +32,80 @@ void launch_metric_pad(double *V, int64_t n, int64_t npad, hipStream_t s)
     hipLaunchKernelGGL(k_metric_pad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V, n, npad);
 }
 
-// Factor the 64x64 diagonal block at (k0, k0) in place.  A pivot <= 0 is
-// recorded (smallest index wins) and replaced by 1 so the remaining steps stay
-// finite; the host reports the recorded index.
-__global__ __launch_bounds__(256) void k_potrf_diag(double *A, int64_t ld, int64_t k0, int32_t *status)
+// Lane `src`'s value of v, broadcast to the wave (two 32-bit lane reads).
+__device__ __forceinline__ double readlane_f64(double v, int src)
 {
-    __shared__ double S[NBK][NBK + 1];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < NBK * NBK; i += 256) S[i / NBK][i % NBK] = A[(k0 + i / NBK) * ld + k0 + i % NBK];
-    __syncthreads();
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, src);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Factor the 64x64 diagonal block at (k0, k0) in place with one wave: lane i
+// holds row i in registers; column j's pivot and entries reach the other
+// lanes by lane reads, so there is no LDS traffic and no barrier.  A pivot
+// <= 0 is recorded (smallest index wins) and replaced by 1 so the remaining
+// steps stay finite; the host reports the recorded index.
+__global__ __launch_bounds__(64) void k_potrf_diag(double *A, int64_t ld, int64_t k0, int32_t *status)
+{
+    const int i = threadIdx.x;
+    double *row = A + (k0 + i) * ld + k0;
+    double r[NBK];
+#pragma unroll
+    for (int c = 0; c < NBK; ++c) r[c] = row[c];
+    int bad = INT_MAX;
+#pragma unroll
     for (int j = 0; j < NBK; ++j) {
-        if (tid == 0) {
-            double d = S[j][j];
-            if (!(d > 0.0)) {
-                atomicMin(status, (int32_t)(k0 + j));
-                d = 1.0;
-            }
-            S[j][j] = sqrt(d);
+        double d = readlane_f64(r[j], j);
+        if (!(d > 0.0)) {
+            if (bad == INT_MAX) bad = (int)(k0 + j);
+            d = 1.0;
         }
-        __syncthreads();
-        const double djj = S[j][j];
-        for (int i = j + 1 + tid; i < NBK; i += 256) S[i][j] /= djj;
-        __syncthreads();
-        // trailing update of the lower triangle inside the block
-        const int w = NBK - 1 - j;
-        for (int e = tid; e < w * w; e += 256) {
-            const int i = j + 1 + e / w, l = j + 1 + e % w;
-            if (l <= i) S[i][l] -= S[i][j] * S[l][j];
+        d = sqrt(d);
+        if (i == j) r[j] = d;
+        else if (i > j) r[j] = r[j] / d;
+#pragma unroll
+        for (int l = j + 1; l < NBK; ++l) {
+            const double lj = readlane_f64(r[j], l);    // L[l][j]
+            if (i >= l) r[l] -= r[j] * lj;
         }
-        __syncthreads();
     }
-    for (int i = tid; i < NBK * NBK; i += 256) {
-        const int r = i / NBK, c = i % NBK;
-        A[(k0 + r) * ld + k0 + c] = (c <= r) ? S[r][c] : 0.0;
-    }
+    if (i == 0 && bad != INT_MAX) atomicMin(status, bad);
+#pragma unroll
+    for (int c = 0; c < NBK; ++c) row[c] = (c <= i) ? r[c] : 0.0;
 }
 
 // Panel: rows i0.. of block column k0 get L_ik = A_ik L_kk^{-T}; one
-// workgroup per 64-row block, one thread per row (x L_kk^T = a, forward).
+// workgroup per 64-row block, one thread per row (x L_kk^T = a, forward),
+// the row in registers and L_kk broadcast from LDS; four partial sums per
+// entry shorten the dependent chain.
 __global__ __launch_bounds__(64) void k_trsm_panel(double *A, int64_t ld, int64_t k0)
 {
     __shared__ double Lk[NBK][NBK + 1];
-    __shared__ double X[NBK][NBK + 1];
     const int tid = threadIdx.x;
     const int64_t r0 = k0 + NBK * (1 + (int64_t)blockIdx.x);
-    for (int i = tid; i < NBK * NBK; i += NBK) {
-        Lk[i / NBK][i % NBK] = A[(k0 + i / NBK) * ld + k0 + i % NBK];
-        X[i / NBK][i % NBK] = A[(r0 + i / NBK) * ld + k0 + i % NBK];
-    }
+    for (int e = tid; e < NBK * NBK; e += NBK) Lk[e / NBK][e % NBK] = A[(k0 + e / NBK) * ld + k0 + e % NBK];
+    double *row = A + (r0 + tid) * ld + k0;
+    double x[NBK];
+#pragma unroll
+    for (int c = 0; c < NBK; ++c) x[c] = row[c];
     __syncthreads();
+#pragma unroll
     for (int j = 0; j < NBK; ++j) {
-        double v = X[tid][j];
-        for (int l = 0; l < j; ++l) v -= X[tid][l] * Lk[j][l];
-        X[tid][j] = v / Lk[j][j];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int l = 0; l + 3 < j; l += 4) {
+            s0 += x[l] * Lk[j][l];
+            s1 += x[l + 1] * Lk[j][l + 1];
+            s2 += x[l + 2] * Lk[j][l + 2];
+            s3 += x[l + 3] * Lk[j][l + 3];
+        }
+#pragma unroll
+        for (int l = j & ~3; l < j; ++l) s0 += x[l] * Lk[j][l];
+        x[j] = (x[j] - ((s0 + s1) + (s2 + s3))) / Lk[j][j];
     }
-    __syncthreads();
-    for (int i = tid; i < NBK * NBK; i += NBK) A[(r0 + i / NBK) * ld + k0 + i % NBK] = X[i / NBK][i % NBK];
+#pragma unroll
+    for (int c = 0; c < NBK; ++c) row[c] = x[c];
 }
 
 void launch_cholesky(double *A, int64_t npad, int32_t *status, hipStream_t s)
@@ -95,7 +113,7 @@ void launch_cholesky(double *A, int64_t npad, int32_t *status, hipStream_t s)
     const int64_t nb = npad / NBK;
     for (int64_t k = 0; k < nb; ++k) {
         const int64_t k0 = k * NBK;
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, npad, k0, status);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NBK), 0, s, A, npad, k0, status);
         const int64_t rest = nb - k - 1;
         if (rest == 0) break;
         hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)rest), dim3(NBK), 0, s, A, npad, k0);
@@ -141,10 +159,17 @@ __global__ __launch_bounds__(64) void k_trtri_diag(const double *L, double *X, i
     for (int r = 0; r < NBK; ++r) x[r] = X[(i0 + r) * ld + c];
 #pragma unroll
     for (int r = 0; r < NBK; ++r) {
-        double v = x[r];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four partial sums shorten the chain
 #pragma unroll
-        for (int l = 0; l < r; ++l) v -= Li[r][l] * x[l];
-        x[r] = v / Li[r][r];
+        for (int l = 0; l + 3 < r; l += 4) {
+            s0 += Li[r][l] * x[l];
+            s1 += Li[r][l + 1] * x[l + 1];
+            s2 += Li[r][l + 2] * x[l + 2];
+            s3 += Li[r][l + 3] * x[l + 3];
+        }
+#pragma unroll
+        for (int l = r & ~3; l < r; ++l) s0 += Li[r][l] * x[l];
+        x[r] = (x[r] - ((s0 + s1) + (s2 + s3))) / Li[r][r];
     }
 #pragma unroll
     for (int r = 0; r < NBK; ++r) X[(i0 + r) * ld + c] = x[r];
