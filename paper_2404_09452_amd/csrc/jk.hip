@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void k_j_rows(const double *__restrict__ B, in
 // row P = l/16 + 4r.
 
 enum { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2 };
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 struct HTArgs {
     const double *B;          // [f][ld]
@@ -188,12 +189,19 @@ void k_halftrans(HTArgs g)
             r[it] = (k < ke) ? g.hk_row[k] : -1;
         }
     };
+    // B rows and X are streamed once; non-temporal accesses keep them from
+    // evicting the coefficient rows C, which every workgroup re-reads from L2
     auto load_a = [&](const int (&r)[NLA], double2 (&a)[NLA]) {
 #pragma unroll
         for (int it = 0; it < NLA; ++it) {
             const int pp = ((tid + NT * it) % 64) * 2;
-            a[it] = (r[it] >= 0) ? *reinterpret_cast<const double2 *>(g.B + (int64_t)r[it] * g.ld + p0 + pp)
-                                 : double2{0.0, 0.0};
+            if (r[it] >= 0) {
+                const f64x2 v = __builtin_nontemporal_load(
+                    reinterpret_cast<const f64x2 *>(g.B + (int64_t)r[it] * g.ld + p0 + pp));
+                a[it] = double2{v[0], v[1]};
+            } else {
+                a[it] = double2{0.0, 0.0};
+            }
         }
     };
     auto load_c = [&](int kc, double2 (&c)[NLC]) {
@@ -265,9 +273,9 @@ void k_halftrans(HTArgs g)
             const int64_t o = ((int64_t)mu * g.plen + (P - g.p_begin)) * g.ncol + col;
             const double v64 = acc[j][r];
             if (OUT == OUT_F64) {
-                static_cast<double *>(g.X)[o] = v64;
+                __builtin_nontemporal_store(v64, static_cast<double *>(g.X) + o);
             } else if (OUT == OUT_F32) {
-                static_cast<float *>(g.X)[o] = (float)v64;
+                __builtin_nontemporal_store((float)v64, static_cast<float *>(g.X) + o);
             } else {
                 const float v = (float)v64;
                 const unsigned short hi = f32_to_bf16_rne(v);
