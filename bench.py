@@ -27,6 +27,11 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The serving stream allocates and frees workspaces of molecules of 1..64
+# waters.  Blocks above 512 MB are never split, so a finished molecule's
+# workspace goes back as whole segments that torch can release when a larger
+# one needs the room (must be set before torch touches the GPU).
+os.environ.setdefault("PYTORCH_ALLOC_CONF", "max_split_size_mb:512")
 
 NBUILDS = 10
 PEAK_F64_TFLOPS = 78.6
