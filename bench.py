@@ -179,7 +179,17 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
 
         def executor():
             return BatchedGpuExecutor(keep_results=False) if batched else GpuExecutor(keep_results=False)
-        srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget)
+
+        def progress(tag):
+            count = [0]
+
+            def done(req):
+                count[0] += 1
+                if count[0] % 16 == 0:
+                    print("bench: serving %s %s: %d of %d requests done" % (mode, tag, count[0], nreq),
+                          file=sys.stderr, flush=True)
+            return done
+        srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget, on_done=progress("closed loop"))
         t0 = time.perf_counter()
         closed = srv.serve(reqs(np.zeros(nreq)))
         wall = time.perf_counter() - t0
@@ -193,7 +203,8 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
             r["saturation_errors"] = sat["errors"]
         for load in loads:
             arr, _ = W.poisson_stream(nreq, load * mu, seed, 1, nmax)
-            srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget)
+            srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget,
+                         on_done=progress("load %.2f" % load))
             t0 = time.perf_counter()
             done = srv.serve(reqs(arr))
             wall = time.perf_counter() - t0

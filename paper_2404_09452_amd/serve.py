@@ -190,9 +190,10 @@ class BatchedGpuExecutor(GpuExecutor):
                         plans = [st["plan"] for st in sts]
                         noccs = [st["Cs"][0].shape[1] for st in sts]
                         need = self.Batch.bytes_needed(plans, noccs, prec)
-                        # the arena is exactly this step's need, which stays within the build
-                        # scratch the joined requests were admitted with
-                        if self._arena is None or self._arena.numel() != need:
+                        # the arena is reused while it is within 25% above this step's need
+                        # (which stays within the build scratch the joined requests were
+                        # admitted with), else replaced by one of exactly that size
+                        if self._arena is None or not need <= self._arena.numel() <= need + need // 4:
                             self._arena = None          # drop the old arena before the new one
                             self._arena = torch.empty(need, dtype=torch.uint8, device="cuda")
                         b = self.Batch(plans, noccs, prec, scratch=self._arena)
@@ -221,7 +222,8 @@ class Server:
     """Admission by slots and an HBM byte budget; FIFO order."""
 
     def __init__(self, executor: Executor, max_active=4, hbm_budget_bytes=64 << 30,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter,
+                 on_done: Optional[Callable[[Request], None]] = None):
         if max_active < 1:
             raise ValueError("max_active must be >= 1")
         self.ex = executor
@@ -234,6 +236,7 @@ class Server:
         self.peak_active = 0
         self._cv = threading.Condition()
         self._errors = []
+        self.on_done = on_done      # called from the worker thread after each request
 
     def _worker(self, req):
         try:
@@ -247,6 +250,8 @@ class Server:
                 self.in_use -= req.bytes_needed
                 self.active -= 1
                 self._cv.notify_all()
+            if self.on_done is not None:
+                self.on_done(req)
 
     def serve(self, requests: List[Request]) -> List[Request]:
         """Feed `requests` at their arrival times and return them completed."""
