@@ -186,6 +186,24 @@ int dfjk_build_batch(int32_t n, dfjk_plan *const *plans, const double *const *d_
                      int32_t precision, double *const *d_J, double *const *d_K, double *const *d_E,
                      void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* Host-resident B, the paper's large-system storage (paper, Section 2.1
+ * "Dataset and Performance": integrals held in host memory and moved to the
+ * GPU asynchronously).  After dfjk_setup, dfjk_offload copies the whitened
+ * tensor B into h_pinned (page-locked host memory the caller allocates and
+ * keeps until dfjk_plan_destroy; slab-major, aux slabs of
+ * dfjk_options.aux_slab functions or 1024) and the few tables later builds
+ * need into d_tables (device memory the caller keeps).  Synchronises
+ * `stream`.  From then on the plan no longer uses the setup workspace (the
+ * caller may free it), and every dfjk_build (C route, any precision) streams
+ * B slab by slab into two staging buffers of its scratch on a copy stream of
+ * the plan, overlapped with the slab's J, half-transform and K work.  One
+ * build at a time per plan.  dfjk_build_delta, dfjk_build_uks,
+ * dfjk_build_batch and the density route return DFJK_E_UNSUPPORTED, and
+ * dfjk_export, dfjk_sample and dfjk_setup DFJK_E_STATE, on such a plan. */
+int dfjk_offload_bytes(const dfjk_plan *plan, size_t *host_bytes, size_t *device_bytes);
+int dfjk_offload(dfjk_plan *plan, void *h_pinned, size_t host_bytes, void *d_tables,
+                 size_t device_bytes, void *stream);
+
 /* Convenience for callers that hold host arrays and want one answer: plan
  * creation, screening, setup and one build (the C or the D route, as in
  * dfjk_build) on the current device, with J, K (nao x nao) and E[2] copied

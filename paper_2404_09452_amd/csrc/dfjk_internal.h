@@ -79,6 +79,13 @@ struct Plan {
     int64_t naux = 0, naux_pad = 0;
     double thresh = 1e-14;
     int32_t aux_slab = 0;               // requested K-build aux slab (0 = automatic)
+    // host-resident B (after dfjk_offload): slab-major pinned copy, the slab
+    // width of that layout, and the stream and events of the slab copies
+    bool host_B = false;
+    const double *hB = nullptr;
+    int64_t host_slab = 0;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr}, ev_start = nullptr;
     int device = 0;
     int num_cus = 256;
     int stage = 0;
@@ -185,6 +192,7 @@ struct BuildLayout {
     size_t bytes;
     // offsets into the scratch
     size_t o_D, o_d, o_cpart, o_c, o_X, o_Xlo, o_Bfull, o_X2, o_X2lo, o_U, o_W, o_Kpart, o_Epart, o_Da, o_Db;
+    size_t o_stage[2];                  // staging of host-resident B slabs
 };
 BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta = false,
                          int nsplit = 0);
@@ -196,6 +204,8 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
                   double *J, double *K, double *E, char *scratch, hipStream_t s);
 void launch_build_uks(Plan &p, const BuildLayout &L, const double *Ca, const double *Cb, double *J, double *Ka,
                       double *Kb, double *E, char *scratch, hipStream_t s);
+void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *J, double *K, double *E,
+                        char *scratch, hipStream_t s);
 
 // export.hip
 void launch_zero(double *p, int64_t n, hipStream_t s);

@@ -105,7 +105,7 @@ __global__ void k_c_reduce(const double *__restrict__ cpart, int nsplit, int64_t
 __global__ __launch_bounds__(256) void k_j_rows(const double *__restrict__ B, int64_t ld,
                                                 const double *__restrict__ c, const int32_t *__restrict__ fmu,
                                                 const int32_t *__restrict__ fnu, const double *__restrict__ fw,
-                                                int64_t nf, int64_t nao, double *__restrict__ J)
+                                                int64_t nf, int64_t nao, int32_t accumulate, double *__restrict__ J)
 {
     const int64_t f = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -117,8 +117,9 @@ __global__ __launch_bounds__(256) void k_j_rows(const double *__restrict__ B, in
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) {
         const int64_t mu = fmu[f], nu = fnu[f];
-        J[mu * nao + nu] = s;
-        if (fw[f] > 1.5) J[nu * nao + mu] = s;
+        const double v = accumulate ? J[mu * nao + nu] + s : s;
+        J[mu * nao + nu] = v;
+        if (fw[f] > 1.5) J[nu * nao + mu] = v;
     }
 }
 
@@ -528,7 +529,8 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     const double per_aux = (double)p.nao * L.ncol *
                            ((double)esz + (precision == DFJK_MIXED_BF16X3 ? 2 : 0) + (with_D ? 8 : 0)) *
                            (delta ? 2 : 1);
-    int64_t slab = p.aux_slab > 0 ? (int64_t)align_up((size_t)p.aux_slab, kPadAux)
+    int64_t slab = p.host_B ? p.host_slab
+                 : p.aux_slab > 0 ? (int64_t)align_up((size_t)p.aux_slab, kPadAux)
                                   : (int64_t)(kAutoSlabBytes / per_aux) / kPadAux * kPadAux;
     if (slab < kPadAux) slab = kPadAux;
     if (slab > p.naux_pad) slab = p.naux_pad;
@@ -564,6 +566,10 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
         L.o_W = take((size_t)p.nao * nocc * 8);
     }
     L.o_Kpart = take((size_t)L.nslab * L.nsplit_k * ntiles * kTileK * kTileK * 8);
+    if (p.host_B) {   // two staging buffers for slabs of the host-resident B
+        L.o_stage[0] = take((size_t)p.nf_pad * L.slab * 8);
+        L.o_stage[1] = take((size_t)p.nf_pad * L.slab * 8);
+    }
     L.o_Epart = take((size_t)L.ntile * (L.ntile + 1) / 2 * (kTileK / 16) * 8);
     L.bytes = align_up(off, 256);
     return L;
@@ -588,7 +594,7 @@ static void launch_j(Plan &p, const BuildLayout &L, const double *D, double *J, 
     fill(J, nao * nao, 0.0, s);
     if (p.nf > 0)
         hipLaunchKernelGGL(k_j_rows, dim3((unsigned)((p.nf + 3) / 4)), dim3(256), 0, s, p.d.B, ld, cvec, p.d.f_mu,
-                           p.d.f_nu, p.d.f_w, p.nf, nao, J);
+                           p.d.f_nu, p.d.f_w, p.nf, nao, 0, J);
 }
 
 static void launch_ht(const Plan &p, int precision, const double *C, int32_t ncol, int64_t p_begin, int64_t plen,
@@ -855,6 +861,102 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         }
         hipLaunchKernelGGL(k_energies_grouped, dim3(m), dim3(256), 0, s, grp, -0.25);
     }
+}
+
+// Closed-shell build from a host-resident B (paper Section 2.1: integrals in
+// host memory, moved to the GPU asynchronously).  The host copy is slab-major
+// ([slab][f][plen], the slab width fixed when B was offloaded); each slab is
+// copied into one of two staging buffers on the plan's copy stream while the
+// previous slab is consumed on `s`: c for the slab's aux functions, its
+// contribution to J, the half transform and the slab's K partial tiles.
+// Events order the two streams: the copy into a buffer waits for the compute
+// that last read it; the compute waits for its copy.
+void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *J, double *K, double *E,
+                        char *scratch, hipStream_t s)
+{
+    const int64_t nao = p.nao, ld = p.naux_pad;
+    double *D = reinterpret_cast<double *>(scratch + L.o_D);
+    double *dvec = reinterpret_cast<double *>(scratch + L.o_d);
+    double *cpart = reinterpret_cast<double *>(scratch + L.o_cpart);
+    double *cvec = reinterpret_cast<double *>(scratch + L.o_c);
+    double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
+    double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
+    double *stage[2] = {reinterpret_cast<double *>(scratch + L.o_stage[0]),
+                        reinterpret_cast<double *>(scratch + L.o_stage[1])};
+    void *X = scratch + L.o_X;
+    void *Xlo = L.o_Xlo ? scratch + L.o_Xlo : nullptr;
+    const int ntiles = L.ntile * (L.ntile + 1) / 2;
+    const size_t slab_part = (size_t)L.nsplit_k * ntiles * kTileK * kTileK;
+    Profiler &pr = p.prof;
+    pr.stream = s;
+    hipStream_t cs = p.copy_stream;
+
+    auto copy_slab = [&](int64_t sl) {
+        const int b = (int)(sl & 1);
+        const int64_t pb = sl * L.slab, plen = (ld - pb < L.slab) ? ld - pb : L.slab;
+        (void)hipStreamWaitEvent(cs, p.ev_free[b], 0);
+        (void)hipMemcpyAsync(stage[b], p.hB + (size_t)p.nf_pad * pb, (size_t)p.nf_pad * plen * 8,
+                             hipMemcpyHostToDevice, cs);
+        (void)hipEventRecord(p.ev_ready[b], cs);
+    };
+    // the copy stream starts after everything already queued on s
+    (void)hipEventRecord(p.ev_start, s);
+    (void)hipStreamWaitEvent(cs, p.ev_start, 0);
+    copy_slab(0);
+    if (L.nslab > 1) copy_slab(1);
+
+    pr.mark(ST_DENSITY, true);
+    hipLaunchKernelGGL(k_density, dim3((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16)), dim3(256), 0, s, C,
+                       nao, (int32_t)L.ncol, 2.0, D);
+    pr.mark(ST_DENSITY, false);
+    hipLaunchKernelGGL(k_gather_d, dim3((unsigned)((p.nf_pad + 255) / 256)), dim3(256), 0, s, D, nao, p.d.f_mu,
+                       p.d.f_nu, p.d.f_w, p.nf, p.nf_pad, dvec);
+    fill(J, nao * nao, 0.0, s);
+    for (int64_t sl = 0; sl < L.nslab; ++sl) {
+        const int b = (int)(sl & 1);
+        const int64_t pb = sl * L.slab, plen = (ld - pb < L.slab) ? ld - pb : L.slab;
+        (void)hipStreamWaitEvent(s, p.ev_ready[b], 0);
+        pr.mark(ST_J, true);
+        hipLaunchKernelGGL(k_c_partial, dim3((unsigned)((plen + 255) / 256), L.nsplit_c), dim3(256), 0, s, stage[b],
+                           plen, dvec, p.nf_pad, cpart);
+        hipLaunchKernelGGL(k_c_reduce, dim3((unsigned)((plen + 255) / 256)), dim3(256), 0, s, cpart, L.nsplit_c,
+                           plen, cvec + pb);
+        if (p.nf > 0)
+            hipLaunchKernelGGL(k_j_rows, dim3((unsigned)((p.nf + 3) / 4)), dim3(256), 0, s, stage[b], plen, cvec + pb,
+                               p.d.f_mu, p.d.f_nu, p.d.f_w, p.nf, nao, 1, J);
+        pr.mark(ST_J, false);
+        pr.mark(ST_HALFTRANS, true);
+        HTArgs h{stage[b], plen, C, (int32_t)L.ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, 0, plen};
+        if (L.precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, nao, s);
+        else if (L.precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, nao, s);
+        else launch_halftrans<OUT_BF16X2>(h, nao, s);
+        pr.mark(ST_HALFTRANS, false);
+        (void)hipEventRecord(p.ev_free[b], s);      // the staging buffer is read
+        if (sl + 2 < L.nslab) copy_slab(sl + 2);
+        pr.mark(ST_K, true);
+        const int64_t kdim = plen * L.ncol;
+        double *part = Kpart + sl * slab_part;
+        if (L.precision == DFJK_FP64) {
+            GemmArgs g{};
+            g.A = static_cast<const double *>(X); g.lda = kdim;
+            g.B = g.A; g.ldb = kdim;
+            g.M = g.N = nao;
+            g.k_begin = 0; g.k_end = kdim;
+            g.ksplit = align_up((size_t)((kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
+            g.alpha = 1.0; g.lower = 1; g.partial = part;
+            gemm_f64<kTileK, false>(g, L.nsplit_k, s);
+        } else {
+            launch_gemm_mixed(L.precision, true, X, Xlo, X, Xlo, nao, kdim, L.nsplit_k, part, s);
+        }
+        pr.mark(ST_K, false);
+    }
+    pr.mark(ST_KREDUCE, true);
+    const int nlower = L.ntile * (L.ntile + 1) / 2;
+    hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
+                       L.ntile, nao, 2.0, D, K, Epart);
+    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (kTileK / 16), -0.25,
+                       E);
+    pr.mark(ST_KREDUCE, false);
 }
 
 }  // namespace dfjk

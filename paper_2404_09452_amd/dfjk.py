@@ -213,6 +213,19 @@ class Plan:
                                       _stream_handle(stream)))
         return J, Ka, Kb, E
 
+    def offload(self, stream=None):
+        """Move B to page-locked host memory (dfjk_offload); later builds stream
+        it back slab by slab.  Frees the device setup workspace."""
+        hb, db = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(N.lib().dfjk_offload_bytes(self._h, ctypes.byref(hb), ctypes.byref(db)))
+        self._host_B = torch.empty(hb.value, dtype=torch.uint8, pin_memory=True)
+        self._tables = torch.empty(max(db.value, 1), dtype=torch.uint8, device="cuda")
+        _check(N.lib().dfjk_offload(self._h, ctypes.c_void_p(self._host_B.data_ptr()), hb.value,
+                                    _ptr(self._tables), self._tables.numel(), _stream_handle(stream)))
+        self._ws = None
+        self._scratch = {}
+        return self
+
     # -- diagnostics -------------------------------------------------------
     NSTAGES = 10
 
@@ -250,6 +263,8 @@ class Plan:
             self._h = None
         self._ws = None
         self._scratch = {}
+        self._host_B = None
+        self._tables = None
 
     def __del__(self):
         try:

@@ -345,3 +345,68 @@ def test_build_host_convenience(water1):
     _, KD, _ = G.build_host(mol.coords, mol.ao_atom, mol.ao_l, mol.ao_exp, mol.aux_atom, mol.aux_l, mol.aux_exp,
                             D=D, schwarz_thresh=TAU)
     assert rel(KD, water1["ref"]["K"]) <= 1e-10
+
+
+@pytest.mark.parametrize("nocc", [1, 30])
+def test_occupation_extremes(water1, nocc):
+    """One occupied column (single-fragment half transform) and every AO
+    occupied (nocc = nao)."""
+    mol = water1["mol"]
+    S = W.overlap_by_quadrature(mol)
+    C = W.occupied_orbitals(S, nocc, 11)
+    ref = oracle.jk_from_B(water1["B"], C=C)
+    J, K, E = (t.cpu().numpy() for t in water1["plan"].build(C=C))
+    assert rel(J, ref["J"]) <= 1e-10 and rel(K, ref["K"]) <= 1e-10
+    assert abs(E[1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
+
+
+def test_density_route_with_column_passes():
+    """Nine waters through the density route: X has nao = 270 columns, more than
+    one 256-column pass of the half transform."""
+    mol, S, C = case(9)
+    D = 2.0 * C @ C.T
+    ref = oracle.dfjk(mol, D=D)
+    plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
+    J, K, E = (t.cpu().numpy() for t in plan.build(D=D))
+    assert rel(J, ref["J"]) <= 1e-10 and rel(K, ref["K"]) <= 1e-10
+    assert abs(E[1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
+
+
+def test_zero_threshold_keeps_every_pair(water1):
+    """Threshold 0 keeps every shell pair and triplet (the unscreened definition)."""
+    mol, C = water1["mol"], water1["C"]
+    plan = G.Plan.from_molecule(mol, schwarz_thresh=0.0).screen().setup()
+    inf = plan.info()
+    assert inf["sig_shell_pairs"] == inf["nshell_pairs"]
+    assert inf["triplets_kept"] == inf["nshell_pairs"] * len(mol.aux_l)
+    J, K, E = (t.cpu().numpy() for t in plan.build(C=C))
+    assert rel(K, water1["ref"]["K"]) <= 1e-11
+    assert rel(J, water1["ref"]["J"]) <= 1e-11
+
+
+@pytest.mark.parametrize("slab", [128, 384])
+def test_host_resident_B_matches_device_B(cluster5, slab):
+    """B moved to page-locked host memory and streamed back slab by slab:
+    K and the energies equal the device-resident build with the same slabs,
+    J to the order of its slab sums."""
+    d = cluster5
+    dev = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU, aux_slab=slab).screen().setup()
+    host = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU, aux_slab=slab).screen().setup().offload()
+    C1 = W.perturbed_orbitals(d["C"], d["S"], 2, eps=1e-2, seed=1000)
+    for C in (d["C"], C1):                      # a second build reuses the staging buffers
+        for prec in ("fp64", "fp32"):
+            J1, K1, E1 = (t.cpu().numpy() for t in dev.build(C=C, precision=prec))
+            J2, K2, E2 = (t.cpu().numpy() for t in host.build(C=C, precision=prec))
+            assert np.array_equal(K1, K2)
+            assert np.array_equal(E1, E2)
+            assert rel(J2, J1) <= 1e-13
+    J, K, E = (t.cpu().numpy() for t in host.build(C=d["C"]))
+    assert rel(K, d["ref"]["K"]) <= 1e-10 and rel(J, d["ref"]["J"]) <= 1e-10
+    with pytest.raises(G.DFJKError) as e:
+        host.export(G.EXPORT_B)
+    assert e.value.status == "STATE"
+    with pytest.raises(G.DFJKError) as e:
+        host.build(D=2.0 * d["C"] @ d["C"].T)
+    assert e.value.status == "UNSUPPORTED"
+    host.close()
+    dev.close()
