@@ -291,6 +291,26 @@ def large_bench(nbuild=2):
         out[prec] = r
         plan._scratch = {}
         print("bench: water128 %s %.1f ms/build" % (prec, r["ms_per_build"]), file=sys.stderr, flush=True)
+    # host-resident B (pinned memory, slabs streamed back during each build)
+    plan.offload()
+    torch.cuda.empty_cache()
+    hb = {"B_host_GB": round(info["nf"] * info["naux_pad"] * 8 / 1e9, 2)}
+    for prec in ("fp64", "fp32"):
+        plan.build(C=Cs[0], precision=prec)
+        torch.cuda.synchronize()
+        plan.profile_read()
+        t0 = time.perf_counter()
+        for C in Cs:
+            plan.build(C=C, precision=prec)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = plan.profile_read()
+        hb[prec] = {"ms_per_build": round(1000.0 * wall / nbuild, 2),
+                    "stage_ms_per_build": {k: round(v[0] / nbuild, 3) for k, v in st.items() if k.startswith("build.")}}
+        plan._scratch = {}
+        print("bench: water128 host-resident B %s %.1f ms/build" % (prec, hb[prec]["ms_per_build"]),
+              file=sys.stderr, flush=True)
+    out["host_resident_B"] = hb
     plan.close()
     torch.cuda.empty_cache()
     return out
