@@ -433,6 +433,11 @@ def main():
             results[prec]["K_tflops"] = round(k_flops / (ms * 1e-3) / 1e12, 2)
             results[prec]["K_frac_of_peak"] = round(k_flops / (ms * 1e-3) / 1e12 / peak, 4)
 
+    # split-count autotuner on the same molecule (outside the timed steps)
+    tplan = Plan.from_molecule(mol, schwarz_thresh=1e-14).screen().setup()
+    chosen, cand_ms = tplan.autotune(Cd[0])
+    autotune = {"chosen_nsplit": chosen, "ms_per_build_by_nsplit": {str(k): round(v, 3) for k, v in cand_ms.items()}}
+    tplan.close()
     del bufs, Cd
     torch.cuda.empty_cache()
     large = None
@@ -474,6 +479,7 @@ def main():
         "mixed": {k: v for k, v in results.items() if k != "fp64"},
         "serving": serving,
         "water128": large,
+        "autotune_K_split": autotune,
         "fp64_detail": {k: v for k, v in f64.items() if k not in ("E_J", "E_K")},
         "device": torch.cuda.get_device_name(0),
     }

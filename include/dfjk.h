@@ -186,6 +186,22 @@ int dfjk_build_batch(int32_t n, dfjk_plan *const *plans, const double *const *d_
                      int32_t precision, double *const *d_J, double *const *d_K, double *const *d_E,
                      void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* Autotuner for the split count of the K contraction of the closed-shell
+ * C-route build (dfjk_build with d_C, this nocc and precision): each
+ * candidate (half, one, two and four times the built-in choice, within the
+ * contraction length) runs one warm-up and three timed builds with d_C on
+ * `stream` (HIP events; synchronises the stream), and the fastest is kept
+ * in the plan for later builds of that shape.  A different split count only
+ * reorders the FP64 sums of the split-K reduction, which stays fixed and
+ * deterministic for a given choice.  dfjk_build_bytes may grow afterwards.
+ * d_scratch must hold dfjk_autotune_bytes.  On return *chosen is the kept
+ * count; with ncand != NULL, *ncand (capacity in, count out) candidates and
+ * their ms per build are written to cand and ms (host arrays, may be NULL). */
+int dfjk_autotune_bytes(const dfjk_plan *plan, int32_t nocc, int32_t precision, size_t *bytes);
+int dfjk_autotune(dfjk_plan *plan, const double *d_C, int32_t nocc, int32_t precision, void *d_scratch,
+                  size_t scratch_bytes, void *stream, int32_t *chosen, int32_t *ncand, int32_t *cand,
+                  double *ms);
+
 /* Host-resident B, the paper's large-system storage (paper, Section 2.1
  * "Dataset and Performance": integrals held in host memory and moved to the
  * GPU asynchronously).  After dfjk_setup, dfjk_offload copies the whitened

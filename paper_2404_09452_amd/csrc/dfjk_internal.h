@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -86,6 +87,9 @@ struct Plan {
     int64_t host_slab = 0;
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr}, ev_start = nullptr;
+    // split counts chosen by dfjk_autotune for the closed-shell C-route build,
+    // keyed by nocc * 4 + precision
+    std::map<int64_t, int> tuned_nsplit;
     int device = 0;
     int num_cus = 256;
     int stage = 0;
@@ -194,6 +198,8 @@ struct BuildLayout {
     size_t o_D, o_d, o_cpart, o_c, o_X, o_Xlo, o_Bfull, o_X2, o_X2lo, o_U, o_W, o_Kpart, o_Epart, o_Da, o_Db;
     size_t o_stage[2];                  // staging of host-resident B slabs
 };
+// nsplit: 0 = the autotuned count when there is one, else the built-in
+// choice; -1 = the built-in choice; > 0 = that count (capped by the length)
 BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta = false,
                          int nsplit = 0);
 int batch_nsplit(const Plan *const *plans, int n);

@@ -540,7 +540,11 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
     L.nsplit_k = (precision == DFJK_FP64) ? choose_ksplit(ntiles, L.kdim, p.num_cus)
                                           : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
-    if (nsplit > 0) {   // a batch chooses the split count for all its molecules together
+    if (nsplit == 0 && !with_D && !delta) {   // a split count the autotuner measured for this shape
+        const auto it = p.tuned_nsplit.find((int64_t)nocc * 4 + precision);
+        if (it != p.tuned_nsplit.end()) nsplit = it->second;
+    }
+    if (nsplit > 0) {   // a batch (or the autotuner) chooses the split count
         const int64_t maxs = L.kdim / 256 > 0 ? L.kdim / 256 : 1;
         L.nsplit_k = nsplit < maxs ? nsplit : (int)maxs;
     }

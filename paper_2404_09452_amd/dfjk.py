@@ -213,6 +213,22 @@ class Plan:
                                       _stream_handle(stream)))
         return J, Ka, Kb, E
 
+    def autotune(self, C, precision="fp64", stream=None):
+        """Time the candidate split counts of the K contraction for this C shape
+        (dfjk_autotune) and keep the fastest; returns (chosen, {split: ms})."""
+        C = torch.as_tensor(C, dtype=torch.float64, device="cuda").contiguous()
+        nocc = C.shape[1]
+        nb = ctypes.c_size_t()
+        _check(N.lib().dfjk_autotune_bytes(self._h, int(nocc), PRECISION[precision], ctypes.byref(nb)))
+        scr = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        chosen, ncand = ctypes.c_int32(), ctypes.c_int32(8)
+        cand = (ctypes.c_int32 * 8)()
+        ms = (ctypes.c_double * 8)()
+        _check(N.lib().dfjk_autotune(self._h, _ptr(C), int(nocc), PRECISION[precision], _ptr(scr), scr.numel(),
+                                     _stream_handle(stream), ctypes.byref(chosen), ctypes.byref(ncand), cand, ms))
+        self._scratch = {}          # build sizes may have changed
+        return chosen.value, {int(cand[i]): float(ms[i]) for i in range(ncand.value)}
+
     def offload(self, stream=None):
         """Move B to page-locked host memory (dfjk_offload); later builds stream
         it back slab by slab.  Frees the device setup workspace."""

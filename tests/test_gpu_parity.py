@@ -410,3 +410,18 @@ def test_host_resident_B_matches_device_B(cluster5, slab):
     assert e.value.status == "UNSUPPORTED"
     host.close()
     dev.close()
+
+
+def test_autotuned_split_count(cluster5):
+    """The autotuner keeps one of its candidates; builds then use it and still
+    agree with the oracle."""
+    d = cluster5
+    plan = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU).screen().setup()
+    chosen, times = plan.autotune(d["C"])
+    assert chosen in times and len(times) >= 2 and all(t > 0 for t in times.values())
+    print("split candidates (ms per build):", times, "chosen", chosen)
+    J, K, E = (t.cpu().numpy() for t in plan.build(C=d["C"]))
+    assert rel(K, d["ref"]["K"]) <= 1e-10
+    J2, K2, E2 = (t.cpu().numpy() for t in plan.build(C=d["C"]))
+    assert np.array_equal(K, K2)
+    plan.close()
