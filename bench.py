@@ -343,7 +343,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the DF-J/K build would shard).", file=sys.stderr)
+              "(the build would shard over aux slabs with one all-reduce of J and K).", file=sys.stderr)
         sys.exit(2)
     if args.serve_sweep:
         # Molecules of 1..64 waters: blocks above 512 MB are never split, so a

@@ -125,7 +125,7 @@ def test_build_host_rejects_bad_input_before_device_work():
 
 
 def test_no_device_is_reported(monkeypatch):
-    """On a machine without a GPU the device calls say so (skipped on a GPU machine)."""
+    """On a machine without a GPU the device calls say so (skipped where a GPU is present)."""
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is visible")
