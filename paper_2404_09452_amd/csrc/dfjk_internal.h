@@ -87,6 +87,9 @@ struct Plan {
     int64_t host_slab = 0;
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr}, ev_start = nullptr;
+    // second stream of the overlapped half transform and its events
+    hipStream_t ht_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_ht[2] = {nullptr, nullptr}, ev_kdone[2] = {nullptr, nullptr};
     // split counts chosen by dfjk_autotune for the closed-shell C-route build,
     // keyed by nocc * 4 + precision
     std::map<int64_t, int> tuned_nsplit;
@@ -197,11 +200,13 @@ struct BuildLayout {
     // offsets into the scratch
     size_t o_D, o_d, o_cpart, o_c, o_X, o_Xlo, o_Bfull, o_X2, o_X2lo, o_U, o_W, o_Kpart, o_Epart, o_Da, o_Db;
     size_t o_stage[2];                  // staging of host-resident B slabs
+    bool overlap;                       // half transform of the next slab beside the K GEMM
+    size_t o_Xb, o_Xblo;                // the second X buffer of the overlapped schedule
 };
 // nsplit: 0 = the autotuned count when there is one, else the built-in
 // choice; -1 = the built-in choice; > 0 = that count (capped by the length)
 BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta = false,
-                         int nsplit = 0);
+                         int nsplit = 0, bool allow_overlap = true);
 int batch_nsplit(const Plan *const *plans, int n);
 void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const double *const *C, double *const *J,
                         double *const *K, double *const *E, char *const *scratch, hipStream_t s);

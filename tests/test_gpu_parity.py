@@ -304,7 +304,10 @@ def test_batch_matches_single_builds(batch_set, prec):
             assert rel(K, K1) <= 1e-13
             assert abs(E[1] - E1[1]) <= 1e-13 * abs(E1[1])
         else:
-            assert np.array_equal(K, K1) and E[1] == E1[1]
+            # the batch contracts one aux slab where a single build may use two
+            # (overlapped), which moves the FP32 chunk boundaries
+            assert rel(K, K1) <= 1e-6
+            assert abs(E[1] - E1[1]) <= 1e-6 * abs(E1[1])
     if prec == "fp64":   # one molecule against the oracle
         mol, _, C = cases[2]
         ref = oracle.dfjk(mol, C=C)

@@ -141,11 +141,13 @@ def test_batched_serving_matches_requests_alone():
         mol = W.make_molecule(z, x)
         S = W.overlap_by_quadrature(mol)
         C0 = W.occupied_orbitals(S, mol.nelec // 2, rid)
-        orbs = [W.perturbed_orbitals(C0, S, k, seed=91 + rid) for k in range(4)]
+        orbs = [W.perturbed_orbitals(C0, S, k, seed=91 + rid) for k in range(8)]
         return Request(rid=rid, mol=mol, orbitals=orbs, arrival=arrival)
 
-    sizes = [2, 1, 4, 3, 1, 6, 2]
-    mix = [make(i, n, 0.003 * i) for i, n in enumerate(sizes)]
+    # all queued at once, 8 builds each, so later requests join while earlier
+    # ones are still building
+    sizes = [4, 2, 6, 3, 2, 8, 5]
+    mix = [make(i, n, 0.0) for i, n in enumerate(sizes)]
     ex = BatchedGpuExecutor()
     srv = Server(ex, max_active=4, hbm_budget_bytes=8 << 30)
     srv.serve(mix)
