@@ -527,12 +527,12 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     // automatic: the largest multiple of 128 whose slab-sized buffers (X, its low part,
     // the expanded B of the density route, the second operand of the increment) stay
     // within kAutoSlabBytes
-    // Overlapped slabs (C route): the half transform of slab s + 1 runs on a
-    // second stream while the K GEMM of slab s runs, into the other of two X
-    // buffers.  An FP64 build of at least 2,048 aux functions that would fit
-    // one slab is cut into two (measured: 1.5% faster at 2,816 aux; the
-    // mixed kernels and smaller molecules lose more to the second launch
-    // than the overlap gains).
+    // Overlapped slabs (C route): when the K build needs several aux slabs, the
+    // half transform of slab s + 1 runs on a second stream while the K GEMM of
+    // slab s runs, into the other of two X buffers (the automatic slab is
+    // sized for both).  A molecule that fits one slab is not cut in two: at
+    // 2,816 aux that saved 1.5% of an FP64 build, lost 3% in FP32, and the
+    // GEMM shares the chip with the half transform while they overlap.
     const bool may_overlap = allow_overlap && !with_D && !delta && !p.host_B && p.naux_pad >= 2 * kPadAux;
     const double per_aux = (double)p.nao * L.ncol *
                            ((double)esz + (precision == DFJK_MIXED_BF16X3 ? 2 : 0) + (with_D ? 8 : 0)) *
@@ -542,8 +542,6 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
                                   : (int64_t)(kAutoSlabBytes / per_aux) / kPadAux * kPadAux;
     if (slab < kPadAux) slab = kPadAux;
     if (slab > p.naux_pad) slab = p.naux_pad;
-    if (may_overlap && p.aux_slab == 0 && slab >= p.naux_pad && precision == DFJK_FP64 && p.naux_pad >= 2048)
-        slab = (int64_t)align_up((size_t)(p.naux_pad + 1) / 2, kPadAux);
     L.slab = slab;
     L.nslab = (p.naux_pad + slab - 1) / slab;
     L.overlap = may_overlap && L.nslab >= 2;
