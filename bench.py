@@ -167,6 +167,8 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
            "max_active": max_active, "hbm_budget_GB": round(budget / 1e9, 1)}
     for mode in modes:
         prec, batched = mode.split("+")[0], mode.endswith("+batched")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()            # each mode starts from the same allocator state
 
         def reqs(arrivals):
             return [Request(rid=i, mol=pool[int(n)][0], orbitals=pool[int(n)][1], arrival=float(a),
@@ -197,6 +199,8 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
         if sat["errors"]:
             r["saturation_errors"] = sat["errors"]
         for load in loads:
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
             arr, _ = W.poisson_stream(nreq, load * mu, seed, 1, nmax)
             srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget,
                          on_done=progress("load %.2f" % load))
