@@ -32,6 +32,7 @@ NBUILDS = 10
 PEAK_F64_TFLOPS = 78.6
 PEAK_F32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
+PEAK_HBM_BYTES = 8.0e12
 
 
 def committed_traffic():
@@ -85,6 +86,16 @@ def run_job(Plan, mol, Cd, precision, bufs, profile):
     return plan, outs
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(mol, Cs, target_s=20.0):
     """The FP64 oracle on a bounded sample of the same job, scaled to builds/s.
 
@@ -126,6 +137,7 @@ def cpu_baseline(mol, Cs, target_s=20.0):
         "value": NBUILDS / total,
         "unit": "builds/s",
         "cores": int(oracle.num_threads()),
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
         "sample": ("water32 job (setup + 10 builds) timed on a sample: int3c for every 22nd aux shell "
                    "(x%.1f), full metric and Cholesky, forward substitution of %d of %d pair columns, "
@@ -435,6 +447,27 @@ def main():
                 "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": committed_traffic(),
                 "traffic_source": "profiles/k_gemm_f64_water32.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, per launch)",
                 "flops_per_launch": k_flops / k_launches, "ms_per_launch": k_ms, "launches_per_build": k_launches}
+    # the other steps of an FP64 build against their bounds (HIP-event stage times;
+    # algorithmic bytes: J reads B twice, the half transform reads B twice and
+    # writes X once)
+    scr = f64["screening"]
+    nf, npad = scr["nf"], -(-naux // 128) * 128
+    b_bytes = float(nf) * npad * 8
+    j_ms = f64["stages_ms_per_launch"]["build.J"]
+    ht_ms = f64["stages_ms_per_launch"]["build.halftransform"]
+    ht_bytes = 2 * b_bytes + float(nao) * npad * nocc * 8
+    by_step = {
+        "J": {"bound": "hbm", "bytes": 2 * b_bytes, "ms": j_ms,
+              "GB_per_s": round(2 * b_bytes / (j_ms * 1e-3) / 1e9, 1),
+              "frac": round(2 * b_bytes / (j_ms * 1e-3) / PEAK_HBM_BYTES, 4)},
+        "halftransform": {"bound": "hbm", "bytes": ht_bytes, "ms": ht_ms,
+                          "GB_per_s": round(ht_bytes / (ht_ms * 1e-3) / 1e9, 1),
+                          "frac": round(ht_bytes / (ht_ms * 1e-3) / PEAK_HBM_BYTES, 4)},
+        "K": {"bound": "mfma", "frac": roofline["frac"]},
+        "int3c": {"bound": "fp64 valu", "ms_per_setup": f64["stages_ms_per_launch"].get("setup.int3c"),
+                  "shell_triplets": scr["triplets_kept"],
+                  "note": "FP64 VALU fraction from counters: profiles/water128_int3c_and_k.md"},
+    }
     for prec, peak in (("fp32", PEAK_F32_TFLOPS), ("bf16x3", PEAK_BF16_TFLOPS / 3.0)):
         if prec in results:
             n_l = results[prec]["stage_launches"]["build.K"] / (args.steps * NBUILDS)
@@ -489,6 +522,7 @@ def main():
         "serving": serving,
         "water128": large,
         "autotune_K_split": autotune,
+        "roofline_by_step": by_step,
         "fp64_detail": {k: v for k, v in f64.items() if k not in ("E_J", "E_K")},
         "device": torch.cuda.get_device_name(0),
     }
