@@ -145,7 +145,11 @@ int dfjk_setup(dfjk_plan *plan, void *d_workspace, size_t bytes, void *stream);
  *   d_D: nao x nao symmetric density (nocc ignored; precision must be FP64).
  * Outputs: d_J, d_K (nao x nao, full symmetric), d_E[2] = {E_J, E_K}.
  * d_scratch must hold dfjk_build_bytes(plan, nocc, precision, d_D != NULL).
- * No host synchronisation; safe to capture in a HIP graph. */
+ * No host synchronisation; safe to capture in a HIP graph.  When the K build
+ * needs several aux slabs (C route), the half transform of the next slab runs
+ * on a second stream owned by the plan, forked from and joined back into
+ * `stream`; such builds of one plan must not run concurrently on different
+ * streams. */
 int dfjk_build_bytes(const dfjk_plan *plan, int32_t nocc, int32_t precision,
                      int32_t with_density, size_t *bytes);
 int dfjk_build(dfjk_plan *plan, const double *d_C, int32_t nocc, const double *d_D,
