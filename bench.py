@@ -398,9 +398,12 @@ def main():
         print("bench: timing %d steps, %s" % (args.steps, prec), file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         stage_ms, stage_n = {}, {}
+        step_ms = []
         for s in range(args.steps):
+            ts = time.perf_counter()
             plan, outs = run_job(Plan, mol, Cd, prec, bufs, profile=True)
             torch.cuda.synchronize()
+            step_ms.append(1000.0 * (time.perf_counter() - ts))
             for k, (ms, n) in plan.profile_read().items():
                 stage_ms[k] = stage_ms.get(k, 0.0) + ms
                 stage_n[k] = stage_n.get(k, 0) + n
@@ -415,6 +418,8 @@ def main():
         r = {
             "builds_per_s": NBUILDS * args.steps / dt,
             "ms_per_step": 1000.0 * dt / args.steps,
+            "ms_per_step_median": float(np.median(step_ms)),
+            "ms_per_step_min": float(np.min(step_ms)),
             "ms_per_build_steady": build_ms,
             "setup_ms": setup_ms,
             "stages_ms_per_launch": {k: round(stage_ms[k] / max(stage_n[k], 1), 4) for k in stage_ms},
@@ -506,6 +511,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(f64["ms_per_step"], 3),
+        "ms_per_step_median": round(f64["ms_per_step_median"], 3),
+        "ms_per_step_min": round(f64["ms_per_step_min"], 3),
         "ms_per_build": round(f64["ms_per_build_steady"], 3),
         "setup_ms": round(f64["setup_ms"], 3),
         "higher_is_better": True,
