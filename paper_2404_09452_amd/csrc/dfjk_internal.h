@@ -114,6 +114,7 @@ struct Plan {
     std::vector<double> f_w;
     // half-transform lists: for AO function mu, entries hk_off[mu]..hk_off[mu+1]
     std::vector<int32_t> hk_off, hk_row, hk_nu;
+    std::vector<int32_t> hk_order;      // AO functions by descending list length
 
     // ---- resident device workspace (after setup) ----
     char *ws = nullptr;
@@ -128,7 +129,7 @@ struct Plan {
         double *sp_q;
         int32_t *f_mu, *f_nu;
         double *f_w;
-        int32_t *hk_off, *hk_row, *hk_nu;
+        int32_t *hk_off, *hk_row, *hk_nu, *hk_order;
         const double *boys;
         double *U, *B, *V, *L, *Linv;
         int32_t *status;

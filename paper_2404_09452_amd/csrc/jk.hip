@@ -140,6 +140,7 @@ struct HTArgs {
     void *X;                  // [nao][plen][ncol]: aux rows p_begin .. p_begin + plen - 1
     void *Xlo;                // second plane for the BF16 split
     int64_t p_begin, plen;    // aux slab (multiples of 128)
+    const int32_t *order;     // blockIdx.y -> AO function (longest list first)
 };
 
 
@@ -172,7 +173,7 @@ void k_halftrans(HTArgs g)
     constexpr int NLA = KC * 128 / 2 / NT;              // double2 loads per thread per chunk (B) = 2
     __shared__ double Cs[2][KC * LDC];
     __shared__ double As[2][KC * LDA];
-    const int mu = blockIdx.y;
+    const int mu = g.order[blockIdx.y];
     const int64_t p0 = g.p_begin + (int64_t)blockIdx.x * 128;
     const int ic0 = blockIdx.z * NCOL;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -617,7 +618,7 @@ static void launch_j(Plan &p, const BuildLayout &L, const double *D, double *J, 
 static void launch_ht(const Plan &p, int precision, const double *C, int32_t ncol, int64_t p_begin, int64_t plen,
                       void *X, void *Xlo, hipStream_t s)
 {
-    HTArgs h{p.d.B, p.naux_pad, C, ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen};
+    HTArgs h{p.d.B, p.naux_pad, C, ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen, p.d.hk_order};
     if (precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, p.nao, s);
     else if (precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, p.nao, s);
     else launch_halftrans<OUT_BF16X2>(h, p.nao, s);
@@ -1012,7 +1013,8 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
                                p.d.f_mu, p.d.f_nu, p.d.f_w, p.nf, nao, 1, J);
         pr.mark(ST_J, false);
         pr.mark(ST_HALFTRANS, true);
-        HTArgs h{stage[b], plen, C, (int32_t)L.ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, 0, plen};
+        HTArgs h{stage[b], plen, C, (int32_t)L.ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, 0, plen,
+                 p.d.hk_order};
         if (L.precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, nao, s);
         else if (L.precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, nao, s);
         else launch_halftrans<OUT_BF16X2>(h, nao, s);
