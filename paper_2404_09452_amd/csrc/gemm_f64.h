@@ -58,6 +58,8 @@ __device__ __forceinline__ void tile_coords(const GemmArgs &g, int t, int &tm, i
     } else {
         tm = t % g.ntm;
         tn = t / g.ntm;
+        // with tri_k a tile's k range grows with tn: issue the longest first
+        if (g.tri_k) tn = g.ntn - 1 - tn;
     }
 }
 
