@@ -336,7 +336,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--serve-max-waters", type=int, default=32)
     ap.add_argument("--no-large", action="store_true", help="skip the 128-water leg")
     ap.add_argument("--serve-modes", default="fp64,fp64+batched,bf16x3_incr")
