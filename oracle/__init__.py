@@ -20,6 +20,14 @@ K = 2 sum_{P,i} X_{P,mu i} X_{P,nu i}.  None of these formulas appears in the
 paper (GPU4PySCF v1.0), which only names the method (Introduction; Section
 "Dataset and Performance"); they are the standard Coulomb-metric fitting
 (Whitten 1973; Vahtras, Almloef and Feyereisen 1993).
+
+For the four-centre direct path (the direct-SCF J/K that the paper's
+package started from, Introduction; "Limitations and Future Development:
+Direct SCF & Other Integral Schemes") the oracle gives the
+unfitted definitions J_{mu nu} = sum (mu nu|la si) D_{la si} and
+K_{mu nu} = sum (mu la|nu si) D_{la si}: dense for tiny systems
+(``exact_jk``) and one shell-pair block at a time for large ones
+(``exact_jk_blocks``), both unscreened.
 """
 from __future__ import annotations
 
@@ -50,6 +58,8 @@ def lib():
                                 ctypes.c_int, ctypes.c_int, dp]
         L.orc_int2c.argtypes = [dp, ctypes.c_int, ip, ip, dp, dp]
         L.orc_int4c.argtypes = [dp, ctypes.c_int, ip, ip, dp, dp]
+        L.orc_jk_blocks.argtypes = [dp, ctypes.c_int, ip, ip, dp, dp, ctypes.c_int, ip, ip,
+                                    ctypes.POINTER(ctypes.c_long), dp, dp]
         L.orc_overlap.argtypes = [dp, ctypes.c_int, ip, ip, dp, dp]
         L.orc_cholesky.argtypes = [ctypes.c_long, dp, dp]
         L.orc_cholesky.restype = ctypes.c_long
@@ -235,6 +245,32 @@ def dfjk_uks(mol, Ca, Cb):
     """Unrestricted DF-J/K for a molecule (unscreened)."""
     B, _ = whitened_3c(mol)
     return uks_from_B(B, Ca, Cb)
+
+
+def exact_jk_blocks(mol, D, shell_pairs):
+    """Exact (unfitted, unscreened) J and K blocks for the AO shell pairs
+    (a, c) listed, from the four-centre definitions
+    J_{mu nu} = sum_{la si} (mu nu|la si) D_{la si} and
+    K_{mu nu} = sum_{la si} (mu la|nu si) D_{la si}, mu in shell a, nu in c.
+    Returns two lists of (2l_a+1, 2l_c+1) arrays.  The cost per block is one
+    pass over every shell pair of the basis, so this reaches single blocks of
+    molecules far too large for the dense tensor."""
+    n, a, l, e = _basis(mol.ao_atom, mol.ao_l, mol.ao_exp)
+    pairs = np.asarray(shell_pairs, dtype=np.int32).reshape(-1, 2)
+    ra = np.ascontiguousarray(pairs[:, 0]); rc = np.ascontiguousarray(pairs[:, 1])
+    sizes = (2 * mol.ao_l[ra] + 1) * (2 * mol.ao_l[rc] + 1)
+    boff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    J = np.zeros(int(boff[-1])); K = np.zeros(int(boff[-1]))
+    xyz = np.ascontiguousarray(mol.coords, np.float64)
+    Dc = np.ascontiguousarray(D, np.float64)
+    rc_ = lib().orc_jk_blocks(_d(xyz), n, _i(a), _i(l), _d(e), _d(Dc), len(pairs), _i(ra), _i(rc),
+                              boff[:-1].ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _d(J), _d(K))
+    if rc_:
+        raise ValueError("angular momentum or shell index out of range")
+    shp = [(2 * int(mol.ao_l[x]) + 1, 2 * int(mol.ao_l[y]) + 1) for x, y in pairs]
+    Js = [J[boff[k]:boff[k + 1]].reshape(shp[k]) for k in range(len(pairs))]
+    Ks = [K[boff[k]:boff[k + 1]].reshape(shp[k]) for k in range(len(pairs))]
+    return Js, Ks
 
 
 def exact_jk(mol, D):

@@ -448,6 +448,77 @@ int orc_int4c(const double *coords, int nsh, const int *atom, const int *l, cons
     return 0;
 }
 
+/* Exact (unfitted, unscreened) J and K blocks at chosen shell pairs, from the
+ * definitions J_{mu nu} = sum_{la si} (mu nu|la si) D_{la si} and
+ * K_{mu nu} = sum_{la si} (mu la|nu si) D_{la si} over every shell of the
+ * basis.  D is nao x nao (row-major, used as given).  Request k asks for
+ * the block of shells (ra[k], rc[k]); its (2l_a+1) x (2l_c+1) values go to
+ * J and K at offset boff[k], row-major. */
+int orc_jk_blocks(const double *coords, int nsh, const int *atom, const int *l, const double *expo,
+                  const double *D, int nreq, const int *ra, const int *rc, const long *boff, double *J, double *K)
+{
+    for (int i = 0; i < nsh; i++) if (l[i] < 0 || l[i] > LMAX) return 1;
+    for (int k = 0; k < nreq; k++) if (ra[k] < 0 || ra[k] >= nsh || rc[k] < 0 || rc[k] >= nsh) return 2;
+    int *o = offsets(nsh, l);
+    long n = o[nsh];
+    for (int k = 0; k < nreq; k++) {
+        const int a = ra[k], c = rc[k];
+        const int na = 2 * l[a] + 1, nc = 2 * l[c] + 1;
+        double *Jb = J + boff[k], *Kb = K + boff[k];
+        for (int i = 0; i < na * nc; i++) { Jb[i] = 0.0; Kb[i] = 0.0; }
+#pragma omp parallel
+        {
+            double *work = (double *)malloc(sizeof(double) * WORK_DOUBLES);
+            double *Rb = (double *)malloc(sizeof(double) * RBUF_DOUBLES);
+            double *cart = (double *)malloc(sizeof(double) * BLK);
+            double *sph = (double *)malloc(sizeof(double) * BLK);
+            double *jl = (double *)calloc((size_t)na * nc, sizeof(double));
+            double *kl = (double *)calloc((size_t)na * nc, sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+            for (int b = 0; b < nsh; b++) {
+                const int nb = 2 * l[b] + 1;
+                Dist dab, dac;
+                make_dist(&dab, l[a], expo[a], coords + 3 * atom[a], l[b], expo[b], coords + 3 * atom[b]);
+                make_dist(&dac, l[a], expo[a], coords + 3 * atom[a], l[c], expo[c], coords + 3 * atom[c]);
+                for (int d = 0; d < nsh; d++) {
+                    const int nd = 2 * l[d] + 1;
+                    /* J: (a c | b d) D_bd */
+                    Dist dbd;
+                    make_dist(&dbd, l[b], expo[b], coords + 3 * atom[b], l[d], expo[d], coords + 3 * atom[d]);
+                    coulomb_cart(&dac, &dbd, cart, Rb, work);
+                    int lj[4] = {l[a], l[c], l[b], l[d]};
+                    double ej[4] = {expo[a], expo[c], expo[b], expo[d]};
+                    sph_transform4(cart, sph, lj, ej);
+                    for (int i = 0; i < na; i++)
+                        for (int j = 0; j < nc; j++)
+                            for (int x = 0; x < nb; x++)
+                                for (int y = 0; y < nd; y++)
+                                    jl[i * nc + j] += sph[((i * nc + j) * nb + x) * nd + y] *
+                                                      D[(o[b] + x) * n + o[d] + y];
+                    /* K: (a b | c d) D_bd */
+                    Dist dcd;
+                    make_dist(&dcd, l[c], expo[c], coords + 3 * atom[c], l[d], expo[d], coords + 3 * atom[d]);
+                    coulomb_cart(&dab, &dcd, cart, Rb, work);
+                    int lk[4] = {l[a], l[b], l[c], l[d]};
+                    double ek[4] = {expo[a], expo[b], expo[c], expo[d]};
+                    sph_transform4(cart, sph, lk, ek);
+                    for (int i = 0; i < na; i++)
+                        for (int x = 0; x < nb; x++)
+                            for (int j = 0; j < nc; j++)
+                                for (int y = 0; y < nd; y++)
+                                    kl[i * nc + j] += sph[((i * nb + x) * nc + j) * nd + y] *
+                                                      D[(o[b] + x) * n + o[d] + y];
+                }
+            }
+#pragma omp critical
+            for (int i = 0; i < na * nc; i++) { Jb[i] += jl[i]; Kb[i] += kl[i]; }
+            free(work); free(Rb); free(cart); free(sph); free(jl); free(kl);
+        }
+    }
+    free(o);
+    return 0;
+}
+
 /* Overlap S_{mu nu} = (pi/p)^{3/2} E^x_0 E^y_0 E^z_0, normalised, spherical. */
 int orc_overlap(const double *coords, int nsh, const int *atom, const int *l, const double *expo,
                 double *out)

@@ -140,3 +140,51 @@ def ssss(a, A, b, B, c, C, d, D):
     al = p * q / (p + q)
     return (n(a) * n(b) * n(c) * n(d) * 2 * math.pi ** 2.5 / (p * q * math.sqrt(p + q))
             * kab * kcd * boys0(al * np.sum((P - Q) ** 2)))
+
+
+def _dir_integrals4(exps, cents, lmax, t):
+    """Per-direction 2-D integrals for a bra pair (a@A, b@B) and a ket pair
+    (c@C, d@D): out[i][j][k][l][tidx] = int int (x1-A)^i (x1-B)^j (x2-C)^k (x2-D)^l
+    exp(-a(x1-A)^2 - b(x1-B)^2 - c(x2-C)^2 - d(x2-D)^2 - t^2 (x1-x2)^2)."""
+    a, b, c, d = exps
+    A, B, C, D = cents
+    la, lb, lc, ld = lmax
+    t2 = t * t
+    nt = len(t)
+    M = np.zeros((nt, 2, 2))
+    M[:, 0, 0] = a + b + t2
+    M[:, 0, 1] = M[:, 1, 0] = -t2
+    M[:, 1, 1] = c + d + t2
+    h = np.array([a * A + b * B, c * C + d * D])
+    Minv = np.linalg.inv(M)
+    xs = Minv @ h
+    const = a * A * A + b * B * B + c * C * C + d * D * D - np.einsum("i,tij,j->t", h, Minv, h)
+    G = np.linalg.cholesky(M)
+    Ginv_T = np.linalg.inv(np.transpose(G, (0, 2, 1)))
+    det = G[:, 0, 0] * G[:, 1, 1]
+    y1, y2 = np.meshgrid(_GH_T, _GH_T, indexing="ij")
+    wy = np.outer(_GH_W, _GH_W).ravel()
+    Y = np.stack([y1.ravel(), y2.ravel()])
+    X = xs[:, :, None] + Ginv_T @ Y[None]
+    x1, x2 = X[:, 0, :], X[:, 1, :]
+    base = np.exp(-const)[:, None] / det[:, None] * wy[None, :]
+    out = np.zeros((la + 1, lb + 1, lc + 1, ld + 1, nt))
+    for i, j, k, l in itertools.product(range(la + 1), range(lb + 1), range(lc + 1), range(ld + 1)):
+        out[i, j, k, l] = np.sum(base * (x1 - A) ** i * (x1 - B) ** j * (x2 - C) ** k * (x2 - D) ** l, axis=1)
+    return out
+
+
+def coulomb4c_block(la, a, A, lb, b, B, lc, c, C, ld, d, D):
+    """(ab|cd) spherical block (2la+1, 2lb+1, 2lc+1, 2ld+1) of unit-normalised functions."""
+    A, B, C, D = (np.asarray(v, float) for v in (A, B, C, D))
+    per_dir = [_dir_integrals4((a, b, c, d), (A[x], B[x], C[x], D[x]), (la, lb, lc, ld), _T) for x in range(3)]
+    ms = [monomials(l) for l in (la, lb, lc, ld)]
+    cart = np.zeros(tuple(len(m) for m in ms))
+    for idx in itertools.product(*[range(len(m)) for m in ms]):
+        e = [ms[k][idx[k]] for k in range(4)]
+        f = np.ones_like(_T)
+        for x in range(3):
+            f = f * per_dir[x][e[0][x], e[1][x], e[2][x], e[3][x]]
+        cart[idx] = 2.0 / math.sqrt(math.pi) * np.sum(f * _TW)
+    cs = [shape_coefficients(l) * sph_norms(l, g)[:, None] for l, g in ((la, a), (lb, b), (lc, c), (ld, d))]
+    return np.einsum("wi,xj,yk,zl,ijkl->wxyz", *cs, cart)

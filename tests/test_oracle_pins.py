@@ -183,6 +183,63 @@ def test_int3c_shell_order_reversal():
     assert np.abs(Ur - U[:, perm][:, :, perm]).max() <= 1e-13 * np.abs(U).max()
 
 
+@pytest.mark.parametrize("la,lb,lc,ld", [(1, 0, 0, 0), (0, 0, 1, 1), (1, 1, 1, 0), (2, 0, 1, 1),
+                                         (2, 1, 2, 0), (2, 2, 1, 1), (1, 2, 2, 2)])
+def test_int4c_against_t_quadrature(la, lb, lc, ld):
+    """Four-centre blocks on four distinct centres against the quadrature,
+    which shares neither the Boys function nor the Hermite recursions."""
+    cen = [[0.2, -0.1, 0.3], [1.1, 0.6, -0.5], [-0.4, 0.9, 0.7], [0.5, -0.6, -0.2]]
+    ex = [1.4, 0.55, 0.95, 2.1]
+    ls = [la, lb, lc, ld]
+    mol = _mol([(k, ls[k], ex[k]) for k in range(4)], [(0, 0, 1.0)], cen)
+    eri = oracle.int4c(mol)
+    o = np.concatenate([[0], np.cumsum([2 * l + 1 for l in ls])])
+    got = eri[o[0]:o[1], o[1]:o[2], o[2]:o[3], o[3]:o[4]]
+    ref = brute.coulomb4c_block(la, ex[0], cen[0], lb, ex[1], cen[1], lc, ex[2], cen[2], ld, ex[3], cen[3])
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_int4c_permutation_symmetry(water):
+    mol, _, _ = water
+    eri = oracle.int4c(mol)
+    for perm in [(1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1)]:
+        assert np.abs(eri - eri.transpose(perm)).max() <= 1e-13 * np.abs(eri).max()
+
+
+def test_exact_jk_blocks_equal_dense_definition(water):
+    """The block routine (one pass over every shell pair per block) against
+    the dense tensor contracted by einsum, on every block of the monomer."""
+    mol, _, C = water
+    D = oracle.density(C)
+    J, K, _, _ = oracle.exact_jk(mol, D)
+    off = np.concatenate([[0], np.cumsum(2 * mol.ao_l + 1)])
+    ns = len(mol.ao_l)
+    pairs = [(a, c) for a in range(ns) for c in range(ns)]
+    Js, Ks = oracle.exact_jk_blocks(mol, D, pairs)
+    for (a, c), jb, kb in zip(pairs, Js, Ks):
+        assert np.abs(jb - J[off[a]:off[a + 1], off[c]:off[c + 1]]).max() <= 1e-13 * np.abs(J).max()
+        assert np.abs(kb - K[off[a]:off[a + 1], off[c]:off[c + 1]]).max() <= 1e-13 * np.abs(K).max()
+
+
+def test_exact_jk_structure(water):
+    """J and K symmetric, K positive semidefinite for D = 2 C C^T, E_J > 0,
+    E_K < 0, and both linear in D."""
+    mol, _, C = water
+    D = oracle.density(C)
+    J, K, EJ, EK = oracle.exact_jk(mol, D)
+    assert np.abs(J - J.T).max() <= 1e-13 * np.abs(J).max()
+    assert np.abs(K - K.T).max() <= 1e-13 * np.abs(K).max()
+    assert np.linalg.eigvalsh(0.5 * (K + K.T)).min() >= -1e-12 * np.abs(K).max()
+    assert EJ > 0 and EK < 0
+    rng = np.random.default_rng(5)
+    M = rng.standard_normal(D.shape)
+    D2 = M + M.T
+    J2, K2, _, _ = oracle.exact_jk(mol, D2)
+    J3, K3, _, _ = oracle.exact_jk(mol, 0.5 * D - 2.0 * D2)
+    assert np.abs(J3 - (0.5 * J - 2.0 * J2)).max() <= 1e-12 * np.abs(J3).max()
+    assert np.abs(K3 - (0.5 * K - 2.0 * K2)).max() <= 1e-12 * np.abs(K3).max()
+
+
 def test_int2c_equals_int3c_with_flat_partner():
     """(P|Q) is (P s_eps|Q) / N_0(eps) for a vanishing-exponent s partner."""
     coords = [[0, 0, 0], [0.7, -0.2, 0.5], [-0.3, 0.8, 0.1]]
