@@ -252,6 +252,41 @@ int dfjk_build_uks(dfjk_plan *plan, const double *d_Ca, int32_t nocc_a, const do
                    int32_t nocc_b, int32_t precision, double *d_J, double *d_Ka, double *d_Kb,
                    double *d_E, void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* Four-centre direct J/K: the exact (unfitted) Coulomb and exchange matrices
+ *   J_{mu nu} = sum_{la si} (mu nu|la si) D_{la si},
+ *   K_{mu nu} = sum_{la si} (mu la|nu si) D_{la si},
+ * from two-electron integrals over shell quartets, computed on the fly
+ * (direct SCF: the integral path the package began with, paper,
+ * Introduction; "Limitations and Future Development: Direct SCF & Other
+ * Integral Schemes").  Needs a screened plan only (no dfjk_setup): a shell
+ * pair is kept if Q_ab max Q_cd >= schwarz_thresh and a quartet is computed
+ * iff Q_ab Q_cd >= schwarz_thresh (Schwarz bound on |(ab|cd)|).
+ *
+ * dfjk_direct_bytes gives the size of the pair tables; dfjk_direct_setup
+ * fills them (product centres, exponents and the Hermite expansion of every
+ * function pair) on the device.  The tables stay borrowed until the plan is
+ * destroyed or set up again and must not be touched meanwhile.  Synchronises
+ * `stream`.
+ *
+ * dfjk_direct_build takes exactly one of
+ *   d_C: nao x nocc occupied orbitals (D = 2 C C^T), 1 <= nocc <= nao, or
+ *   d_D: nao x nao symmetric density (nocc ignored),
+ * and writes d_J, d_K (nao x nao, full symmetric, must not alias) and
+ * d_E[2] = {E_J, E_K} = {1/2 Tr(D J), -1/4 Tr(D K)}.  FP64 throughout; K is
+ * accumulated with atomics, so its last bits may differ between runs.
+ * d_scratch must hold dfjk_direct_build_bytes(plan, d_D != NULL).  No host
+ * synchronisation; safe to capture in a HIP graph.
+ *
+ * dfjk_direct_stats: kept pairs per class (s-s, p-s, p-p, d-s, d-p, d-d) in
+ * pairs[6] and the number of (bra pair, ket pair) combinations that pass the
+ * screen. */
+int dfjk_direct_bytes(const dfjk_plan *plan, size_t *table_bytes);
+int dfjk_direct_setup(dfjk_plan *plan, void *d_tables, size_t bytes, void *stream);
+int dfjk_direct_stats(const dfjk_plan *plan, int64_t *pairs, int64_t *quartets);
+int dfjk_direct_build_bytes(const dfjk_plan *plan, int32_t with_density, size_t *bytes);
+int dfjk_direct_build(dfjk_plan *plan, const double *d_C, int32_t nocc, const double *d_D, double *d_J,
+                      double *d_K, double *d_E, void *d_scratch, size_t scratch_bytes, void *stream);
+
 /* Diagnostics for tests (valid after setup).  Dense copies of intermediate
  * quantities in the caller's function order:
  *   DFJK_EXPORT_INT3C   (naux x nao x nao) unwhitened (mu nu|P), screened

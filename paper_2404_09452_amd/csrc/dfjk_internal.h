@@ -54,6 +54,38 @@ enum Stage {
     ST_COUNT
 };
 
+// One angular class (la >= lb) of the shell pairs of the four-centre direct
+// path, as the kernels read it.  Pairs are sorted by descending Schwarz
+// factor; entries at and past n are padding.  The Hermite expansion of every
+// function pair f = (ma, mb) of pair i is stored twice:
+//   Eb[(f * NH + h) * npad + i]         bra layout (pair index fastest)
+//   Ek[(i * NF + f) * NH + h]           ket layout, times (-1)^{t+u+v}
+// with NF = (2la+1)(2lb+1), NH the Hermite indices (t,u,v) of order <= la+lb.
+struct DirectClassDev {
+    int32_t n = 0, npad = 0;
+    const int32_t *off_a = nullptr, *off_b = nullptr;   // first AO function of each shell
+    const int32_t *sh_a = nullptr, *sh_b = nullptr;     // shell indices
+    const double *q = nullptr;                          // Schwarz factor
+    const double *px = nullptr, *py = nullptr, *pz = nullptr, *p = nullptr;   // product centre, exponent
+    const double *Eb = nullptr, *Ek = nullptr;
+    int64_t herm_off = 0;   // first double of this class in the per-build Hermite buffers
+};
+
+// Host and device state of the four-centre direct path (after dfjk_direct_setup).
+struct DirectState {
+    bool ready = false;
+    std::vector<int32_t> sa[6], sb[6];   // shell pairs per class, orientation la >= lb
+    std::vector<double> q[6];
+    DirectClassDev cls[6];
+    int64_t herm_total = 0;              // doubles of one Hermite buffer (all classes)
+    int64_t quartets = 0;                // (bra, ket) pair combinations that pass the screen
+    size_t table_bytes = 0;
+    char *tables = nullptr;
+    const int32_t *fn_shell = nullptr;   // AO function -> shell (device)
+    const double *boys = nullptr;
+    int device = -1;
+};
+
 struct Profiler {
     bool on = false;
     std::vector<hipEvent_t> pool;       // created on demand, destroyed with the plan
@@ -117,6 +149,9 @@ struct Plan {
     std::vector<int32_t> hk_off, hk_row, hk_nu;
     std::vector<int32_t> hk_order;      // AO functions by descending list length
 
+    // ---- four-centre direct path ----
+    DirectState dir;
+
     // ---- resident device workspace (after setup) ----
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -176,6 +211,9 @@ void launch_schwarz_aux(int32_t nsh, const ShellsDev &ax, double *q, hipStream_t
 void launch_int3c(const Plan &p, hipStream_t s);
 void launch_int2c(const Plan &p, hipStream_t s);
 void upload_constants(const double coef[kMaxLAux + 1][7][10], hipStream_t s);
+// Pair tables of the direct path: for each class, px..p, Eb and Ek from the
+// shell lists already in the tables and the AO shell arrays.
+void launch_direct_pairs(const DirectClassDev *cls, const ShellsDev &ao, hipStream_t s);
 
 // linalg.hip
 void launch_metric_pad(double *V, int64_t n, int64_t npad, hipStream_t s);
@@ -219,6 +257,17 @@ void launch_build_uks(Plan &p, const BuildLayout &L, const double *Ca, const dou
                       double *Kb, double *E, char *scratch, hipStream_t s);
 void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *J, double *K, double *E,
                         char *scratch, hipStream_t s);
+
+// direct.hip: four-centre direct J/K.  Scratch: the density (C route), the
+// Hermite density and Hermite J buffers, and the energy partials.
+struct DirectLayout {
+    bool with_D;
+    size_t o_D, o_Dh, o_Jh, o_Epart, bytes;
+};
+DirectLayout direct_layout(const Plan &p, bool with_D);
+void launch_direct_build(const Plan &p, const DirectLayout &L, const double *C, int32_t nocc, const double *D,
+                         double *J, double *K, double *E, char *scratch, hipStream_t s);
+void launch_density(const double *C, int64_t nao, int32_t nocc, double scale, double *D, hipStream_t s);
 
 // export.hip
 void launch_zero(double *p, int64_t n, hipStream_t s);

@@ -1,0 +1,416 @@
+// Four-centre direct J/K on gfx950: exact (unfitted) Coulomb and exchange
+// from Schwarz-screened two-electron integrals over shell quartets, the
+// direct-SCF path the package began with (paper, Introduction; "Limitations
+// and Future Development: Direct SCF & Other Integral Schemes").  The paper's
+// kernels use Rys quadrature; here the integrals are McMurchie-Davidson on
+// the Hermite tables the three-centre kernels already use, in the split that
+// gives a J-engine for Coulomb:
+//
+//   (ab|cd) = pref sum_h E^{ab}_f[h] sum_k (-1)^{|k|} E^{cd}_g[k] R_{h+k}(alpha, P - Q),
+//   pref = 2 pi^{5/2} / (p q sqrt(p+q)),  alpha = p q / (p+q).
+//
+// J.  With the ket density in Hermite form, Dh_cd[k] = w (-1)^{|k|} sum_g E^{cd}_g[k] D_g
+// (w = 2 for c != d: both orders of the pair), every quartet adds
+// pref sum_k R_{h+k} Dh_cd[k] to a Hermite J vector Jh_ab[h] of the bra pair,
+// which a thread keeps in registers over its ket loop; J_f = sum_h E^{ab}_f[h] Jh_ab[h].
+//
+// K.  K_{mu nu} = sum (mu la|nu si) D_{la si}.  A visit of bra pair {a,b}
+// and ket pair {c,d} forms the integral block and adds its contractions
+// to the blocks K_ac (with D_bd), K_ad (D_bc), K_bc (D_ad) and K_bd (D_ac),
+// leaving out the duplicates of a = b or c = d.  Every ordered (bra, ket)
+// combination of pairs is visited, so the block K_xy (x in {a,b}, y in
+// {c,d}) of shells x > y also arrives, transposed, from the visit with bra
+// and ket swapped: only blocks with shell x >= y are written (FP64 atomics)
+// and the upper triangle is mirrored at the end.
+//
+// Mapping.  One wave of 64 lanes per launch block; lane = bra pair of one
+// class, pairs sorted by descending Schwarz factor.  The ket loop (pairs of
+// one class, also sorted) is the same for every lane, so its data are
+// uniform loads, and it stops for the whole wave at the first ket pair with
+// Q_cd * Q_max(wave) below the threshold; lanes whose own bound fails sit
+// out that iteration.  blockIdx.y splits the ket range so that a launch has
+// enough waves to fill the chip; the Hermite J vectors of the splits are
+// summed with FP64 atomics.
+#include "dfjk_internal.h"
+#include "hermite.h"
+
+namespace dfjk {
+
+DirectLayout direct_layout(const Plan &p, bool with_D)
+{
+    DirectLayout L{};
+    L.with_D = with_D;
+    size_t off = 0;
+    auto take = [&](size_t b) { off = align_up(off, 256); size_t o = off; off += b; return o; };
+    L.o_D = with_D ? 0 : take((size_t)p.nao * p.nao * 8);
+    L.o_Dh = take((size_t)std::max<int64_t>(p.dir.herm_total, 1) * 8);
+    L.o_Jh = take((size_t)std::max<int64_t>(p.dir.herm_total, 1) * 8);
+    L.o_Epart = take((size_t)2 * 256 * 8);
+    L.bytes = align_up(off, 256);
+    return L;
+}
+
+__global__ void k_dfill(double *p, int64_t n, double v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static void dfill(double *p, int64_t n, hipStream_t s)
+{
+    const int64_t nb = std::min<int64_t>((n + 255) / 256, 4096);
+    if (n > 0) hipLaunchKernelGGL(k_dfill, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256), 0, s, p, n, 0.0);
+}
+
+// Hermite density of every pair of one class (ket layout, signed).
+template <int LA, int LB>
+__global__ __launch_bounds__(128) void k_dherm(DirectClassDev c, const double *__restrict__ D, int64_t nao,
+                                               double *__restrict__ Dh)
+{
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, LAB = LA + LB, NH = nherm(LAB);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n) return;
+    const int oa = c.off_a[i], ob = c.off_b[i];
+    const bool same = c.sh_a[i] == c.sh_b[i];
+    double d[NA * NB];
+#pragma unroll
+    for (int ma = 0; ma < NA; ++ma)
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) {
+            const double v = D[(int64_t)(oa + ma) * nao + ob + mb];
+            d[ma * NB + mb] = same ? v : v + D[(int64_t)(ob + mb) * nao + oa + ma];
+        }
+    double *out = Dh + c.herm_off + (int64_t)i * NH;
+#pragma unroll
+    for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+        for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+            for (int v = 0; v + u + t <= LAB; ++v) {
+                const int h = hidx(t, u, v);
+                double s = 0.0;
+#pragma unroll
+                for (int f = 0; f < NA * NB; ++f) s += c.Eb[(int64_t)(f * NH + h) * c.npad + i] * d[f];
+                out[h] = ((t + u + v) & 1) ? -s : s;
+            }
+}
+
+// The integral kernel for bra class (LA, LB) and ket class (LC, LD).
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDev ket, int32_t kchunk, double tau,
+                                               const double *__restrict__ boys_tab, const double *__restrict__ D,
+                                               int64_t nao, const double *__restrict__ Dh, double *__restrict__ Jh,
+                                               double *__restrict__ K, int32_t with_k)
+{
+    constexpr int LAB = LA + LB, LCD = LC + LD, L = LAB + LCD;
+    constexpr int NHB = nherm(LAB), NHK = nherm(LCD);
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1, ND = 2 * LD + 1;
+    constexpr int NFB = NA * NB, NFK = NC * ND;
+    // Small bra classes: the rows of a unrolled and the bra Hermite table kept
+    // in registers over the ket loop; larger ones loop over the rows of a at
+    // run time and read the table (cached) per use.
+    constexpr int kUnrollA = NFB <= 3 ? NA : 1;
+    constexpr bool kHoist = NFB <= 3;
+
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const bool valid = i < bra.n;
+    const int j0 = blockIdx.y * kchunk;
+    const int j1 = min(ket.n, j0 + kchunk);
+    if (j0 >= j1) return;
+    const double qwave = bra.q[blockIdx.x * 64];    // largest bound of this wave
+    if (!(ket.q[j0] * qwave >= tau)) return;
+
+    const int ic = valid ? i : blockIdx.x * 64;
+    const double qa = bra.q[ic];
+    const double p = bra.p[ic], Px = bra.px[ic], Py = bra.py[ic], Pz = bra.pz[ic];
+    const int oa = bra.off_a[ic], ob = bra.off_b[ic], sa = bra.sh_a[ic], sb = bra.sh_b[ic];
+    const bool ab_same = sa == sb;
+
+    double ebr[kHoist ? NFB * NHB : 1];
+    if constexpr (kHoist) {
+#pragma unroll
+        for (int x = 0; x < NFB * NHB; ++x) ebr[x] = bra.Eb[(int64_t)x * bra.npad + ic];
+    }
+    double jh[NHB];
+#pragma unroll
+    for (int h = 0; h < NHB; ++h) jh[h] = 0.0;
+    bool any = false;
+
+    for (int j = j0; j < j1; ++j) {
+        const double qc = ket.q[j];
+        if (!(qc * qwave >= tau)) break;
+        if (!(valid && qa * qc >= tau)) continue;
+        any = true;
+        const double q = ket.p[j];
+        const double X = Px - ket.px[j], Y = Py - ket.py[j], Z = Pz - ket.pz[j];
+        const double pq = p + q, alpha = p * q / pq;
+        double F[L + 1];
+        boys<L>(alpha * (X * X + Y * Y + Z * Z), F, boys_tab);
+        double R[nherm(L)];
+        hermite_R<L>(alpha, X, Y, Z, F, R);
+        const double pref = kTwoPi52 / (p * q * sqrt(pq));
+
+        // Coulomb: Jh[h] += pref sum_k R[h + k] Dh[k]
+        const double *dh = Dh + ket.herm_off + (int64_t)j * NHK;
+        double dk[NHK];
+#pragma unroll
+        for (int k = 0; k < NHK; ++k) dk[k] = dh[k];
+#pragma unroll
+        for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+            for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+                for (int v = 0; v + u + t <= LAB; ++v) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int t2 = 0; t2 <= LCD; ++t2)
+#pragma unroll
+                        for (int u2 = 0; u2 + t2 <= LCD; ++u2)
+#pragma unroll
+                            for (int v2 = 0; v2 + u2 + t2 <= LCD; ++v2)
+                                s += R[hidx(t + t2, u + u2, v + v2)] * dk[hidx(t2, u2, v2)];
+                    jh[hidx(t, u, v)] += pref * s;
+                }
+        if (!with_k) continue;
+
+        // Exchange
+        const int oc = ket.off_a[j], od = ket.off_b[j], sc = ket.sh_a[j], sd = ket.sh_b[j];
+        const bool cd_same = sc == sd;
+        const bool w_ac = sa >= sc, w_ad = !cd_same && sa >= sd;
+        const bool w_bc = !ab_same && sb >= sc, w_bd = !ab_same && !cd_same && sb >= sd;
+        if (!(w_ac || w_ad || w_bc || w_bd)) continue;
+        const double *ek = ket.Ek + (int64_t)j * NFK * NHK;
+        // rows of b: accumulated over every ma; rows of a: one row per ma
+        double kbc[NB][NC], kbd[NB][ND], dbc[NB][NC], dbd[NB][ND];
+#pragma unroll
+        for (int x = 0; x < NB; ++x) {
+#pragma unroll
+            for (int y = 0; y < NC; ++y) { kbc[x][y] = 0.0; dbc[x][y] = D[(int64_t)(ob + x) * nao + oc + y]; }
+#pragma unroll
+            for (int y = 0; y < ND; ++y) { kbd[x][y] = 0.0; dbd[x][y] = D[(int64_t)(ob + x) * nao + od + y]; }
+        }
+#pragma unroll kUnrollA
+        for (int ma = 0; ma < NA; ++ma) {
+            double kac[NC], kad[ND], dac[NC], dad[ND];
+#pragma unroll
+            for (int y = 0; y < NC; ++y) { kac[y] = 0.0; dac[y] = D[(int64_t)(oa + ma) * nao + oc + y]; }
+#pragma unroll
+            for (int y = 0; y < ND; ++y) { kad[y] = 0.0; dad[y] = D[(int64_t)(oa + ma) * nao + od + y]; }
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb) {
+                const int f = ma * NB + mb;
+                // V[k] = sum_h E_f[h] R[h + k]
+                double V[NHK];
+#pragma unroll
+                for (int k = 0; k < NHK; ++k) V[k] = 0.0;
+#pragma unroll
+                for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+                    for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+                        for (int v = 0; v + u + t <= LAB; ++v) {
+                            const int h = hidx(t, u, v);
+                            double e;
+                            if constexpr (kHoist) e = ebr[f * NHB + h];
+                            else e = bra.Eb[(int64_t)(f * NHB + h) * bra.npad + ic];
+#pragma unroll
+                            for (int t2 = 0; t2 <= LCD; ++t2)
+#pragma unroll
+                                for (int u2 = 0; u2 + t2 <= LCD; ++u2)
+#pragma unroll
+                                    for (int v2 = 0; v2 + u2 + t2 <= LCD; ++v2)
+                                        V[hidx(t2, u2, v2)] += e * R[hidx(t + t2, u + u2, v + v2)];
+                        }
+#pragma unroll
+                for (int mc = 0; mc < NC; ++mc)
+#pragma unroll
+                    for (int md = 0; md < ND; ++md) {
+                        const int g = mc * ND + md;
+                        double I = 0.0;
+#pragma unroll
+                        for (int k = 0; k < NHK; ++k) I += ek[g * NHK + k] * V[k];
+                        I *= pref;
+                        kac[mc] += I * dbd[mb][md];
+                        kad[md] += I * dbc[mb][mc];
+                        kbc[mb][mc] += I * dad[md];
+                        kbd[mb][md] += I * dac[mc];
+                    }
+            }
+            if (w_ac)
+#pragma unroll
+                for (int y = 0; y < NC; ++y) unsafeAtomicAdd(&K[(int64_t)(oa + ma) * nao + oc + y], kac[y]);
+            if (w_ad)
+#pragma unroll
+                for (int y = 0; y < ND; ++y) unsafeAtomicAdd(&K[(int64_t)(oa + ma) * nao + od + y], kad[y]);
+        }
+        if (w_bc)
+#pragma unroll
+            for (int x = 0; x < NB; ++x)
+#pragma unroll
+                for (int y = 0; y < NC; ++y) unsafeAtomicAdd(&K[(int64_t)(ob + x) * nao + oc + y], kbc[x][y]);
+        if (w_bd)
+#pragma unroll
+            for (int x = 0; x < NB; ++x)
+#pragma unroll
+                for (int y = 0; y < ND; ++y) unsafeAtomicAdd(&K[(int64_t)(ob + x) * nao + od + y], kbd[x][y]);
+    }
+    if (valid && any) {
+#pragma unroll
+        for (int h = 0; h < NHB; ++h)
+            unsafeAtomicAdd(&Jh[bra.herm_off + (int64_t)h * bra.npad + i], jh[h]);
+    }
+}
+
+// J_f = sum_h E_f[h] Jh[h] for every pair of one class, written to both
+// triangles (one triangle's positions for a = b: the block holds both).
+template <int LA, int LB>
+__global__ __launch_bounds__(128) void k_jout(DirectClassDev c, const double *__restrict__ Jh, int64_t nao,
+                                              double *__restrict__ J)
+{
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NH = nherm(LA + LB);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n) return;
+    const int oa = c.off_a[i], ob = c.off_b[i];
+    const bool same = c.sh_a[i] == c.sh_b[i];
+    double jh[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) jh[h] = Jh[c.herm_off + (int64_t)h * c.npad + i];
+#pragma unroll
+    for (int ma = 0; ma < NA; ++ma)
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) {
+            const int f = ma * NB + mb;
+            double s = 0.0;
+#pragma unroll
+            for (int h = 0; h < NH; ++h) s += c.Eb[(int64_t)(f * NH + h) * c.npad + i] * jh[h];
+            J[(int64_t)(oa + ma) * nao + ob + mb] = s;
+            if (!same) J[(int64_t)(ob + mb) * nao + oa + ma] = s;
+        }
+}
+
+// Symmetrise J (mean of the two triangles), complete K from its lower shell
+// triangle (mean on diagonal shell blocks) and form the block partials of
+// sum D.J and sum D.K over the lower triangle mu >= nu.
+__global__ __launch_bounds__(256) void k_direct_finish(int64_t nao, const int32_t *__restrict__ fn_shell,
+                                                       const double *__restrict__ D, double *__restrict__ J,
+                                                       double *__restrict__ K, double *__restrict__ Epart)
+{
+    const int64_t ntri = nao * (nao + 1) / 2;
+    double ej = 0.0, ek = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ntri; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t mu = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+        while (mu * (mu + 1) / 2 > e) --mu;
+        while ((mu + 1) * (mu + 2) / 2 <= e) ++mu;
+        const int64_t nu = e - mu * (mu + 1) / 2;
+        const int64_t a = mu * nao + nu, b = nu * nao + mu;
+        const double jv = mu == nu ? J[a] : 0.5 * (J[a] + J[b]);
+        const double kv = (fn_shell[mu] == fn_shell[nu] && mu != nu) ? 0.5 * (K[a] + K[b]) : K[a];
+        J[a] = jv; J[b] = jv;
+        K[a] = kv; K[b] = kv;
+        const double dw = mu == nu ? D[a] : D[a] + D[b];
+        ej += dw * jv;
+        ek += dw * kv;
+    }
+    __shared__ double sj[256], sk[256];
+    sj[threadIdx.x] = ej; sk[threadIdx.x] = ek;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) { sj[threadIdx.x] += sj[threadIdx.x + w]; sk[threadIdx.x] += sk[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { Epart[blockIdx.x] = sj[0]; Epart[256 + blockIdx.x] = sk[0]; }
+}
+
+// E_J = 1/2 sum D.J, E_K = -1/4 sum D.K from the 256 block partials, in a fixed order.
+__global__ __launch_bounds__(256) void k_direct_energy(const double *__restrict__ Epart, double *__restrict__ E)
+{
+    __shared__ double sj[256], sk[256];
+    sj[threadIdx.x] = Epart[threadIdx.x]; sk[threadIdx.x] = Epart[256 + threadIdx.x];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) { sj[threadIdx.x] += sj[threadIdx.x + w]; sk[threadIdx.x] += sk[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { E[0] = 0.5 * sj[0]; E[1] = -0.25 * sk[0]; }
+}
+
+template <int LA, int LB, int LC, int LD>
+static void launch_quartets(const DirectClassDev &bra, const DirectClassDev &ket, double tau, const double *boys,
+                            const double *D, int64_t nao, const double *Dh, double *Jh, double *K, hipStream_t s)
+{
+    const int gx = (bra.n + 63) / 64;
+    // enough blocks to fill the chip: split the ket range, at least 16 pairs per split
+    const int want = std::max(1, (8192 + gx - 1) / gx);
+    const int nchunk = std::max(1, std::min(want, (ket.n + 15) / 16));
+    const int kchunk = (ket.n + nchunk - 1) / nchunk;
+    const int gy = (ket.n + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL((k_direct<LA, LB, LC, LD>), dim3((unsigned)gx, (unsigned)gy), dim3(64), 0, s, bra, ket, kchunk,
+                       tau, boys, D, nao, Dh, Jh, K, 1);
+}
+
+template <int LA, int LB>
+static void launch_bra(const DirectClassDev *cls, double tau, const double *boys, const double *D, int64_t nao,
+                       const double *Dh, double *Jh, double *K, hipStream_t s)
+{
+    const DirectClassDev &b = cls[LA == 0 ? 0 : (LA == 1 ? 1 + LB : 3 + LB)];
+    if (b.n <= 0) return;
+    if (cls[0].n > 0) launch_quartets<LA, LB, 0, 0>(b, cls[0], tau, boys, D, nao, Dh, Jh, K, s);
+    if (cls[1].n > 0) launch_quartets<LA, LB, 1, 0>(b, cls[1], tau, boys, D, nao, Dh, Jh, K, s);
+    if (cls[2].n > 0) launch_quartets<LA, LB, 1, 1>(b, cls[2], tau, boys, D, nao, Dh, Jh, K, s);
+    if (cls[3].n > 0) launch_quartets<LA, LB, 2, 0>(b, cls[3], tau, boys, D, nao, Dh, Jh, K, s);
+    if (cls[4].n > 0) launch_quartets<LA, LB, 2, 1>(b, cls[4], tau, boys, D, nao, Dh, Jh, K, s);
+    if (cls[5].n > 0) launch_quartets<LA, LB, 2, 2>(b, cls[5], tau, boys, D, nao, Dh, Jh, K, s);
+}
+
+template <int LA, int LB>
+static void launch_pair_pass(const DirectClassDev &c, const double *D, int64_t nao, double *Dh, const double *Jh,
+                             double *J, bool jout, hipStream_t s)
+{
+    if (c.n <= 0) return;
+    const dim3 grid((unsigned)((c.n + 127) / 128));
+    if (jout) hipLaunchKernelGGL((k_jout<LA, LB>), grid, dim3(128), 0, s, c, Jh, nao, J);
+    else hipLaunchKernelGGL((k_dherm<LA, LB>), grid, dim3(128), 0, s, c, D, nao, Dh);
+}
+
+static void pair_passes(const DirectClassDev *cls, const double *D, int64_t nao, double *Dh, const double *Jh,
+                        double *J, bool jout, hipStream_t s)
+{
+    launch_pair_pass<0, 0>(cls[0], D, nao, Dh, Jh, J, jout, s);
+    launch_pair_pass<1, 0>(cls[1], D, nao, Dh, Jh, J, jout, s);
+    launch_pair_pass<1, 1>(cls[2], D, nao, Dh, Jh, J, jout, s);
+    launch_pair_pass<2, 0>(cls[3], D, nao, Dh, Jh, J, jout, s);
+    launch_pair_pass<2, 1>(cls[4], D, nao, Dh, Jh, J, jout, s);
+    launch_pair_pass<2, 2>(cls[5], D, nao, Dh, Jh, J, jout, s);
+}
+
+void launch_direct_build(const Plan &p, const DirectLayout &L, const double *C, int32_t nocc, const double *Din,
+                         double *J, double *K, double *E, char *scratch, hipStream_t s)
+{
+    const int64_t nao = p.nao;
+    const DirectState &ds = p.dir;
+    const double *D = Din;
+    if (!L.with_D) {
+        double *Dw = reinterpret_cast<double *>(scratch + L.o_D);
+        launch_density(C, nao, nocc, 2.0, Dw, s);
+        D = Dw;
+    }
+    double *Dh = reinterpret_cast<double *>(scratch + L.o_Dh);
+    double *Jh = reinterpret_cast<double *>(scratch + L.o_Jh);
+    double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
+    dfill(J, nao * nao, s);
+    dfill(K, nao * nao, s);
+    dfill(Jh, ds.herm_total, s);
+    pair_passes(ds.cls, D, nao, Dh, nullptr, nullptr, false, s);
+    const double tau = p.thresh;
+    launch_bra<0, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
+    launch_bra<1, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
+    launch_bra<1, 1>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
+    launch_bra<2, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
+    launch_bra<2, 1>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
+    launch_bra<2, 2>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
+    pair_passes(ds.cls, D, nao, Dh, Jh, J, true, s);
+    hipLaunchKernelGGL(k_direct_finish, dim3(256), dim3(256), 0, s, nao, ds.fn_shell, D, J, K, Epart);
+    hipLaunchKernelGGL(k_direct_energy, dim3(1), dim3(256), 0, s, Epart, E);
+}
+
+}  // namespace dfjk

@@ -432,6 +432,71 @@ void launch_int3c(const Plan &p, hipStream_t s)
 }
 
 // --------------------------------------------------------------------------
+// Pair tables of the four-centre direct path.  For pair i of class (LA, LB)
+// (shells a, b): p = a + b, P = (aA + bB)/p and, for every function pair
+// f = (ma, mb), the spherical Hermite expansion
+//   E_f[tuv] = N_a N_b sum_{ca,cb} s_a[ma][ca] s_b[mb][cb] E^x E^y E^z,
+// so that (ab|cd) = 2 pi^{5/2} / (p q sqrt(p+q))
+//                   sum_{tuv} E_f[tuv] sum_{t'u'v'} (-1)^{t'+u'+v'} E_g[t'u'v'] R_{t+t',u+u',v+v'}.
+
+template <int LA, int LB>
+__global__ __launch_bounds__(128) void k_direct_pairs(DirectClassDev c, ShellsDev ao, double *px, double *py,
+                                                      double *pz, double *pp, double *Eb, double *Ek)
+{
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NF = NA * NB, LAB = LA + LB, NH = nherm(LAB);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n) return;
+    const int a = c.sh_a[i], b = c.sh_b[i];
+    const double ea = ao.exp[a], eb = ao.exp[b];
+    const double Ax = ao.x[a], Ay = ao.y[a], Az = ao.z[a], Bx = ao.x[b], By = ao.y[b], Bz = ao.z[b];
+    const double p = ea + eb, ip = 1.0 / p;
+    const double Px = (ea * Ax + eb * Bx) * ip, Py = (ea * Ay + eb * By) * ip, Pz = (ea * Az + eb * Bz) * ip;
+    const double mu = ea * eb * ip;
+    double Ex[LA + 1][LB + 1][LAB + 1], Ey[LA + 1][LB + 1][LAB + 1], Ez[LA + 1][LB + 1][LAB + 1];
+    hermite_E<LA, LB>(Px - Ax, Px - Bx, 0.5 * ip, exp(-mu * (Ax - Bx) * (Ax - Bx)), Ex);
+    hermite_E<LA, LB>(Py - Ay, Py - By, 0.5 * ip, exp(-mu * (Ay - By) * (Ay - By)), Ey);
+    hermite_E<LA, LB>(Pz - Az, Pz - Bz, 0.5 * ip, exp(-mu * (Az - Bz) * (Az - Bz)), Ez);
+    px[i] = Px; py[i] = Py; pz[i] = Pz; pp[i] = p;
+    const double nn = ao.norm[a] * ao.norm[b];
+    for (int ma = 0; ma < NA; ++ma)
+        for (int mb = 0; mb < NB; ++mb) {
+            const int f = ma * NB + mb;
+            double Es[NH];
+            bra_sph<LA, LB>(ma, mb, Ex, Ey, Ez, Es);
+#pragma unroll
+            for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+                for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+                    for (int v = 0; v + u + t <= LAB; ++v) {
+                        const int h = hidx(t, u, v);
+                        const double e = nn * Es[h];
+                        Eb[(int64_t)(f * NH + h) * c.npad + i] = e;
+                        Ek[((int64_t)i * NF + f) * NH + h] = ((t + u + v) & 1) ? -e : e;
+                    }
+        }
+}
+
+void launch_direct_pairs(const DirectClassDev *cls, const ShellsDev &ao, hipStream_t s)
+{
+    for (int k = 0; k < 6; ++k) {
+        const DirectClassDev &c = cls[k];
+        if (c.n <= 0) continue;
+        const dim3 grid((unsigned)((c.n + 127) / 128));
+        double *px = const_cast<double *>(c.px), *py = const_cast<double *>(c.py), *pz = const_cast<double *>(c.pz);
+        double *pp = const_cast<double *>(c.p), *Eb = const_cast<double *>(c.Eb), *Ek = const_cast<double *>(c.Ek);
+        switch (k) {
+        case 0: hipLaunchKernelGGL((k_direct_pairs<0, 0>), grid, dim3(128), 0, s, c, ao, px, py, pz, pp, Eb, Ek); break;
+        case 1: hipLaunchKernelGGL((k_direct_pairs<1, 0>), grid, dim3(128), 0, s, c, ao, px, py, pz, pp, Eb, Ek); break;
+        case 2: hipLaunchKernelGGL((k_direct_pairs<1, 1>), grid, dim3(128), 0, s, c, ao, px, py, pz, pp, Eb, Ek); break;
+        case 3: hipLaunchKernelGGL((k_direct_pairs<2, 0>), grid, dim3(128), 0, s, c, ao, px, py, pz, pp, Eb, Ek); break;
+        case 4: hipLaunchKernelGGL((k_direct_pairs<2, 1>), grid, dim3(128), 0, s, c, ao, px, py, pz, pp, Eb, Ek); break;
+        default: hipLaunchKernelGGL((k_direct_pairs<2, 2>), grid, dim3(128), 0, s, c, ao, px, py, pz, pp, Eb, Ek); break;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // Two-centre metric (P|Q), both sides solid harmonic (Hobson on each):
 // (c|d) = N_c N_d 2 pi^{5/2}/(g d sqrt(g+d)) (2g)^{-lc} (-1)^{ld} (2d)^{-ld}
 //         sum_{k,k'} s_c(k) s_d(k') R_{k+k'}(alpha, C-D).

@@ -55,6 +55,12 @@ __global__ __launch_bounds__(256) void k_density(const double *__restrict__ C, i
     if (m0 + ty < nao && n0 + tx < nao) D[(m0 + ty) * nao + n0 + tx] = scale * s;
 }
 
+void launch_density(const double *C, int64_t nao, int32_t nocc, double scale, double *D, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_density, dim3((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16)), dim3(256), 0, s,
+                       C, nao, nocc, scale, D);
+}
+
 __global__ void k_add(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
                       double *__restrict__ out)
 {

@@ -74,6 +74,7 @@ class Plan:
         self._h = h
         self._ws = None
         self._scratch = {}
+        self._dscratch = {}
         inf = self.info()
         self.nao, self.naux = inf["nao"], inf["naux"]
 
@@ -273,6 +274,53 @@ class Plan:
         _check(N.lib().dfjk_sample(self._h, int(kind), n, _ptr(idx), _ptr(out), _stream_handle(stream)))
         return out
 
+    # -- four-centre direct J/K ---------------------------------------------
+    def direct_setup(self, stream=None):
+        """Pair tables of the four-centre direct path (needs screen(), not setup())."""
+        n = ctypes.c_size_t()
+        _check(N.lib().dfjk_direct_bytes(self._h, ctypes.byref(n)))
+        self._dtables = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+        _check(N.lib().dfjk_direct_setup(self._h, _ptr(self._dtables), self._dtables.numel(), _stream_handle(stream)))
+        self._dscratch = {}
+        return self
+
+    def direct_stats(self):
+        """Kept shell pairs per class (ss, ps, pp, ds, dp, dd) and the screened
+        (bra pair, ket pair) combinations."""
+        pairs = (ctypes.c_int64 * 6)()
+        q = ctypes.c_int64()
+        _check(N.lib().dfjk_direct_stats(self._h, pairs, ctypes.byref(q)))
+        return {"pairs": [int(x) for x in pairs], "quartets": int(q.value)}
+
+    def direct_build(self, C=None, D=None, out=None, stream=None):
+        """Exact J, K and E = [E_J, E_K] from four-centre integrals (FP64);
+        give exactly one of C (nao x nocc, D = 2 C C^T) and D (symmetric)."""
+        if (C is None) == (D is None):
+            raise ValueError("give exactly one of C and D")
+        dev = torch.device("cuda")
+        withD = D is not None
+        X = torch.as_tensor(D if withD else C, dtype=torch.float64, device=dev).contiguous()
+        if withD and tuple(X.shape) != (self.nao, self.nao):
+            raise ValueError("D must be (nao, nao)")
+        if not withD and (X.dim() != 2 or X.shape[0] != self.nao):
+            raise ValueError("C must be (nao, nocc)")
+        nocc = 0 if withD else X.shape[1]
+        if out is None:
+            J = torch.empty((self.nao, self.nao), dtype=torch.float64, device=dev)
+            K = torch.empty_like(J)
+            E = torch.empty(2, dtype=torch.float64, device=dev)
+        else:
+            J, K, E = out
+        if withD not in self._dscratch:
+            n = ctypes.c_size_t()
+            _check(N.lib().dfjk_direct_build_bytes(self._h, int(withD), ctypes.byref(n)))
+            self._dscratch[withD] = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        scr = self._dscratch[withD]
+        _check(N.lib().dfjk_direct_build(self._h, ctypes.c_void_p(0) if withD else _ptr(X), int(nocc),
+                                         _ptr(X) if withD else ctypes.c_void_p(0), _ptr(J), _ptr(K), _ptr(E),
+                                         _ptr(scr), scr.numel(), _stream_handle(stream)))
+        return J, K, E
+
     def close(self):
         if getattr(self, "_h", None):
             N.lib().dfjk_plan_destroy(self._h)
@@ -281,6 +329,8 @@ class Plan:
         self._scratch = {}
         self._host_B = None
         self._tables = None
+        self._dtables = None
+        self._dscratch = {}
 
     def __del__(self):
         try:

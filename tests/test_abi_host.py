@@ -97,6 +97,18 @@ def test_call_order_is_enforced_without_device():
                               ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(8), ctypes.c_void_p(8),
                               1 << 20, None) == 7
     assert lib.dfjk_build_uks_bytes(plan._h, 3, 2, 0, ctypes.byref(n)) == 7
+    # four-centre direct path: tables need a screened plan, builds need tables
+    assert lib.dfjk_direct_bytes(plan._h, ctypes.byref(n)) == 7
+    assert lib.dfjk_direct_setup(plan._h, ctypes.c_void_p(8), 1 << 20, None) == 7
+    assert b"screen" in lib.dfjk_last_error()
+    assert lib.dfjk_direct_build_bytes(plan._h, 0, ctypes.byref(n)) == 7
+    assert lib.dfjk_direct_build(plan._h, ctypes.c_void_p(8), 5, None, ctypes.c_void_p(8), ctypes.c_void_p(16),
+                                 ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 20, None) == 7
+    assert b"direct_setup" in lib.dfjk_last_error()
+    pairs = (ctypes.c_int64 * 6)()
+    q = ctypes.c_int64()
+    assert lib.dfjk_direct_stats(plan._h, pairs, ctypes.byref(q)) == 7
+    assert lib.dfjk_direct_stats(plan._h, None, ctypes.byref(q)) == 1
     hs = (ctypes.c_void_p * 1)(plan._h.value)
     nocc = (ctypes.c_int32 * 1)(5)
     assert lib.dfjk_build_batch_bytes(1, hs, nocc, 0, ctypes.byref(n)) == 7     # not screened
