@@ -23,12 +23,15 @@
 // and ket swapped: only blocks with shell x >= y are written (FP64 atomics)
 // and the upper triangle is mirrored at the end.
 //
-// Mapping.  One wave of 64 lanes per launch block; lane = bra pair of one
-// class, pairs sorted by descending Schwarz factor.  The ket loop (pairs of
-// one class, also sorted) is the same for every lane, so its data are
-// uniform loads, and it stops for the whole wave at the first ket pair with
-// Q_cd * Q_max(wave) below the threshold; lanes whose own bound fails sit
-// out that iteration.  blockIdx.y splits the ket range so that a launch has
+// Mapping.  One wave of 64 lanes per launch block.  Light quartet classes:
+// lane = bra pair of one class, pairs sorted by descending Schwarz factor,
+// and the ket loop (pairs of one class, also sorted) is the same for every
+// lane, so its data are uniform loads.  Heavy classes (la+lb+lc+ld >= 5, or
+// la = 2 with few pairs: much work per quartet): a wave takes 8 bra pairs x 8 ket pairs
+// per step and blockIdx.z takes one row of the first bra shell.  The ket
+// loop stops for the whole wave at the first step whose leading ket pair
+// has Q_cd * Q_max(wave) below the threshold; lanes whose own bound fails
+// sit out that step.  blockIdx.y splits the ket range so that a launch has
 // enough waves to fill the chip; the Hermite J vectors of the splits are
 // summed with FP64 atomics.
 #include "dfjk_internal.h"
@@ -95,8 +98,22 @@ __global__ __launch_bounds__(128) void k_dherm(DirectClassDev c, const double *_
             }
 }
 
+// Shape of the work of one quartet class: the plain shape gives each lane
+// its own bra pair against a ket pair that is the same for the whole wave;
+// the tiled shape (for heavy classes: few pairs, much work per quartet) gives
+// a wave an 8 x 8 tile of (bra, ket) pairs, so that a handful of pairs still
+// fills the lanes, and splits the rows of the first bra shell over blockIdx.z.
+template <bool TILED, int LA>
+struct QuartetShape {
+    static constexpr int NA = 2 * LA + 1;
+    static constexpr bool heavy = TILED;
+    static constexpr int TK = heavy ? 8 : 1;       // ket pairs per wave iteration
+    static constexpr int TB = 64 / TK;             // bra pairs per wave
+    static constexpr bool split_a = heavy && NA > 1;
+};
+
 // The integral kernel for bra class (LA, LB) and ket class (LC, LD).
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, bool TILED>
 __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDev ket, int32_t kchunk, double tau,
                                                const double *__restrict__ boys_tab, const double *__restrict__ D,
                                                int64_t nao, const double *__restrict__ Dh, double *__restrict__ Jh,
@@ -106,21 +123,27 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
     constexpr int NHB = nherm(LAB), NHK = nherm(LCD);
     constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1, ND = 2 * LD + 1;
     constexpr int NFB = NA * NB, NFK = NC * ND;
+    using S = QuartetShape<TILED, LA>;
+    constexpr int TK = S::TK, TB = S::TB;
     // Small bra classes: the rows of a unrolled and the bra Hermite table kept
     // in registers over the ket loop; larger ones loop over the rows of a at
-    // run time and read the table (cached) per use.
+    // run time (or take one row per blockIdx.z) and read the table per use.
     constexpr int kUnrollA = NFB <= 3 ? NA : 1;
-    constexpr bool kHoist = NFB <= 3;
+    constexpr bool kHoist = NFB <= 3 && !S::split_a;
 
-    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int lane = threadIdx.x, ib = lane / TK, jk = lane % TK;
+    const int i = blockIdx.x * TB + ib;
     const bool valid = i < bra.n;
     const int j0 = blockIdx.y * kchunk;
     const int j1 = min(ket.n, j0 + kchunk);
     if (j0 >= j1) return;
-    const double qwave = bra.q[blockIdx.x * 64];    // largest bound of this wave
+    const double qwave = bra.q[blockIdx.x * TB];    // largest bound of this wave
     if (!(ket.q[j0] * qwave >= tau)) return;
+    const int ma0 = S::split_a ? (int)blockIdx.z : 0;
+    const int ma1 = S::split_a ? ma0 + 1 : NA;
+    const bool do_j = !S::split_a || blockIdx.z == 0;
 
-    const int ic = valid ? i : blockIdx.x * 64;
+    const int ic = valid ? i : blockIdx.x * TB;
     const double qa = bra.q[ic];
     const double p = bra.p[ic], Px = bra.px[ic], Py = bra.py[ic], Pz = bra.pz[ic];
     const int oa = bra.off_a[ic], ob = bra.off_b[ic], sa = bra.sh_a[ic], sb = bra.sh_b[ic];
@@ -136,10 +159,10 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
     for (int h = 0; h < NHB; ++h) jh[h] = 0.0;
     bool any = false;
 
-    for (int j = j0; j < j1; ++j) {
-        const double qc = ket.q[j];
-        if (!(qc * qwave >= tau)) break;
-        if (!(valid && qa * qc >= tau)) continue;
+    for (int jt = j0; jt < j1; jt += TK) {
+        if (!(ket.q[jt] * qwave >= tau)) break;      // the first ket of a step is its largest
+        const int j = jt + jk;
+        if (!(valid && j < j1 && qa * ket.q[j] >= tau)) continue;
         any = true;
         const double q = ket.p[j];
         const double X = Px - ket.px[j], Y = Py - ket.py[j], Z = Pz - ket.pz[j];
@@ -151,26 +174,25 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
         const double pref = kTwoPi52 / (p * q * sqrt(pq));
 
         // Coulomb: Jh[h] += pref sum_k R[h + k] Dh[k]
-        const double *dh = Dh + ket.herm_off + (int64_t)j * NHK;
-        double dk[NHK];
+        if (do_j) {
+            const double *dh = Dh + ket.herm_off + (int64_t)j * NHK;
 #pragma unroll
-        for (int k = 0; k < NHK; ++k) dk[k] = dh[k];
+            for (int t = 0; t <= LAB; ++t)
 #pragma unroll
-        for (int t = 0; t <= LAB; ++t)
+                for (int u = 0; u + t <= LAB; ++u)
 #pragma unroll
-            for (int u = 0; u + t <= LAB; ++u)
+                    for (int v = 0; v + u + t <= LAB; ++v) {
+                        double s = 0.0;
 #pragma unroll
-                for (int v = 0; v + u + t <= LAB; ++v) {
-                    double s = 0.0;
+                        for (int t2 = 0; t2 <= LCD; ++t2)
 #pragma unroll
-                    for (int t2 = 0; t2 <= LCD; ++t2)
+                            for (int u2 = 0; u2 + t2 <= LCD; ++u2)
 #pragma unroll
-                        for (int u2 = 0; u2 + t2 <= LCD; ++u2)
-#pragma unroll
-                            for (int v2 = 0; v2 + u2 + t2 <= LCD; ++v2)
-                                s += R[hidx(t + t2, u + u2, v + v2)] * dk[hidx(t2, u2, v2)];
-                    jh[hidx(t, u, v)] += pref * s;
-                }
+                                for (int v2 = 0; v2 + u2 + t2 <= LCD; ++v2)
+                                    s += R[hidx(t + t2, u + u2, v + v2)] * dh[hidx(t2, u2, v2)];
+                        jh[hidx(t, u, v)] += pref * s;
+                    }
+        }
         if (!with_k) continue;
 
         // Exchange
@@ -180,22 +202,25 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
         const bool w_bc = !ab_same && sb >= sc, w_bd = !ab_same && !cd_same && sb >= sd;
         if (!(w_ac || w_ad || w_bc || w_bd)) continue;
         const double *ek = ket.Ek + (int64_t)j * NFK * NHK;
-        // rows of b: accumulated over every ma; rows of a: one row per ma
-        double kbc[NB][NC], kbd[NB][ND], dbc[NB][NC], dbd[NB][ND];
+        // rows of b: over every ma of this thread in registers (one row of a
+        // per thread: flushed per mb instead)
+        double kbc[S::split_a ? 1 : NB][NC], kbd[S::split_a ? 1 : NB][ND];
+        if constexpr (!S::split_a) {
 #pragma unroll
-        for (int x = 0; x < NB; ++x) {
+            for (int x = 0; x < NB; ++x) {
 #pragma unroll
-            for (int y = 0; y < NC; ++y) { kbc[x][y] = 0.0; dbc[x][y] = D[(int64_t)(ob + x) * nao + oc + y]; }
+                for (int y = 0; y < NC; ++y) kbc[x][y] = 0.0;
 #pragma unroll
-            for (int y = 0; y < ND; ++y) { kbd[x][y] = 0.0; dbd[x][y] = D[(int64_t)(ob + x) * nao + od + y]; }
+                for (int y = 0; y < ND; ++y) kbd[x][y] = 0.0;
+            }
         }
 #pragma unroll kUnrollA
-        for (int ma = 0; ma < NA; ++ma) {
-            double kac[NC], kad[ND], dac[NC], dad[ND];
+        for (int ma = ma0; ma < ma1; ++ma) {
+            double kac[NC], kad[ND];
 #pragma unroll
-            for (int y = 0; y < NC; ++y) { kac[y] = 0.0; dac[y] = D[(int64_t)(oa + ma) * nao + oc + y]; }
+            for (int y = 0; y < NC; ++y) kac[y] = 0.0;
 #pragma unroll
-            for (int y = 0; y < ND; ++y) { kad[y] = 0.0; dad[y] = D[(int64_t)(oa + ma) * nao + od + y]; }
+            for (int y = 0; y < ND; ++y) kad[y] = 0.0;
 #pragma unroll
             for (int mb = 0; mb < NB; ++mb) {
                 const int f = ma * NB + mb;
@@ -221,6 +246,11 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
                                     for (int v2 = 0; v2 + u2 + t2 <= LCD; ++v2)
                                         V[hidx(t2, u2, v2)] += e * R[hidx(t + t2, u + u2, v + v2)];
                         }
+                double rbc[NC], rbd[ND];
+#pragma unroll
+                for (int y = 0; y < NC; ++y) rbc[y] = 0.0;
+#pragma unroll
+                for (int y = 0; y < ND; ++y) rbd[y] = 0.0;
 #pragma unroll
                 for (int mc = 0; mc < NC; ++mc)
 #pragma unroll
@@ -230,11 +260,24 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
 #pragma unroll
                         for (int k = 0; k < NHK; ++k) I += ek[g * NHK + k] * V[k];
                         I *= pref;
-                        kac[mc] += I * dbd[mb][md];
-                        kad[md] += I * dbc[mb][mc];
-                        kbc[mb][mc] += I * dad[md];
-                        kbd[mb][md] += I * dac[mc];
+                        kac[mc] += I * D[(int64_t)(ob + mb) * nao + od + md];
+                        kad[md] += I * D[(int64_t)(ob + mb) * nao + oc + mc];
+                        rbc[mc] += I * D[(int64_t)(oa + ma) * nao + od + md];
+                        rbd[md] += I * D[(int64_t)(oa + ma) * nao + oc + mc];
                     }
+                if constexpr (S::split_a) {
+                    if (w_bc)
+#pragma unroll
+                        for (int y = 0; y < NC; ++y) unsafeAtomicAdd(&K[(int64_t)(ob + mb) * nao + oc + y], rbc[y]);
+                    if (w_bd)
+#pragma unroll
+                        for (int y = 0; y < ND; ++y) unsafeAtomicAdd(&K[(int64_t)(ob + mb) * nao + od + y], rbd[y]);
+                } else {
+#pragma unroll
+                    for (int y = 0; y < NC; ++y) kbc[mb][y] += rbc[y];
+#pragma unroll
+                    for (int y = 0; y < ND; ++y) kbd[mb][y] += rbd[y];
+                }
             }
             if (w_ac)
 #pragma unroll
@@ -243,18 +286,32 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
 #pragma unroll
                 for (int y = 0; y < ND; ++y) unsafeAtomicAdd(&K[(int64_t)(oa + ma) * nao + od + y], kad[y]);
         }
-        if (w_bc)
+        if constexpr (!S::split_a) {
+            if (w_bc)
 #pragma unroll
-            for (int x = 0; x < NB; ++x)
+                for (int x = 0; x < NB; ++x)
 #pragma unroll
-                for (int y = 0; y < NC; ++y) unsafeAtomicAdd(&K[(int64_t)(ob + x) * nao + oc + y], kbc[x][y]);
-        if (w_bd)
+                    for (int y = 0; y < NC; ++y) unsafeAtomicAdd(&K[(int64_t)(ob + x) * nao + oc + y], kbc[x][y]);
+            if (w_bd)
 #pragma unroll
-            for (int x = 0; x < NB; ++x)
+                for (int x = 0; x < NB; ++x)
 #pragma unroll
-                for (int y = 0; y < ND; ++y) unsafeAtomicAdd(&K[(int64_t)(ob + x) * nao + od + y], kbd[x][y]);
+                    for (int y = 0; y < ND; ++y) unsafeAtomicAdd(&K[(int64_t)(ob + x) * nao + od + y], kbd[x][y]);
+        }
     }
-    if (valid && any) {
+    if (!do_j) return;
+    if constexpr (TK > 1) {
+        // the TK lanes of one bra pair are adjacent: sum their Hermite J vectors
+        int a = any ? 1 : 0;
+#pragma unroll
+        for (int w = TK / 2; w > 0; w >>= 1) {
+#pragma unroll
+            for (int h = 0; h < NHB; ++h) jh[h] += __shfl_xor(jh[h], w);
+            a |= __shfl_xor(a, w);
+        }
+        any = a != 0;
+    }
+    if (valid && any && jk == 0) {
 #pragma unroll
         for (int h = 0; h < NHB; ++h)
             unsafeAtomicAdd(&Jh[bra.herm_off + (int64_t)h * bra.npad + i], jh[h]);
@@ -334,18 +391,40 @@ __global__ __launch_bounds__(256) void k_direct_energy(const double *__restrict_
     if (threadIdx.x == 0) { E[0] = 0.5 * sj[0]; E[1] = -0.25 * sk[0]; }
 }
 
+template <int LA, int LB, int LC, int LD, bool TILED>
+static void launch_shape(const DirectClassDev &bra, const DirectClassDev &ket, double tau, const double *boys,
+                         const double *D, int64_t nao, const double *Dh, double *Jh, double *K, hipStream_t s)
+{
+    using S = QuartetShape<TILED, LA>;
+    const int gx = (bra.n + S::TB - 1) / S::TB;
+    const int gz = S::split_a ? 2 * LA + 1 : 1;
+    // enough blocks to fill the chip: split the ket range (the plain shape
+    // keeps at least 16 ket pairs per split to amortise the bra set-up)
+    const int minchunk = S::heavy ? S::TK : 16;
+    const int want = std::max(1, (8192 + gx * gz - 1) / (gx * gz));
+    const int nchunk = std::max(1, std::min(want, (ket.n + minchunk - 1) / minchunk));
+    int kchunk = (ket.n + nchunk - 1) / nchunk;
+    kchunk = (kchunk + S::TK - 1) / S::TK * S::TK;
+    const int gy = (ket.n + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL((k_direct<LA, LB, LC, LD, TILED>), dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(64), 0,
+                       s, bra, ket, kchunk, tau, boys, D, nao, Dh, Jh, K, 1);
+}
+
+// Tiled shape for total angular momentum 5 and up; for a d shell first in the
+// bra (pairs few and costly) when that class has under 512 pairs; else plain.
 template <int LA, int LB, int LC, int LD>
 static void launch_quartets(const DirectClassDev &bra, const DirectClassDev &ket, double tau, const double *boys,
                             const double *D, int64_t nao, const double *Dh, double *Jh, double *K, hipStream_t s)
 {
-    const int gx = (bra.n + 63) / 64;
-    // enough blocks to fill the chip: split the ket range, at least 16 pairs per split
-    const int want = std::max(1, (8192 + gx - 1) / gx);
-    const int nchunk = std::max(1, std::min(want, (ket.n + 15) / 16));
-    const int kchunk = (ket.n + nchunk - 1) / nchunk;
-    const int gy = (ket.n + kchunk - 1) / kchunk;
-    hipLaunchKernelGGL((k_direct<LA, LB, LC, LD>), dim3((unsigned)gx, (unsigned)gy), dim3(64), 0, s, bra, ket, kchunk,
-                       tau, boys, D, nao, Dh, Jh, K, 1);
+    constexpr int L = LA + LB + LC + LD;
+    if constexpr (L >= 5) {
+        launch_shape<LA, LB, LC, LD, true>(bra, ket, tau, boys, D, nao, Dh, Jh, K, s);
+    } else if constexpr (LA == 2) {
+        if (bra.n < 512) launch_shape<LA, LB, LC, LD, true>(bra, ket, tau, boys, D, nao, Dh, Jh, K, s);
+        else launch_shape<LA, LB, LC, LD, false>(bra, ket, tau, boys, D, nao, Dh, Jh, K, s);
+    } else {
+        launch_shape<LA, LB, LC, LD, false>(bra, ket, tau, boys, D, nao, Dh, Jh, K, s);
+    }
 }
 
 template <int LA, int LB>
