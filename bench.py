@@ -55,6 +55,75 @@ def committed_traffic():
     return int(b.group(1))
 
 
+def committed_direct_flops():
+    """FP64 VALU flops per direct build (per Schwarz threshold) from the
+    committed rocprofv3 counter summary, or {} when the direct kernels'
+    source changed since those counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "direct_jk_water32.md")
+    src = os.path.join(ROOT, "paper_2404_09452_amd", "csrc", "direct.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return {}
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    if not h or h.group(1) != sha:
+        return {}
+    return {float(t): float(f) for t, f in re.findall(r"fp64_valu_flops_per_build\[tau=([0-9.e+-]+)\]:\s*([0-9.e+]+)", text)}
+
+
+def direct_bench(mol, Cd, taus=(1e-10, 1e-12), nbuild=5, E_df=None):
+    """Four-centre direct J/K (exact exchange) on the same molecule and
+    orbitals: ms per build (HIP events on the stream the builds run on),
+    screened quartets, and the FP64 VALU roofline fraction from committed
+    counters."""
+    import numpy as np
+    import torch
+    from paper_2404_09452_amd.dfjk import Plan
+    flops = committed_direct_flops()
+    out = {}
+    for tau in taus:
+        t0 = time.perf_counter()
+        plan = Plan.from_molecule(mol, schwarz_thresh=tau).screen().direct_setup()
+        torch.cuda.synchronize()
+        setup_ms = 1000.0 * (time.perf_counter() - t0)
+        st = plan.direct_stats()
+        plan.direct_build(C=Cd[0])
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nbuild)]
+        for b in range(nbuild):
+            ev[2 * b].record(stream)
+            J, K, E = plan.direct_build(C=Cd[b % len(Cd)], stream=stream)
+            ev[2 * b + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = [ev[2 * b].elapsed_time(ev[2 * b + 1]) for b in range(nbuild)]
+        med = float(np.median(ms))
+        Ed = E.cpu().numpy()
+        r = {"ms_per_build_median": round(med, 3), "ms_per_build_min": round(float(np.min(ms)), 3),
+             "builds_per_s": round(1000.0 / med, 3), "setup_ms": round(setup_ms, 2),
+             "pairs_per_class_ss_ps_pp_ds_dp_dd": st["pairs"], "quartets": st["quartets"],
+             "quartets_per_s": round(st["quartets"] / (med * 1e-3), 1),
+             "E_J": float(Ed[0]), "E_K": float(Ed[1])}
+        if E_df is not None:
+            k = (nbuild - 1) % len(Cd)
+            r["E_exact_minus_E_DF"] = [float(Ed[0] - E_df[k][0]), float(Ed[1] - E_df[k][1])]
+        f = flops.get(tau)
+        if f:
+            ach = f / (med * 1e-3) / 1e12
+            r["roofline"] = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_F64_TFLOPS,
+                             "achieved": round(ach, 3), "frac": round(ach / PEAK_F64_TFLOPS, 4),
+                             "flops_per_build": f,
+                             "flops_source": "profiles/direct_jk_water32.md (FP64 VALU instruction counters)"}
+        out["tau_%g" % tau] = r
+        plan.close()
+        del J, K, E
+    torch.cuda.empty_cache()
+    return out
+
+
 def make_inputs(n=32, box=10.0, geom_seed=1, cocc_seed=1):
     import workload as W
     z, x = W.water_cluster(n, box, geom_seed)
@@ -346,6 +415,10 @@ def main():
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 128-water leg and print its JSON (for profiling)")
     ap.add_argument("--large-builds", type=int, default=2)
+    ap.add_argument("--no-direct", action="store_true", help="skip the four-centre direct J/K leg")
+    ap.add_argument("--only-direct", action="store_true",
+                    help="run only the four-centre direct J/K leg on the 32-water cluster and print its JSON")
+    ap.add_argument("--direct-builds", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -374,6 +447,12 @@ def main():
         return
     if args.only_large:
         print(json.dumps({"water128": large_bench(args.large_builds)}))
+        return
+    if args.only_direct:
+        import torch
+        mol, _, Cs = make_inputs()
+        Cd = [torch.as_tensor(C, device="cuda") for C in Cs]
+        print(json.dumps({"direct_scf": direct_bench(mol, Cd, nbuild=args.direct_builds)}))
         return
     import numpy as np
     import torch
@@ -481,6 +560,11 @@ def main():
             results[prec]["K_tflops"] = round(k_flops / (ms * 1e-3) / 1e12, 2)
             results[prec]["K_frac_of_peak"] = round(k_flops / (ms * 1e-3) / 1e12 / peak, 4)
 
+    direct = None
+    if not args.no_direct:
+        print("bench: four-centre direct J/K", file=sys.stderr, flush=True)
+        direct = direct_bench(mol, Cd, nbuild=args.direct_builds, E_df=ref_E)
+
     # split-count autotuner on the same molecule (outside the timed steps)
     tplan = Plan.from_molecule(mol, schwarz_thresh=1e-14).screen().setup()
     chosen, cand_ms = tplan.autotune(Cd[0])
@@ -529,6 +613,7 @@ def main():
         "mixed": {k: v for k, v in results.items() if k != "fp64"},
         "serving": serving,
         "water128": large,
+        "direct_scf": direct,
         "autotune_K_split": autotune,
         "roofline_by_step": by_step,
         "fp64_detail": {k: v for k, v in f64.items() if k not in ("E_J", "E_K")},

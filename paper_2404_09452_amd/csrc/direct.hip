@@ -65,6 +65,16 @@ static void dfill(double *p, int64_t n, hipStream_t s)
     if (n > 0) hipLaunchKernelGGL(k_dfill, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256), 0, s, p, n, 0.0);
 }
 
+// Read of a table entry whose index is the same for every lane of the wave,
+// through the constant address space so that it becomes a scalar load (the
+// tables are read only for the whole kernel).  Tables written by an earlier
+// kernel on the stream are visible: caches are invalidated between kernels.
+template <class T>
+__device__ __forceinline__ T uniform_load(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)(p);
+}
+
 // Hermite density of every pair of one class (ket layout, signed).
 template <int LA, int LB>
 __global__ __launch_bounds__(128) void k_dherm(DirectClassDev c, const double *__restrict__ D, int64_t nao,
@@ -137,8 +147,8 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
     const int j0 = blockIdx.y * kchunk;
     const int j1 = min(ket.n, j0 + kchunk);
     if (j0 >= j1) return;
-    const double qwave = bra.q[blockIdx.x * TB];    // largest bound of this wave
-    if (!(ket.q[j0] * qwave >= tau)) return;
+    const double qwave = uniform_load(bra.q + blockIdx.x * TB);    // largest bound of this wave
+    if (!(uniform_load(ket.q + j0) * qwave >= tau)) return;
     const int ma0 = S::split_a ? (int)blockIdx.z : 0;
     const int ma1 = S::split_a ? ma0 + 1 : NA;
     const bool do_j = !S::split_a || blockIdx.z == 0;
@@ -159,13 +169,22 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
     for (int h = 0; h < NHB; ++h) jh[h] = 0.0;
     bool any = false;
 
+    // ket entries: scalar loads when the whole wave reads the same pair
+    auto kd = [&](const double *t, int64_t x) -> double {
+        if constexpr (TK == 1) return uniform_load(t + x);
+        else return t[x];
+    };
+    auto ki = [&](const int32_t *t, int64_t x) -> int32_t {
+        if constexpr (TK == 1) return uniform_load(t + x);
+        else return t[x];
+    };
     for (int jt = j0; jt < j1; jt += TK) {
-        if (!(ket.q[jt] * qwave >= tau)) break;      // the first ket of a step is its largest
+        if (!(uniform_load(ket.q + jt) * qwave >= tau)) break;   // the first ket of a step is its largest
         const int j = jt + jk;
-        if (!(valid && j < j1 && qa * ket.q[j] >= tau)) continue;
+        if (!(valid && j < j1 && qa * kd(ket.q, j) >= tau)) continue;
         any = true;
-        const double q = ket.p[j];
-        const double X = Px - ket.px[j], Y = Py - ket.py[j], Z = Pz - ket.pz[j];
+        const double q = kd(ket.p, j);
+        const double X = Px - kd(ket.px, j), Y = Py - kd(ket.py, j), Z = Pz - kd(ket.pz, j);
         const double pq = p + q, alpha = p * q / pq;
         double F[L + 1];
         boys<L>(alpha * (X * X + Y * Y + Z * Z), F, boys_tab);
@@ -189,14 +208,14 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
                             for (int u2 = 0; u2 + t2 <= LCD; ++u2)
 #pragma unroll
                                 for (int v2 = 0; v2 + u2 + t2 <= LCD; ++v2)
-                                    s += R[hidx(t + t2, u + u2, v + v2)] * dh[hidx(t2, u2, v2)];
+                                    s += R[hidx(t + t2, u + u2, v + v2)] * kd(dh, hidx(t2, u2, v2));
                         jh[hidx(t, u, v)] += pref * s;
                     }
         }
         if (!with_k) continue;
 
         // Exchange
-        const int oc = ket.off_a[j], od = ket.off_b[j], sc = ket.sh_a[j], sd = ket.sh_b[j];
+        const int oc = ki(ket.off_a, j), od = ki(ket.off_b, j), sc = ki(ket.sh_a, j), sd = ki(ket.sh_b, j);
         const bool cd_same = sc == sd;
         const bool w_ac = sa >= sc, w_ad = !cd_same && sa >= sd;
         const bool w_bc = !ab_same && sb >= sc, w_bd = !ab_same && !cd_same && sb >= sd;
@@ -258,7 +277,7 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
                         const int g = mc * ND + md;
                         double I = 0.0;
 #pragma unroll
-                        for (int k = 0; k < NHK; ++k) I += ek[g * NHK + k] * V[k];
+                        for (int k = 0; k < NHK; ++k) I += kd(ek, g * NHK + k) * V[k];
                         I *= pref;
                         kac[mc] += I * D[(int64_t)(ob + mb) * nao + od + md];
                         kad[md] += I * D[(int64_t)(ob + mb) * nao + oc + mc];
