@@ -122,7 +122,6 @@ struct Plan {
     // second stream of the overlapped half transform and its events
     hipStream_t ht_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_ht[2] = {nullptr, nullptr}, ev_kdone[2] = {nullptr, nullptr};
-    hipEvent_t ev_jfork = nullptr, ev_jdone = nullptr;   // J beside the half transform
     // split counts chosen by dfjk_autotune for the closed-shell C-route build,
     // keyed by nocc * 4 + precision
     std::map<int64_t, int> tuned_nsplit;

@@ -659,7 +659,7 @@ static void slab_gemm(const BuildLayout &L, bool lower, const void *X, const voi
 static bool overlap_streams(Plan &p)
 {
     if (p.ht_stream) return true;
-    hipEvent_t ev[7] = {};
+    hipEvent_t ev[5] = {};
     hipStream_t hs = nullptr;
     bool ok = true;
     for (hipEvent_t &e : ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
@@ -671,7 +671,6 @@ static bool overlap_streams(Plan &p)
         return false;
     }
     p.ev_fork = ev[0]; p.ev_ht[0] = ev[1]; p.ev_ht[1] = ev[2]; p.ev_kdone[0] = ev[3]; p.ev_kdone[1] = ev[4];
-    p.ev_jfork = ev[5]; p.ev_jdone = ev[6];
     p.ht_stream = hs;
     return true;
 }
@@ -774,21 +773,10 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
                            (int32_t)L.ncol, reinterpret_cast<double *>(scratch + L.o_U),
                            reinterpret_cast<double *>(scratch + L.o_W));
     pr.mark(ST_DENSITY, false);
-    // 2-4. J (always FP64), on the plan's second stream beside the half
-    // transform when that stream exists (joined back before the energies)
-    const bool side_j = overlap_streams(p);
-    hipStream_t js = s;
-    if (side_j) {
-        (void)hipEventRecord(p.ev_jfork, s);
-        (void)hipStreamWaitEvent(p.ht_stream, p.ev_jfork, 0);
-        js = p.ht_stream;
-    }
-    pr.stream = js;
+    // 2-4. J (always FP64)
     pr.mark(ST_J, true);
-    launch_j(p, L, D, J, scratch, js);
+    launch_j(p, L, D, J, scratch, s);
     pr.mark(ST_J, false);
-    pr.stream = s;
-    if (side_j) (void)hipEventRecord(p.ev_jdone, js);
     // 5-6. per aux slab: half transform(s) and the slab's K contribution
     if (!L.delta)
         contract_slabs(p, L, L.with_D ? Din : C, nullptr, L.ncol, scratch, s);
@@ -806,7 +794,6 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
         hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
                            L.ntile, nao,
                            L.with_D ? 1.0 : 2.0, D, K, Epart);
-    if (side_j) (void)hipStreamWaitEvent(s, p.ev_jdone, 0);
     hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (kTileK / 16), -0.25,
                        E);
     pr.mark(ST_KREDUCE, false);
