@@ -74,7 +74,7 @@ def committed_direct_flops():
     return {float(t): float(f) for t, f in re.findall(r"fp64_valu_flops_per_build\[tau=([0-9.e+-]+)\]:\s*([0-9.e+]+)", text)}
 
 
-def direct_bench(mol, Cd, taus=(1e-10, 1e-12), nbuild=5, E_df=None):
+def direct_bench(mol, Cd, taus=(1e-10, 1e-12), nbuild=5, E_df=None, S=None):
     """Four-centre direct J/K (exact exchange) on the same molecule and
     orbitals: ms per build (HIP events on the stream the builds run on),
     screened quartets, and the FP64 VALU roofline fraction from committed
@@ -117,10 +117,45 @@ def direct_bench(mol, Cd, taus=(1e-10, 1e-12), nbuild=5, E_df=None):
                              "achieved": round(ach, 3), "frac": round(ach / PEAK_F64_TFLOPS, 4),
                              "flops_per_build": f,
                              "flops_source": "profiles/direct_jk_water32.md (FP64 VALU instruction counters)"}
+        if S is not None and tau == taus[0]:
+            r["incremental"] = direct_delta_bench(plan, Cd[0], S, med, nbuild)
         out["tau_%g" % tau] = r
         plan.close()
         del J, K, E
     torch.cuda.empty_cache()
+    return out
+
+
+def direct_delta_bench(plan, C0, S, full_ms, nbuild):
+    """Incremental direct builds J0, K0 + J, K(D - D0) with the
+    density-weighted screen, for a step like the headline sequence's
+    (eps 1e-2) and a late-iteration step (eps 1e-4); HIP events on the
+    stream the builds run on."""
+    import numpy as np
+    import torch
+    import workload as W
+    C0h = C0.cpu().numpy()
+    D0 = 2.0 * C0 @ C0.T
+    J0, K0, _ = plan.direct_build(D=D0)
+    out = {}
+    stream = torch.cuda.current_stream()
+    for eps in (1e-2, 1e-4):
+        C1 = torch.as_tensor(W.perturbed_orbitals(C0h, S, 1, eps=eps, seed=4242), device="cuda")
+        D1 = 2.0 * C1 @ C1.T
+        _, _, Ef = plan.direct_build(D=D1)
+        plan.direct_build_delta(D1, D0, J0, K0)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nbuild)]
+        for b in range(nbuild):
+            ev[2 * b].record(stream)
+            _, _, E = plan.direct_build_delta(D1, D0, J0, K0, stream=stream)
+            ev[2 * b + 1].record(stream)
+        torch.cuda.synchronize()
+        med = float(np.median([ev[2 * b].elapsed_time(ev[2 * b + 1]) for b in range(nbuild)]))
+        dE = (E - Ef).abs().cpu().numpy()
+        out["eps_%g" % eps] = {"ms_per_build_median": round(med, 3), "speedup_vs_full": round(full_ms / med, 2),
+                               "max_abs_dD": float((D1 - D0).abs().max()),
+                               "abs_dE_vs_full_build": [float(dE[0]), float(dE[1])]}
     return out
 
 
@@ -450,9 +485,9 @@ def main():
         return
     if args.only_direct:
         import torch
-        mol, _, Cs = make_inputs()
+        mol, S, Cs = make_inputs()
         Cd = [torch.as_tensor(C, device="cuda") for C in Cs]
-        print(json.dumps({"direct_scf": direct_bench(mol, Cd, nbuild=args.direct_builds)}))
+        print(json.dumps({"direct_scf": direct_bench(mol, Cd, nbuild=args.direct_builds, S=S)}))
         return
     import numpy as np
     import torch
@@ -563,7 +598,7 @@ def main():
     direct = None
     if not args.no_direct:
         print("bench: four-centre direct J/K", file=sys.stderr, flush=True)
-        direct = direct_bench(mol, Cd, nbuild=args.direct_builds, E_df=ref_E)
+        direct = direct_bench(mol, Cd, nbuild=args.direct_builds, E_df=ref_E, S=S)
 
     # split-count autotuner on the same molecule (outside the timed steps)
     tplan = Plan.from_molecule(mol, schwarz_thresh=1e-14).screen().setup()

@@ -287,6 +287,24 @@ int dfjk_direct_build_bytes(const dfjk_plan *plan, int32_t with_density, size_t 
 int dfjk_direct_build(dfjk_plan *plan, const double *d_C, int32_t nocc, const double *d_D, double *d_J,
                       double *d_K, double *d_E, void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* Incremental direct J/K for later SCF iterations, after the paper's
+ * Schwarz-bound error control in direct SCF ("Limitations and Future
+ * Development: Mixed Precision"): with the exact J0 = J(D0), K0 = K(D0) of an
+ * earlier dfjk_direct_build on this plan,
+ *   J = J0 + J(D - D0),  K = K0 + K(D - D0),
+ * where the increment skips every quartet whose density-weighted bound
+ * Q_ab Q_cd max|D - D0| (the largest element of D - D0 over the shell blocks
+ * the quartet contracts with: cd for J; bd, bc, ad, ac for K) is below
+ * schwarz_thresh, so the work shrinks as D approaches D0.
+ * d_D, d_D0: nao x nao symmetric; d_J0, d_K0: nao x nao (read only, must not
+ * alias the outputs).  Outputs as for dfjk_direct_build, with
+ * d_E = {1/2 Tr(D J), -1/4 Tr(D K)} of the full D.  d_scratch must hold
+ * dfjk_direct_build_delta_bytes(plan). */
+int dfjk_direct_build_delta_bytes(const dfjk_plan *plan, size_t *bytes);
+int dfjk_direct_build_delta(dfjk_plan *plan, const double *d_D, const double *d_D0, const double *d_J0,
+                            const double *d_K0, double *d_J, double *d_K, double *d_E, void *d_scratch,
+                            size_t scratch_bytes, void *stream);
+
 /* Diagnostics for tests (valid after setup).  Dense copies of intermediate
  * quantities in the caller's function order:
  *   DFJK_EXPORT_INT3C   (naux x nao x nao) unwhitened (mu nu|P), screened

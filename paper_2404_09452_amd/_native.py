@@ -59,6 +59,8 @@ SIGNATURES = {
     "dfjk_direct_stats": (c_i32, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     "dfjk_direct_build_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_sz)]),
     "dfjk_direct_build": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "dfjk_direct_build_delta_bytes": (c_i32, [c_vp, ctypes.POINTER(c_sz)]),
+    "dfjk_direct_build_delta": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "dfjk_export": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "dfjk_sample": (c_i32, [c_vp, c_i32, c_i64, c_vp, c_vp, c_vp]),
     "dfjk_boys": (c_i32, [c_i32, c_i64, c_vp, c_vp, c_vp]),

@@ -82,6 +82,7 @@ struct DirectState {
     size_t table_bytes = 0;
     char *tables = nullptr;
     const int32_t *fn_shell = nullptr;   // AO function -> shell (device)
+    const int32_t *shell_off = nullptr;  // first AO function of each shell, nsh + 1 entries (device)
     const double *boys = nullptr;
     int device = -1;
 };
@@ -259,13 +260,16 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
 
 // direct.hip: four-centre direct J/K.  Scratch: the density (C route), the
 // Hermite density and Hermite J buffers, and the energy partials.
+// An incremental build (delta) integrates dD = D - D0 with the
+// density-weighted screen and adds the reference J0, K0.
 struct DirectLayout {
-    bool with_D;
-    size_t o_D, o_Dh, o_Jh, o_Epart, bytes;
+    bool with_D, delta;
+    size_t o_D, o_dsh, o_Dh, o_Jh, o_Epart, bytes;
 };
-DirectLayout direct_layout(const Plan &p, bool with_D);
+DirectLayout direct_layout(const Plan &p, bool with_D, bool delta = false);
 void launch_direct_build(const Plan &p, const DirectLayout &L, const double *C, int32_t nocc, const double *D,
-                         double *J, double *K, double *E, char *scratch, hipStream_t s);
+                         const double *D0, const double *J0, const double *K0, double *J, double *K, double *E,
+                         char *scratch, hipStream_t s);
 void launch_density(const double *C, int64_t nao, int32_t nocc, double scale, double *D, hipStream_t s);
 
 // export.hip

@@ -39,13 +39,15 @@
 
 namespace dfjk {
 
-DirectLayout direct_layout(const Plan &p, bool with_D)
+DirectLayout direct_layout(const Plan &p, bool with_D, bool delta)
 {
     DirectLayout L{};
     L.with_D = with_D;
+    L.delta = delta;
     size_t off = 0;
     auto take = [&](size_t b) { off = align_up(off, 256); size_t o = off; off += b; return o; };
-    L.o_D = with_D ? 0 : take((size_t)p.nao * p.nao * 8);
+    L.o_D = (with_D && !delta) ? 0 : take((size_t)p.nao * p.nao * 8);   // D from C, or D - D0
+    L.o_dsh = delta ? take(((size_t)p.nsh_ao * p.nsh_ao + 1) * 8) : 0;   // block maxima, then the overall max
     L.o_Dh = take((size_t)std::max<int64_t>(p.dir.herm_total, 1) * 8);
     L.o_Jh = take((size_t)std::max<int64_t>(p.dir.herm_total, 1) * 8);
     L.o_Epart = take((size_t)2 * 256 * 8);
@@ -73,6 +75,43 @@ template <class T>
 __device__ __forceinline__ T uniform_load(const T *p)
 {
     return *(const __attribute__((address_space(4))) T *)(p);
+}
+
+// dD = D - D0, and the largest |dD| over each block of shells (x, y), taken
+// over both orientations (the density-weighted Schwarz bound of a quartet).
+__global__ void k_dsub(const double *__restrict__ D, const double *__restrict__ D0, int64_t n,
+                       double *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = D[i] - D0[i];
+}
+
+__global__ void k_shell_dmax(const double *__restrict__ dD, int64_t nao, int32_t nsh, const int32_t *__restrict__ off,
+                             double *__restrict__ dsh)
+{
+    const int64_t xy = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (xy >= (int64_t)nsh * nsh) return;
+    const int x = (int)(xy / nsh), y = (int)(xy % nsh);
+    double m = 0.0;
+    for (int mu = off[x]; mu < off[x + 1]; ++mu)
+        for (int nu = off[y]; nu < off[y + 1]; ++nu)
+            m = fmax(m, fmax(fabs(dD[(int64_t)mu * nao + nu]), fabs(dD[(int64_t)nu * nao + mu])));
+    dsh[xy] = m;
+}
+
+// dsh[nsh * nsh] = the largest entry of the table (one block, fixed order).
+__global__ __launch_bounds__(256) void k_dmax_all(double *__restrict__ dsh, int64_t n)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, dsh[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dsh[n] = red[0];
 }
 
 // Hermite density of every pair of one class (ket layout, signed).
@@ -127,7 +166,8 @@ template <int LA, int LB, int LC, int LD, bool TILED>
 __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDev ket, int32_t kchunk, double tau,
                                                const double *__restrict__ boys_tab, const double *__restrict__ D,
                                                int64_t nao, const double *__restrict__ Dh, double *__restrict__ Jh,
-                                               double *__restrict__ K, int32_t with_k)
+                                               double *__restrict__ K, int32_t with_k,
+                                               const double *__restrict__ dsh, int32_t nsh)
 {
     constexpr int LAB = LA + LB, LCD = LC + LD, L = LAB + LCD;
     constexpr int NHB = nherm(LAB), NHK = nherm(LCD);
@@ -147,7 +187,10 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
     const int j0 = blockIdx.y * kchunk;
     const int j1 = min(ket.n, j0 + kchunk);
     if (j0 >= j1) return;
-    const double qwave = uniform_load(bra.q + blockIdx.x * TB);    // largest bound of this wave
+    // the Schwarz bound of the loop ends: Q_ab Q_cd, times the largest
+    // |D - D0| anywhere for an incremental build
+    const double qwave = uniform_load(bra.q + blockIdx.x * TB) *
+                         (dsh ? uniform_load(dsh + (int64_t)nsh * nsh) : 1.0);   // largest bound of this wave
     if (!(uniform_load(ket.q + j0) * qwave >= tau)) return;
     const int ma0 = S::split_a ? (int)blockIdx.z : 0;
     const int ma1 = S::split_a ? ma0 + 1 : NA;
@@ -182,6 +225,14 @@ __global__ __launch_bounds__(64) void k_direct(DirectClassDev bra, DirectClassDe
         if (!(uniform_load(ket.q + jt) * qwave >= tau)) break;   // the first ket of a step is its largest
         const int j = jt + jk;
         if (!(valid && j < j1 && qa * kd(ket.q, j) >= tau)) continue;
+        if (dsh) {
+            // density-weighted bound: Q_ab Q_cd times the largest |dD| of the
+            // blocks this quartet contracts with (cd for J; bd, bc, ad, ac for K)
+            const int64_t jc = ki(ket.sh_a, j), jd = ki(ket.sh_b, j);
+            const double dm = fmax(fmax(dsh[jc * nsh + jd], fmax(dsh[(int64_t)sb * nsh + jd], dsh[(int64_t)sb * nsh + jc])),
+                                   fmax(dsh[(int64_t)sa * nsh + jd], dsh[(int64_t)sa * nsh + jc]));
+            if (!(qa * kd(ket.q, j) * dm >= tau)) continue;
+        }
         any = true;
         const double q = kd(ket.p, j);
         const double X = Px - kd(ket.px, j), Y = Py - kd(ket.py, j), Z = Pz - kd(ket.pz, j);
@@ -365,10 +416,12 @@ __global__ __launch_bounds__(128) void k_jout(DirectClassDev c, const double *__
 }
 
 // Symmetrise J (mean of the two triangles), complete K from its lower shell
-// triangle (mean on diagonal shell blocks) and form the block partials of
-// sum D.J and sum D.K over the lower triangle mu >= nu.
+// triangle (mean on diagonal shell blocks), add the reference J0, K0 of an
+// incremental build, and form the block partials of sum D.J and sum D.K
+// over the lower triangle mu >= nu.
 __global__ __launch_bounds__(256) void k_direct_finish(int64_t nao, const int32_t *__restrict__ fn_shell,
-                                                       const double *__restrict__ D, double *__restrict__ J,
+                                                       const double *__restrict__ D, const double *__restrict__ J0,
+                                                       const double *__restrict__ K0, double *__restrict__ J,
                                                        double *__restrict__ K, double *__restrict__ Epart)
 {
     const int64_t ntri = nao * (nao + 1) / 2;
@@ -379,8 +432,9 @@ __global__ __launch_bounds__(256) void k_direct_finish(int64_t nao, const int32_
         while ((mu + 1) * (mu + 2) / 2 <= e) ++mu;
         const int64_t nu = e - mu * (mu + 1) / 2;
         const int64_t a = mu * nao + nu, b = nu * nao + mu;
-        const double jv = mu == nu ? J[a] : 0.5 * (J[a] + J[b]);
-        const double kv = (fn_shell[mu] == fn_shell[nu] && mu != nu) ? 0.5 * (K[a] + K[b]) : K[a];
+        double jv = mu == nu ? J[a] : 0.5 * (J[a] + J[b]);
+        double kv = (fn_shell[mu] == fn_shell[nu] && mu != nu) ? 0.5 * (K[a] + K[b]) : K[a];
+        if (J0) { jv += J0[a]; kv += K0[a]; }   // increment on top of the reference (symmetric) J0, K0
         J[a] = jv; J[b] = jv;
         K[a] = kv; K[b] = kv;
         const double dw = mu == nu ? D[a] : D[a] + D[b];
@@ -412,7 +466,8 @@ __global__ __launch_bounds__(256) void k_direct_energy(const double *__restrict_
 
 template <int LA, int LB, int LC, int LD, bool TILED>
 static void launch_shape(const DirectClassDev &bra, const DirectClassDev &ket, double tau, const double *boys,
-                         const double *D, int64_t nao, const double *Dh, double *Jh, double *K, hipStream_t s)
+                         const double *D, int64_t nao, const double *Dh, double *Jh, double *K, const double *dsh,
+                         int nsh, hipStream_t s)
 {
     using S = QuartetShape<TILED, LA>;
     const int gx = (bra.n + S::TB - 1) / S::TB;
@@ -426,38 +481,39 @@ static void launch_shape(const DirectClassDev &bra, const DirectClassDev &ket, d
     kchunk = (kchunk + S::TK - 1) / S::TK * S::TK;
     const int gy = (ket.n + kchunk - 1) / kchunk;
     hipLaunchKernelGGL((k_direct<LA, LB, LC, LD, TILED>), dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(64), 0,
-                       s, bra, ket, kchunk, tau, boys, D, nao, Dh, Jh, K, 1);
+                       s, bra, ket, kchunk, tau, boys, D, nao, Dh, Jh, K, 1, dsh, nsh);
 }
 
 // Tiled shape for total angular momentum 5 and up; for a d shell first in the
 // bra (pairs few and costly) when that class has under 512 pairs; else plain.
 template <int LA, int LB, int LC, int LD>
 static void launch_quartets(const DirectClassDev &bra, const DirectClassDev &ket, double tau, const double *boys,
-                            const double *D, int64_t nao, const double *Dh, double *Jh, double *K, hipStream_t s)
+                            const double *D, int64_t nao, const double *Dh, double *Jh, double *K, const double *dsh,
+                            int nsh, hipStream_t s)
 {
     constexpr int L = LA + LB + LC + LD;
     if constexpr (L >= 5) {
-        launch_shape<LA, LB, LC, LD, true>(bra, ket, tau, boys, D, nao, Dh, Jh, K, s);
+        launch_shape<LA, LB, LC, LD, true>(bra, ket, tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
     } else if constexpr (LA == 2) {
-        if (bra.n < 512) launch_shape<LA, LB, LC, LD, true>(bra, ket, tau, boys, D, nao, Dh, Jh, K, s);
-        else launch_shape<LA, LB, LC, LD, false>(bra, ket, tau, boys, D, nao, Dh, Jh, K, s);
+        if (bra.n < 512) launch_shape<LA, LB, LC, LD, true>(bra, ket, tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+        else launch_shape<LA, LB, LC, LD, false>(bra, ket, tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
     } else {
-        launch_shape<LA, LB, LC, LD, false>(bra, ket, tau, boys, D, nao, Dh, Jh, K, s);
+        launch_shape<LA, LB, LC, LD, false>(bra, ket, tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
     }
 }
 
 template <int LA, int LB>
 static void launch_bra(const DirectClassDev *cls, double tau, const double *boys, const double *D, int64_t nao,
-                       const double *Dh, double *Jh, double *K, hipStream_t s)
+                       const double *Dh, double *Jh, double *K, const double *dsh, int nsh, hipStream_t s)
 {
     const DirectClassDev &b = cls[LA == 0 ? 0 : (LA == 1 ? 1 + LB : 3 + LB)];
     if (b.n <= 0) return;
-    if (cls[0].n > 0) launch_quartets<LA, LB, 0, 0>(b, cls[0], tau, boys, D, nao, Dh, Jh, K, s);
-    if (cls[1].n > 0) launch_quartets<LA, LB, 1, 0>(b, cls[1], tau, boys, D, nao, Dh, Jh, K, s);
-    if (cls[2].n > 0) launch_quartets<LA, LB, 1, 1>(b, cls[2], tau, boys, D, nao, Dh, Jh, K, s);
-    if (cls[3].n > 0) launch_quartets<LA, LB, 2, 0>(b, cls[3], tau, boys, D, nao, Dh, Jh, K, s);
-    if (cls[4].n > 0) launch_quartets<LA, LB, 2, 1>(b, cls[4], tau, boys, D, nao, Dh, Jh, K, s);
-    if (cls[5].n > 0) launch_quartets<LA, LB, 2, 2>(b, cls[5], tau, boys, D, nao, Dh, Jh, K, s);
+    if (cls[0].n > 0) launch_quartets<LA, LB, 0, 0>(b, cls[0], tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    if (cls[1].n > 0) launch_quartets<LA, LB, 1, 0>(b, cls[1], tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    if (cls[2].n > 0) launch_quartets<LA, LB, 1, 1>(b, cls[2], tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    if (cls[3].n > 0) launch_quartets<LA, LB, 2, 0>(b, cls[3], tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    if (cls[4].n > 0) launch_quartets<LA, LB, 2, 1>(b, cls[4], tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    if (cls[5].n > 0) launch_quartets<LA, LB, 2, 2>(b, cls[5], tau, boys, D, nao, Dh, Jh, K, dsh, nsh, s);
 }
 
 template <int LA, int LB>
@@ -482,16 +538,33 @@ static void pair_passes(const DirectClassDev *cls, const double *D, int64_t nao,
 }
 
 void launch_direct_build(const Plan &p, const DirectLayout &L, const double *C, int32_t nocc, const double *Din,
-                         double *J, double *K, double *E, char *scratch, hipStream_t s)
+                         const double *D0, const double *J0, const double *K0, double *J, double *K, double *E,
+                         char *scratch, hipStream_t s)
 {
     const int64_t nao = p.nao;
     const DirectState &ds = p.dir;
-    const double *D = Din;
+    const double *Dfull = Din;
     if (!L.with_D) {
         double *Dw = reinterpret_cast<double *>(scratch + L.o_D);
         launch_density(C, nao, nocc, 2.0, Dw, s);
-        D = Dw;
+        Dfull = Dw;
     }
+    // the density whose J and K are integrated: D, or dD = D - D0 with the
+    // shell-block bound table of the density-weighted screen
+    const double *D = Dfull;
+    const double *dsh = nullptr;
+    if (L.delta) {
+        double *dD = reinterpret_cast<double *>(scratch + L.o_D);
+        double *tab = reinterpret_cast<double *>(scratch + L.o_dsh);
+        hipLaunchKernelGGL(k_dsub, dim3((unsigned)((nao * nao + 255) / 256)), dim3(256), 0, s, Din, D0, nao * nao, dD);
+        const int64_t nxy = (int64_t)p.nsh_ao * p.nsh_ao;
+        hipLaunchKernelGGL(k_shell_dmax, dim3((unsigned)((nxy + 255) / 256)), dim3(256), 0, s, dD, nao, p.nsh_ao,
+                           ds.shell_off, tab);
+        hipLaunchKernelGGL(k_dmax_all, dim3(1), dim3(256), 0, s, tab, nxy);
+        D = dD;
+        dsh = tab;
+    }
+    const int nsh = p.nsh_ao;
     double *Dh = reinterpret_cast<double *>(scratch + L.o_Dh);
     double *Jh = reinterpret_cast<double *>(scratch + L.o_Jh);
     double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
@@ -500,14 +573,15 @@ void launch_direct_build(const Plan &p, const DirectLayout &L, const double *C, 
     dfill(Jh, ds.herm_total, s);
     pair_passes(ds.cls, D, nao, Dh, nullptr, nullptr, false, s);
     const double tau = p.thresh;
-    launch_bra<0, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
-    launch_bra<1, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
-    launch_bra<1, 1>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
-    launch_bra<2, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
-    launch_bra<2, 1>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
-    launch_bra<2, 2>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, s);
+    launch_bra<0, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    launch_bra<1, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    launch_bra<1, 1>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    launch_bra<2, 0>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    launch_bra<2, 1>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, dsh, nsh, s);
+    launch_bra<2, 2>(ds.cls, tau, ds.boys, D, nao, Dh, Jh, K, dsh, nsh, s);
     pair_passes(ds.cls, D, nao, Dh, Jh, J, true, s);
-    hipLaunchKernelGGL(k_direct_finish, dim3(256), dim3(256), 0, s, nao, ds.fn_shell, D, J, K, Epart);
+    hipLaunchKernelGGL(k_direct_finish, dim3(256), dim3(256), 0, s, nao, ds.fn_shell, Dfull, L.delta ? J0 : nullptr,
+                       L.delta ? K0 : nullptr, J, K, Epart);
     hipLaunchKernelGGL(k_direct_energy, dim3(1), dim3(256), 0, s, Epart, E);
 }
 

@@ -321,6 +321,29 @@ class Plan:
                                          _ptr(scr), scr.numel(), _stream_handle(stream)))
         return J, K, E
 
+    def direct_build_delta(self, D, D0, J0, K0, out=None, stream=None):
+        """Incremental exact J, K = J0, K0 + J, K(D - D0) with the
+        density-weighted Schwarz screen; E from the full D."""
+        dev = torch.device("cuda")
+        ins = [torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous() for x in (D, D0, J0, K0)]
+        for x in ins:
+            if tuple(x.shape) != (self.nao, self.nao):
+                raise ValueError("D, D0, J0 and K0 must be (nao, nao)")
+        if out is None:
+            J = torch.empty((self.nao, self.nao), dtype=torch.float64, device=dev)
+            K = torch.empty_like(J)
+            E = torch.empty(2, dtype=torch.float64, device=dev)
+        else:
+            J, K, E = out
+        if "delta" not in self._dscratch:
+            n = ctypes.c_size_t()
+            _check(N.lib().dfjk_direct_build_delta_bytes(self._h, ctypes.byref(n)))
+            self._dscratch["delta"] = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        scr = self._dscratch["delta"]
+        _check(N.lib().dfjk_direct_build_delta(self._h, *(_ptr(x) for x in ins), _ptr(J), _ptr(K), _ptr(E),
+                                               _ptr(scr), scr.numel(), _stream_handle(stream)))
+        return J, K, E
+
     def close(self):
         if getattr(self, "_h", None):
             N.lib().dfjk_plan_destroy(self._h)

@@ -105,6 +105,9 @@ def test_call_order_is_enforced_without_device():
     assert lib.dfjk_direct_build(plan._h, ctypes.c_void_p(8), 5, None, ctypes.c_void_p(8), ctypes.c_void_p(16),
                                  ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 20, None) == 7
     assert b"direct_setup" in lib.dfjk_last_error()
+    assert lib.dfjk_direct_build_delta_bytes(plan._h, ctypes.byref(n)) == 7
+    assert lib.dfjk_direct_build_delta(plan._h, *([ctypes.c_void_p(8)] * 4), ctypes.c_void_p(16), ctypes.c_void_p(24),
+                                       ctypes.c_void_p(32), ctypes.c_void_p(40), 1 << 20, None) == 7
     pairs = (ctypes.c_int64 * 6)()
     q = ctypes.c_int64()
     assert lib.dfjk_direct_stats(plan._h, pairs, ctypes.byref(q)) == 7

@@ -161,6 +161,47 @@ def test_direct_water32_sampled_blocks():
     plan.close()
 
 
+def test_direct_delta_against_oracle():
+    """Incremental build on the dimer: J0, K0 from D0, then D from perturbed
+    orbitals; J, K, E against the dense exact definition for D."""
+    mol, C0 = _cluster(2)
+    S = W.overlap_by_quadrature(mol)
+    C1 = W.perturbed_orbitals(C0, S, 1, eps=1e-2, seed=77)
+    D0, D1 = oracle.density(C0), oracle.density(C1)
+    plan = _plan(mol)
+    J0, K0, _ = plan.direct_build(D=D0)
+    J, K, E = _np(*plan.direct_build_delta(D1, D0, J0, K0))
+    Jr, Kr, EJr, EKr = oracle.exact_jk(mol, D1)
+    assert np.abs(J - Jr).max() <= TOL * np.abs(Jr).max()
+    assert np.abs(K - Kr).max() <= TOL * np.abs(Kr).max()
+    assert abs(E[0] - EJr) <= TOL * abs(EJr) and abs(E[1] - EKr) <= TOL * abs(EKr)
+    assert np.array_equal(J, J.T) and np.array_equal(K, K.T)
+    # D = D0 gives back J0 and K0 exactly (every quartet screened out)
+    Js, Ks, _ = _np(*plan.direct_build_delta(D0, D0, J0, K0))
+    assert np.array_equal(Js, J0.cpu().numpy()) and np.array_equal(Ks, K0.cpu().numpy())
+    plan.close()
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_direct_delta_matches_full_build(eps):
+    """Eight waters at tau = 1e-12: the incremental build equals the full build
+    to the screening error, for a large and a small density change."""
+    mol, C0 = _cluster(8, seed=2)
+    S = W.overlap_by_quadrature(mol)
+    C1 = W.perturbed_orbitals(C0, S, 1, eps=eps, seed=78)
+    D0, D1 = oracle.density(C0), oracle.density(C1)
+    plan = _plan(mol, tau=1e-12)
+    J0, K0, _ = plan.direct_build(D=D0)
+    Jf, Kf, Ef = _np(*plan.direct_build(D=D1))
+    J, K, E = _np(*plan.direct_build_delta(D1, D0, J0, K0))
+    ej = np.abs(J - Jf).max() / np.abs(Jf).max()
+    ek = np.abs(K - Kf).max() / np.abs(Kf).max()
+    print("eps %g: incremental vs full  J %.2e  K %.2e  dE %.2e %.2e" % (eps, ej, ek, E[0] - Ef[0], E[1] - Ef[1]))
+    assert ej <= 1e-9 and ek <= 1e-9
+    assert abs(E[0] - Ef[0]) <= 1e-9 * abs(Ef[0]) and abs(E[1] - Ef[1]) <= 1e-9 * abs(Ef[1])
+    plan.close()
+
+
 def test_direct_agrees_with_df_to_fitting_accuracy():
     """The exact J/K and the density-fitted J/K of the same molecule differ by
     the fitting error only (a sanity link between the two paths; DF energies
@@ -214,6 +255,8 @@ def test_direct_errors():
     plan.direct_setup()
     with pytest.raises(ValueError):
         plan.direct_build()
+    with pytest.raises(ValueError):
+        plan.direct_build_delta(np.zeros((2, 2)), np.zeros((2, 2)), np.zeros((2, 2)), np.zeros((2, 2)))
     with pytest.raises(ValueError):
         plan.direct_build(C=np.zeros((mol.nao + 1, 2)))
     plan.close()
