@@ -454,6 +454,8 @@ def main():
     ap.add_argument("--only-direct", action="store_true",
                     help="run only the four-centre direct J/K leg on the 32-water cluster and print its JSON")
     ap.add_argument("--direct-builds", type=int, default=5)
+    ap.add_argument("--no-direct-incremental", action="store_true",
+                    help="leave out the incremental direct builds (for counter runs of full builds only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -487,7 +489,8 @@ def main():
         import torch
         mol, S, Cs = make_inputs()
         Cd = [torch.as_tensor(C, device="cuda") for C in Cs]
-        print(json.dumps({"direct_scf": direct_bench(mol, Cd, nbuild=args.direct_builds, S=S)}))
+        print(json.dumps({"direct_scf": direct_bench(mol, Cd, nbuild=args.direct_builds,
+                                                     S=None if args.no_direct_incremental else S)}))
         return
     import numpy as np
     import torch
