@@ -42,12 +42,18 @@ __device__ __forceinline__ double readlane_f64(double v, int src)
 }
 
 // Factor the 64x64 diagonal block at (k0, k0) in place with one wave: lane i
-// holds row i in registers; column j's pivot and entries reach the other
-// lanes by lane reads, so there is no LDS traffic and no barrier.  A pivot
-// <= 0 is recorded (smallest index wins) and replaced by 1 so the remaining
-// steps stay finite; the host reports the recorded index.
+// holds row i in registers.  Step j takes the pivot from lane j by a lane
+// read, scales column j, publishes the column through LDS (one wave, so a
+// barrier per step orders the write before the broadcast reads) and updates
+// every later column of every row with one FMA per entry.  Entries above the
+// diagonal are updated too but never read by a later step (a step reads the
+// pivot from its own lane and the column from the rows below it) and are
+// stored as zero.  A pivot <= 0 is recorded (smallest index wins) and
+// replaced by 1 so the remaining steps stay finite; the host reports the
+// recorded index.
 __global__ __launch_bounds__(64) void k_potrf_diag(double *A, int64_t ld, int64_t k0, int32_t *status)
 {
+    __shared__ __align__(16) double col[2][NBK];
     const int i = threadIdx.x;
     double *row = A + (k0 + i) * ld + k0;
     double r[NBK];
@@ -62,12 +68,21 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double *A, int64_t ld, int64_
             d = 1.0;
         }
         d = sqrt(d);
-        if (i == j) r[j] = d;
-        else if (i > j) r[j] = r[j] / d;
+        r[j] = (i == j) ? d : r[j] / d;
+        double *cj = col[j & 1];
+        cj[i] = r[j];
+        __syncthreads();
+        // L[l][j] for l > j: an odd first entry alone, then 16-byte aligned pairs
+        int l0 = j + 1;
+        if ((l0 & 1) && l0 < NBK) {
+            r[l0] = fma(-r[j], cj[l0], r[l0]);
+            ++l0;
+        }
 #pragma unroll
-        for (int l = j + 1; l < NBK; ++l) {
-            const double lj = readlane_f64(r[j], l);    // L[l][j]
-            if (i >= l) r[l] -= r[j] * lj;
+        for (int l = l0; l < NBK; l += 2) {
+            const double2 v = *reinterpret_cast<const double2 *>(cj + l);
+            r[l] = fma(-r[j], v.x, r[l]);
+            r[l + 1] = fma(-r[j], v.y, r[l + 1]);
         }
     }
     if (i == 0 && bad != INT_MAX) atomicMin(status, bad);
@@ -144,13 +159,21 @@ __global__ void k_identity(double *A, int64_t npad)
     A[i] = (i % npad == i / npad) ? 1.0 : 0.0;
 }
 
-// X[i0 + r][c] <- (L_ii^{-1} X_i)[r][c] for c < ncols; one thread per column.
+// X[i0 + r][c] <- (L_ii^{-1} X_i)[r][c] for c < ncols; one thread per column,
+// the column in registers.  Forward substitution in right-looking order: x_l
+// is final once divided by L_ll, and its column of L updates every later row
+// with independent FMAs.  L_ii sits transposed in LDS (row l holds column l,
+// 16-byte aligned rows), so each update reads two entries per broadcast read.
 __global__ __launch_bounds__(64) void k_trtri_diag(const double *L, double *X, int64_t ld, int64_t i0,
                                                     int64_t ncols)
 {
-    __shared__ double Li[NBK][NBK + 1];
+    constexpr int LDT = NBK + 2;
+    __shared__ __align__(16) double LT[NBK * LDT];
     const int tid = threadIdx.x;
-    for (int e = tid; e < NBK * NBK; e += NBK) Li[e / NBK][e % NBK] = L[(i0 + e / NBK) * ld + i0 + e % NBK];
+    for (int e = tid; e < NBK * NBK; e += NBK) {
+        const int r = e / NBK, l = e % NBK;
+        LT[l * LDT + r] = L[(i0 + r) * ld + i0 + l];
+    }
     __syncthreads();
     const int64_t c = blockIdx.x * (int64_t)NBK + tid;
     if (c >= ncols) return;
@@ -158,18 +181,20 @@ __global__ __launch_bounds__(64) void k_trtri_diag(const double *L, double *X, i
 #pragma unroll
     for (int r = 0; r < NBK; ++r) x[r] = X[(i0 + r) * ld + c];
 #pragma unroll
-    for (int r = 0; r < NBK; ++r) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four partial sums shorten the chain
-#pragma unroll
-        for (int l = 0; l + 3 < r; l += 4) {
-            s0 += Li[r][l] * x[l];
-            s1 += Li[r][l + 1] * x[l + 1];
-            s2 += Li[r][l + 2] * x[l + 2];
-            s3 += Li[r][l + 3] * x[l + 3];
+    for (int l = 0; l < NBK; ++l) {
+        const double *cl = LT + l * LDT;
+        x[l] = x[l] / cl[l];
+        int r0 = l + 1;
+        if ((r0 & 1) && r0 < NBK) {
+            x[r0] = fma(-cl[r0], x[l], x[r0]);
+            ++r0;
         }
 #pragma unroll
-        for (int l = r & ~3; l < r; ++l) s0 += Li[r][l] * x[l];
-        x[r] = (x[r] - ((s0 + s1) + (s2 + s3))) / Li[r][r];
+        for (int r = r0; r < NBK; r += 2) {
+            const double2 v = *reinterpret_cast<const double2 *>(cl + r);
+            x[r] = fma(-v.x, x[l], x[r]);
+            x[r + 1] = fma(-v.y, x[l], x[r + 1]);
+        }
     }
 #pragma unroll
     for (int r = 0; r < NBK; ++r) X[(i0 + r) * ld + c] = x[r];
