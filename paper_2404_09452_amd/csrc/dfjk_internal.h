@@ -274,6 +274,7 @@ void launch_density(const double *C, int64_t nao, int32_t nocc, double scale, do
 
 // export.hip
 void launch_zero(double *p, int64_t n, hipStream_t s);
+void launch_fmap(const Plan &p, hipStream_t s);   // the sampling diagnostic's pair map, from the stored rows
 void launch_export(const Plan &p, int kind, double *out, hipStream_t s);
 void launch_sample(const Plan &p, int kind, int64_t n, const int32_t *idx, double *out,
                    hipStream_t s);

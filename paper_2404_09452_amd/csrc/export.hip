@@ -59,6 +59,33 @@ void launch_export(const Plan &p, int kind, double *out, hipStream_t s)
     }
 }
 
+// The dense pair map of the sampling diagnostic, built on the device from the
+// stored rows: fmap[mu][nu] = f for the row f holding the pair (both
+// orientations of an off-diagonal shell block), -1 elsewhere.
+__global__ void k_fmap_clear(int32_t *__restrict__ fmap, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) fmap[i] = -1;
+}
+
+__global__ void k_fmap_rows(const int32_t *__restrict__ fmu, const int32_t *__restrict__ fnu,
+                            const double *__restrict__ fw, int64_t nf, int64_t nao, int32_t *__restrict__ fmap)
+{
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    fmap[(int64_t)fmu[f] * nao + fnu[f]] = (int32_t)f;
+    if (fw[f] > 1.5) fmap[(int64_t)fnu[f] * nao + fmu[f]] = (int32_t)f;
+}
+
+void launch_fmap(const Plan &p, hipStream_t s)
+{
+    const int64_t n = p.nao * p.nao;
+    hipLaunchKernelGGL(k_fmap_clear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.d.fmap, n);
+    if (p.nf > 0)
+        hipLaunchKernelGGL(k_fmap_rows, dim3((unsigned)((p.nf + 255) / 256)), dim3(256), 0, s, p.d.f_mu, p.d.f_nu,
+                           p.d.f_w, p.nf, p.nao, p.d.fmap);
+}
+
 // Sampled (P, mu, nu) -> value through the dense pair map fmap[mu][nu] = f or -1.
 __global__ void k_sample(const double *__restrict__ T, int64_t ld, const int32_t *__restrict__ fmap,
                          const int32_t *__restrict__ fn_internal, int64_t naux, int64_t nao, int64_t n,
