@@ -94,6 +94,7 @@ def test_arrivals_are_honoured():
 
 
 @pytest.mark.gpu
+@pytest.mark.gpu
 def test_results_identical_alone_and_in_the_mix():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
@@ -161,3 +162,34 @@ def test_batched_serving_matches_requests_alone():
         s = np.abs(alone.K_last).max()
         assert np.abs(alone.K_last - r.K_last).max() <= 1e-13 * s
         assert np.allclose(alone.energies[:, 1], r.energies[:, 1], rtol=1e-13, atol=0)
+
+
+@pytest.mark.gpu
+def test_served_results_match_oracle():
+    """A seeded sample of served requests (1-3 waters, served concurrently):
+    the last build's J, K and energies against the oracle's density-fitted
+    definition for that build's orbitals, at 1e-10."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import workload as W
+    from paper_2404_09452_amd.serve import GpuExecutor
+
+    def make(rid, n):
+        z, x = W.water_cluster(n, W.cluster_box(n), 900 + rid) if n > 1 else W.water_monomer()
+        mol = W.make_molecule(z, x)
+        S = W.overlap_by_quadrature(mol)
+        C0 = W.occupied_orbitals(S, mol.nelec // 2, rid)
+        orbs = [W.perturbed_orbitals(C0, S, k, seed=131 + rid) for k in range(3)]
+        return Request(rid=rid, mol=mol, orbitals=orbs, arrival=0.0)
+
+    reqs = [make(i, n) for i, n in enumerate([1, 3, 2, 3])]
+    Server(GpuExecutor(), max_active=3, hbm_budget_bytes=8 << 30).serve(reqs)
+    for r in reqs:
+        assert r.error is None, r.error
+        ref = oracle.dfjk(r.mol, C=r.orbitals[-1])
+        assert np.abs(r.J_last - ref["J"]).max() <= 1e-10 * np.abs(ref["J"]).max()
+        assert np.abs(r.K_last - ref["K"]).max() <= 1e-10 * np.abs(ref["K"]).max()
+        assert abs(r.energies[-1, 0] - ref["EJ"]) <= 1e-10 * abs(ref["EJ"])
+        assert abs(r.energies[-1, 1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
