@@ -279,7 +279,14 @@ int dfjk_build_uks(dfjk_plan *plan, const double *d_Ca, int32_t nocc_a, const do
  *
  * dfjk_direct_stats: kept pairs per class (s-s, p-s, p-p, d-s, d-p, d-d) in
  * pairs[6] and the number of (bra pair, ket pair) combinations that pass the
- * screen. */
+ * screen.
+ *
+ * Errors (nothing is enqueued on failure): DFJK_E_STATE before dfjk_screen
+ * (tables) or dfjk_direct_setup (builds, stats), or on a device other than
+ * the one the tables were set up on; DFJK_E_OOM when the tables or the
+ * scratch are smaller than the *_bytes query; DFJK_E_INVALID for a NULL
+ * pointer, both or neither of d_C and d_D, nocc out of range, or outputs
+ * that alias each other (or J0, K0 below). */
 int dfjk_direct_bytes(const dfjk_plan *plan, size_t *table_bytes);
 int dfjk_direct_setup(dfjk_plan *plan, void *d_tables, size_t bytes, void *stream);
 int dfjk_direct_stats(const dfjk_plan *plan, int64_t *pairs, int64_t *quartets);
