@@ -31,8 +31,8 @@
 // per step and blockIdx.z takes one row of the first bra shell.  The ket
 // loop stops for the whole wave at the first step whose leading ket pair
 // has Q_cd * Q_max(wave) below the threshold; lanes whose own bound fails
-// sit out that step.  blockIdx.y splits the ket range so that a launch has
-// enough waves to fill the chip; the Hermite J vectors of the splits are
+// sit out that step.  blockIdx.y splits the ket range into short pieces so
+// that a launch has many waves; the Hermite J vectors of the splits are
 // summed with FP64 atomics.
 #include "dfjk_internal.h"
 #include "hermite.h"
@@ -472,10 +472,13 @@ static void launch_shape(const DirectClassDev &bra, const DirectClassDev &ket, d
     using S = QuartetShape<TILED, LA>;
     const int gx = (bra.n + S::TB - 1) / S::TB;
     const int gz = S::split_a ? 2 * LA + 1 : 1;
-    // enough blocks to fill the chip: split the ket range (the plain shape
-    // keeps at least 16 ket pairs per split to amortise the bra set-up)
-    const int minchunk = S::heavy ? S::TK : 16;
-    const int want = std::max(1, (8192 + gx * gz - 1) / (gx * gz));
+    // split the ket range into about 32768 waves per launch, at least two
+    // ket pairs (or one tile step) per split: with pairs sorted by Schwarz
+    // factor, short splits let the many waves whose bound fails early end
+    // early, and the long loops of the leading pairs spread over the chip
+    // (measured against 4096 / 8192 / 16384 waves and 4-32 pairs)
+    const int minchunk = S::heavy ? S::TK : 2;
+    const int want = std::max(1, (32768 + gx * gz - 1) / (gx * gz));
     const int nchunk = std::max(1, std::min(want, (ket.n + minchunk - 1) / minchunk));
     int kchunk = (ket.n + nchunk - 1) / nchunk;
     kchunk = (kchunk + S::TK - 1) / S::TK * S::TK;
