@@ -112,8 +112,15 @@ int dfjk_options_default(dfjk_options *opt);
 
 /* Host preparation (no device work): validates the molecule, orders the
  * auxiliary shells by angular momentum and enumerates AO shell pairs.
+ * Passage: the paper's problem statement is a PySCF molecule with an AO
+ * basis and an auxiliary (fitting) basis, density fitting being its
+ * optimised SCF path (Introduction, contribution 1; Section 4.1 "Improved
+ * Compatibility with PySCF", the density_fit example).  The paper prints no
+ * data structure; the shell tables here are this library's.
  * coords: natm x 3 Bohr.  opt may be NULL (defaults).  *out receives a plan
- * that the caller releases with dfjk_plan_destroy. */
+ * that the caller releases with dfjk_plan_destroy.  Errors: DFJK_E_INVALID
+ * for NULL pointers, natm < 1, an atom index out of range, an exponent <= 0
+ * or a non-finite coordinate; DFJK_E_UNSUPPORTED for AO l > 2 or aux l > 3. */
 int dfjk_plan_create(int32_t natm, const double *coords, const dfjk_basis *ao,
                      const dfjk_basis *aux, const dfjk_options *opt, dfjk_plan **out);
 
@@ -124,15 +131,26 @@ int dfjk_plan_info(const dfjk_plan *plan, dfjk_info *info);
  * DFJK_EXPORT_B and the whitened samples of dfjk_sample use this order. */
 int dfjk_plan_aux_order(const dfjk_plan *plan, int32_t *out);
 
-/* Schwarz screening.  dfjk_screen_bytes gives the size of the device scratch
- * dfjk_screen needs; dfjk_screen computes Q_ab for every AO shell pair and
- * Q_P for every aux shell on the GPU, copies them back, and keeps the pairs
- * whose largest triplet bound reaches the threshold.  Synchronises `stream`. */
+/* Schwarz screening.  Passage: the paper ties error control to the Schwarz
+ * inequality |(ab|P)| <= sqrt|(ab|ab)| sqrt (P|P) (Section 5 "Limitations
+ * and Future Development: Mixed Precision") and attributes the sub-quartic
+ * growth of its timings to sparsity (Section 2.1 "Dataset and Performance").
+ * dfjk_screen_bytes gives the size of the device scratch dfjk_screen needs;
+ * dfjk_screen computes Q_ab for every AO shell pair and Q_P for every aux
+ * shell on the GPU, copies them back, and keeps the pairs whose largest
+ * triplet bound reaches the threshold.  Synchronises `stream`.  Errors:
+ * DFJK_E_INVALID (NULL plan or scratch), DFJK_E_OOM (scratch smaller than
+ * dfjk_screen_bytes), DFJK_E_DEVICE (HIP error, message attached). */
 int dfjk_screen_bytes(const dfjk_plan *plan, size_t *bytes);
 int dfjk_screen(dfjk_plan *plan, void *d_scratch, size_t bytes, void *stream);
 
 /* Per-molecule setup on the resident workspace: three-centre integrals,
- * metric, its Cholesky factor, L^{-1} and the whitened tensor B.  The
+ * metric, its Cholesky factor, L^{-1} and the whitened tensor B.  Passage:
+ * the three-centre integrals of density fitting computed on the GPU, after
+ * which everything is tensor contractions (Introduction, contribution 1),
+ * kept resident in GPU memory for small systems (Section 2.1 "Dataset and
+ * Performance").  The fitting formulas themselves are the textbook
+ * Coulomb-metric ones in the header comment; the paper prints none.  The
  * workspace stays borrowed until dfjk_plan_destroy (or the next setup) and
  * must not be touched by the caller meanwhile.  Returns DFJK_E_NOT_POSDEF
  * with the failing pivot in the message if the metric is not positive
@@ -140,7 +158,16 @@ int dfjk_screen(dfjk_plan *plan, void *d_scratch, size_t bytes, void *stream);
 int dfjk_setup_bytes(const dfjk_plan *plan, size_t *bytes);
 int dfjk_setup(dfjk_plan *plan, void *d_workspace, size_t bytes, void *stream);
 
-/* One J/K build.  Give exactly one of
+/* One J/K build: J, K, E_J, E_K from the resident B and the current
+ * orbitals or density, once per SCF iteration.  Passage: the tensor
+ * contractions after the three-centre integrals, run on matrix units
+ * (Introduction, contributions 1 and 2); the lower-precision variants follow
+ * Section 5 "Limitations and Future Development: Mixed Precision".
+ * Errors: DFJK_E_STATE before dfjk_setup; DFJK_E_INVALID for NULL outputs,
+ * both or neither of d_C and d_D, nocc out of range or an unknown
+ * precision; DFJK_E_UNSUPPORTED for the density route in a precision other
+ * than FP64; DFJK_E_OOM for scratch below dfjk_build_bytes.  Nothing is
+ * enqueued on failure.  Give exactly one of
  *   d_C: nao x nocc occupied orbitals (D = 2 C C^T), 1 <= nocc <= nao, or
  *   d_D: nao x nao symmetric density (nocc ignored; precision must be FP64).
  * Outputs: d_J, d_K (nao x nao, full symmetric), d_E[2] = {E_J, E_K}.
@@ -171,7 +198,12 @@ int dfjk_build_delta(dfjk_plan *plan, const double *d_C, const double *d_C0, int
                      const double *d_K0, int32_t precision, double *d_J, double *d_K, double *d_E,
                      void *d_scratch, size_t scratch_bytes, void *stream);
 
-/* A batch of n closed-shell builds (molecules of any sizes, each with its own
+/* Passage for batching: none in the paper, which runs one molecule at a
+ * time; this is the serving form the library adds for many small molecules.
+ * The contractions batched are those of dfjk_build (Introduction,
+ * contributions 1 and 2).  Errors as for dfjk_build, per molecule, checked
+ * for all n before anything is enqueued.
+ * A batch of n closed-shell builds (molecules of any sizes, each with its own
  * set-up plan, all on the current device) on one stream: the same results as
  * n dfjk_build calls with d_C[i] (nao_i x nocc[i]), up to the order of the
  * split-K sums, but the K contractions of all FP64 molecules whose

@@ -94,7 +94,6 @@ def test_arrivals_are_honoured():
 
 
 @pytest.mark.gpu
-@pytest.mark.gpu
 def test_results_identical_alone_and_in_the_mix():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
