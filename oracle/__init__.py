@@ -279,3 +279,61 @@ def exact_jk(mol, D):
     J = np.einsum("mnls,ls->mn", eri, D)
     K = np.einsum("mlns,ls->mn", eri, D)
     return J, K, 0.5 * float(np.sum(D * J)), -0.25 * float(np.sum(D * K))
+
+
+def dfjk_streamed(mol, Cs, rows, shell_step=16):
+    """Fitted J/K energies and sampled rows for molecules too large for the
+    dense path, from the same textbook definitions evaluated one slice of
+    auxiliary shells at a time (unscreened):
+
+        u_Q = sum_{mu nu} (mu nu|Q) D_{mu nu},  c = L^{-1} u,  E_J = 1/2 c.c
+        J_{mu nu} = sum_Q (mu nu|Q) w_Q,        w = L^{-T} c
+        T_{Q,mu i} = sum_nu (mu nu|Q) C_{nu i}, X = L^{-1} T
+        K = 2 sum_{P,i} X_{P,mu i} X_{P,nu i},  E_K = -1/4 Tr(D K)
+
+    with D = 2 C C^T and V = (P|Q) = L L^T.  This is J = sum_P B_P c_P and
+    the half-transform route of K with B = L^{-1} U, rearranged so that
+    neither U nor B is held whole (the (mu nu|Q) slices are recomputed for
+    the J pass).  Cs is a list of (nao, nocc) orbital matrices; returns one
+    dict per entry with E_J, E_K and the K and J rows listed in `rows`."""
+    import scipy.linalg
+
+    nao, naux = mol.nao, mol.naux
+    Ds = [density(C) for C in Cs]
+    L = cholesky(int2c(mol))
+    nsh = len(mol.aux_l)
+    u = [np.zeros(naux) for _ in Cs]
+    T = [np.zeros((naux, nao, C.shape[1])) for C in Cs]
+    p = 0
+    for c0 in range(0, nsh, shell_step):
+        U = int3c(mol, c0, min(nsh, c0 + shell_step))
+        m = U.shape[0]
+        for k, C in enumerate(Cs):
+            u[k][p:p + m] = U.reshape(m, -1) @ Ds[k].ravel()
+            T[k][p:p + m] = U @ C
+        p += m
+    rows = np.asarray(rows, dtype=np.int64)
+    out = []
+    for k, C in enumerate(Cs):
+        c = forward_subst(L, u[k][:, None])[:, 0]
+        X = forward_subst(L, T[k].reshape(naux, -1)).reshape(naux, nao, C.shape[1])
+        T[k] = None
+        A = np.ascontiguousarray(X.transpose(1, 0, 2)).reshape(nao, -1)
+        del X
+        K = 2.0 * (A @ A.T)
+        del A
+        out.append({"E_J": 0.5 * float(c @ c), "E_K": -0.25 * float(np.sum(Ds[k] * K)),
+                    "K_rows": K[rows].copy(), "c": c,
+                    "w": scipy.linalg.solve_triangular(L, c, trans="T", lower=True)})
+    Jr = [np.zeros((len(rows), nao)) for _ in Cs]
+    p = 0
+    for c0 in range(0, nsh, shell_step):
+        U = int3c(mol, c0, min(nsh, c0 + shell_step))
+        m = U.shape[0]
+        Ur = U[:, rows, :]
+        for k in range(len(Cs)):
+            Jr[k] += np.tensordot(out[k]["w"][p:p + m], Ur, axes=(0, 0))
+        p += m
+    for k in range(len(Cs)):
+        out[k]["J_rows"] = Jr[k]
+    return out

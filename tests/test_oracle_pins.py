@@ -2,6 +2,7 @@
 closed forms, a library routine, brute-force quadrature, exactness cases and
 invariants of Coulomb-metric density fitting.  All CPU-only."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -482,3 +483,148 @@ def test_uks_exact_two_centre_against_brute_force():
     assert np.abs(u["Kb"] - Kb).max() <= 1e-12 * np.abs(Kb).max()
     EK = -0.5 * (np.sum(Da * Ka) + np.sum(Db * Kb))
     assert abs(u["EK"] - EK) <= 1e-12 * abs(EK)
+
+
+def test_streamed_route_equals_dense_definition():
+    """The slice-by-slice evaluation used for large clusters (oracle.dfjk_streamed)
+    gives the dense path's E_J, E_K and J/K rows (3 waters, ragged last slice)."""
+    import workload as W
+    mol, S, C = W.build_case(3, geom_seed=103)
+    C2 = W.perturbed_orbitals(C, S, 1)
+    rows = [0, 5, 17, 44, 89]
+    res = oracle.dfjk_streamed(mol, [C, C2], rows, shell_step=7)
+    for Ck, r in zip([C, C2], res):
+        ref = oracle.dfjk(mol, C=Ck)
+        assert abs(r["E_J"] - ref["EJ"]) <= 1e-13 * abs(ref["EJ"])
+        assert abs(r["E_K"] - ref["EK"]) <= 1e-13 * abs(ref["EK"])
+        assert np.abs(r["K_rows"] - ref["K"][rows]).max() <= 1e-13 * np.abs(ref["K"]).max()
+        assert np.abs(r["J_rows"] - ref["J"][rows]).max() <= 1e-13 * np.abs(ref["J"]).max()
+
+
+def test_golden_water32_fixture_is_consistent():
+    """The stored 32-water oracle values obey the structure every fitted K has:
+    K rows are the rows of a symmetric matrix (K[r_a][r_b] = K[r_b][r_a]),
+    E_J > 0 > E_K, and builds 0 and 9 differ by a small orbital step."""
+    import json
+    path = os.path.join(os.path.dirname(__file__), "golden", "water32.json")
+    if not os.path.exists(path):
+        pytest.skip("water32.json not generated")
+    g = json.load(open(path))
+    rows = g["rows"]
+    for b in g["builds"].values():
+        K = np.asarray(b["K_rows"])
+        assert K.shape == (len(rows), g["nao"])
+        sub = K[:, rows]
+        assert np.abs(sub - sub.T).max() <= 1e-12 * np.abs(K).max()
+        J = np.asarray(b["J_rows"])
+        subj = J[:, rows]
+        assert np.abs(subj - subj.T).max() <= 1e-12 * np.abs(J).max()
+        assert b["E_J"] > 0 > b["E_K"]
+        # diagonal of K for D = 2 C C^T is >= 0 (K is positive semidefinite)
+        assert np.all(np.diag(sub) >= 0)
+    e0, e9 = g["builds"]["0"], g["builds"]["9"]
+    assert abs(e0["E_K"] - e9["E_K"]) < 0.05 * abs(e0["E_K"])
+
+
+# ---------------------------------------------------------------------------
+# Mixed-precision formats (oracle.mixed)
+
+def test_bf16_rounding_matches_torch():
+    """The bf16 rounding of oracle.mixed equals torch's float32 -> bfloat16
+    conversion (round to nearest even), ties and subnormals included."""
+    torch = pytest.importorskip("torch")
+    from oracle import mixed as M
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000),
+                        np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -1.0 - 2.0 ** -8, 1e-40, -3e-39])])
+    x32 = x.astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M._bf16(x32), ref)
+    hi, lo = M.split_bf16(x)
+    xs = x32.astype(np.float64)
+    normal = np.abs(xs) > 1e-30          # lo stays a normal number
+    assert np.all(np.abs(hi + lo - xs)[normal] <= 2.0 ** -17 * np.abs(xs)[normal])
+
+
+def test_int8_slices_digits_and_reconstruction():
+    from oracle import mixed as M
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((7, 1024)) * 10.0 ** rng.uniform(-12, 3, (7, 1024))
+    X[3, 256:512] = 0.0                                  # an all-zero block
+    X[4, 0] = 127.0 / 128.0 * 4.0                        # block max on the scale boundary
+    a, e = M.int8_slices(X, block=256, nslices=5)
+    assert np.abs(a[0]).max() <= 127 and all(np.abs(s).max() <= 64 for s in a[1:])
+    m = np.abs(X.reshape(7, 4, 256)).max(axis=2)
+    nz = m > 0
+    # e is the least integer with 2^e > max|x| 128/127
+    assert np.all(np.ldexp(1.0, e[nz]) > m[nz] * 128 / 127)
+    assert np.all(np.ldexp(1.0, e[nz] - 1) <= m[nz] * 128 / 127)
+    rec = sum(np.ldexp(s, -7 * (k + 1)) for k, s in enumerate(a)).reshape(7, 4, 256)
+    rec = rec * np.ldexp(1.0, e)[:, :, None]
+    scale = np.ldexp(1.0, e)[:, :, None] * np.ones((1, 1, 256))
+    assert np.all(np.abs(rec - X.reshape(7, 4, 256)) <= 2.0 ** -36 * scale)
+    assert np.all(a[0][3, 256:512] == 0)
+
+
+def test_int8_product_truncation_bound_and_limit():
+    """Kept orders i + j <= 4 stay within 2^-33 of the scale envelope of the
+    exact product; keeping every product of eight slices approaches it to
+    FP64 level (the slicing itself is exact)."""
+    from oracle import mixed as M
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((20, 512)) * 10.0 ** rng.uniform(-6, 1, (20, 512))
+    B = rng.standard_normal((12, 512)) * 10.0 ** rng.uniform(-6, 1, (12, 512))
+    exact = A @ B.T
+    S = M.int8_scale_envelope(A, B)
+    P = M.int8_product(A, B)
+    assert np.all(np.abs(P - exact) <= 2.0 ** -33 * S)
+    assert np.abs(P - exact).max() > 0
+    P8 = M.int8_product(A, B, nslices=8, keep=lambda i, j: True)
+    assert np.all(np.abs(P8 - exact) <= 2.0 ** -48 * S + 1e-15 * np.abs(A) @ np.abs(B).T)
+
+
+def _x_rows_water3():
+    """X of 3 waters (the mixed GPU test's case) as contraction rows, aux
+    functions in the library's internal order (shells sorted by l)."""
+    from oracle import mixed as M  # noqa: F401
+    z, x = W.water_cluster(3, W.cluster_box(3), 103)
+    mol = W.make_molecule(z, x)
+    S = W.overlap_by_quadrature(mol)
+    C = W.occupied_orbitals(S, mol.nelec // 2, 10)
+    U, V = oracle.int3c(mol), oracle.int2c(mol)
+    sh = np.argsort(mol.aux_l, kind="stable")
+    off = np.concatenate([[0], np.cumsum(2 * mol.aux_l + 1)])
+    perm = np.concatenate([np.arange(off[s], off[s + 1]) for s in sh])
+    L = oracle.cholesky(V[np.ix_(perm, perm)])
+    B = oracle.forward_subst(L, U[perm].reshape(len(perm), -1)).reshape(U.shape)
+    X = B @ C
+    naux, nao, nocc = X.shape
+    npad = (naux + 127) // 128 * 128
+    Xp = np.zeros((npad, nao, nocc + (nocc & 1)))
+    Xp[:naux, :, :nocc] = X
+    return Xp.transpose(1, 0, 2).reshape(nao, -1)
+
+
+def test_mixed_mutations_break_the_device_checks():
+    """Planted mistakes in the mixed formats exceed the tolerances the GPU
+    tests allow between the device result and the format's exact value
+    (tests/test_gpu_mixed.py) by a wide margin, so a kernel that made them
+    would fail: dropping any one of the 15 kept int8 products (tolerance
+    2^-39 S + 1e-13 max|K|) and dropping the hi.lo cross term of BF16x3
+    (tolerance 2^-15 2 sum |x||x|, the FP32 summation bound)."""
+    from oracle import mixed as M
+    A = _x_rows_water3()
+    K = 2 * A @ A.T
+    Ke = 2 * M.int8_product(A, A)
+    tight = 2.0 ** -39 * 2 * M.int8_scale_envelope(A, A) + 1e-13 * np.abs(K).max()
+    assert (np.abs(Ke - K) / tight).max() < 1e3     # the format's own error, for scale
+    for i in range(5):
+        for j in range(5 - i):
+            Km = 2 * M.int8_product(A, A, keep=lambda a, b, i=i, j=j: a + b <= 4 and (a, b) != (i, j))
+            assert (np.abs(Km - Ke) / tight).max() > 4.0, (i, j)
+    hi, lo = M.split_bf16(A)
+    Kf = 2 * (hi @ hi.T + hi @ lo.T + lo @ hi.T)
+    ab = np.abs(hi) + np.abs(lo)
+    acc = 2.0 ** -15 * 2 * (ab @ ab.T)
+    Kdrop = 2 * (hi @ hi.T + lo @ hi.T)
+    assert (np.abs(Kdrop - Kf) / acc).max() > 4.0
