@@ -508,7 +508,7 @@ def main():
     results = {}
     ref_E = None
     ref_K = None
-    modes = ["fp64"] + ([] if args.no_mixed else ["fp32", "bf16x3", "fp32_incr", "bf16x3_incr"])
+    modes = ["fp64"] + ([] if args.no_mixed else ["int8", "fp32", "bf16x3", "fp32_incr", "bf16x3_incr"])
     for prec in modes:
         for w in range(args.warmup):
             run_job(Plan, mol, Cd, prec, bufs, profile=False)

@@ -65,8 +65,15 @@ typedef enum {
 typedef enum {
     DFJK_FP64 = 0,           /* every step in FP64                              */
     DFJK_MIXED_FP32 = 1,     /* X stored FP32, K on FP32 MFMA, FP64 chunk sums   */
-    DFJK_MIXED_BF16X3 = 2    /* X split into BF16 hi+lo, K = hi.hi + hi.lo +
+    DFJK_MIXED_BF16X3 = 2,   /* X split into BF16 hi+lo, K = hi.hi + hi.lo +
                                 lo.hi on BF16 MFMA, FP32 chunks, FP64 sums       */
+    DFJK_MIXED_INT8 = 3      /* X split into five int8 slices under a power-of-
+                                two scale per 256-element block of each row
+                                (Ozaki scheme); K from the 15 slice products
+                                of combined order <= 6 on int8 MFMA with exact
+                                int32 sums, folded into FP64 once per block.
+                                Per product the dropped part is below
+                                2^-33 of the product of the two block scales */
 } dfjk_precision;
 
 /* One basis (AO or auxiliary): nshell uncontracted shells on atoms. */

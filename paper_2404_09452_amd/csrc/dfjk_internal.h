@@ -19,6 +19,43 @@ constexpr int kMaxLAux = 3;    // highest aux angular momentum
 constexpr int kPadAux = 128;   // aux dimension stored as a multiple of this (half-transform tile)
 constexpr int kPadF = 64;      // function-pair dimension stored as a multiple of this
 
+// Int8 slices of the half-transformed tensor (DFJK_MIXED_INT8).  Row mu of X
+// is cut into blocks of kI8Block contraction elements; each block has a
+// power-of-two scale 2^e (stored as a double) with |x| <= 127/128 2^e, and
+// x ~ 2^e sum_{s<kI8Slices} a_s 2^{-7(s+1)}, a_0 in [-127, 127], a_s in
+// [-64, 64].  Storage per row: chunks of kI8Chunk elements, each chunk the
+// kI8Slices slices one after another ([chunk][slice][64] bytes).  The
+// contraction index of a slab runs over column passes of the half transform,
+// then aux rows, then the pass's columns (its width rounded up to even, so
+// every pass region is a whole number of blocks; the pad column is zero).
+constexpr int kI8Slices = 5;
+constexpr int kI8Block = 256;
+constexpr int kI8Chunk = 64;
+
+// Contraction length of one aux slab of plen rows with ncol columns as the
+// precision stores it, and the bytes of its X buffers (main and second plane).
+inline int64_t x_kdim(int precision, int64_t plen, int64_t ncol)
+{
+    return plen * (precision == DFJK_MIXED_INT8 ? ncol + (ncol & 1) : ncol);
+}
+inline size_t x_bytes(int precision, int64_t rows, int64_t kdim)
+{
+    const size_t n = (size_t)rows * (size_t)kdim;
+    switch (precision) {
+    case DFJK_FP64: return n * 8;
+    case DFJK_MIXED_FP32: return n * 4;
+    case DFJK_MIXED_BF16X3: return n * 2;
+    default: return n * kI8Slices;
+    }
+}
+inline size_t x_lo_bytes(int precision, int64_t rows, int64_t kdim)
+{
+    if (precision == DFJK_MIXED_BF16X3) return (size_t)rows * (size_t)kdim * 2;
+    if (precision == DFJK_MIXED_INT8) return (size_t)rows * (size_t)(kdim / kI8Block) * 8;   // block scales
+    return 0;
+}
+inline bool valid_precision(int precision) { return precision >= DFJK_FP64 && precision <= DFJK_MIXED_INT8; }
+
 // Boys table: F_m(T_k) at T_k = k * h, 0 <= k < kBoysNT, 0 <= m < kBoysNM.
 constexpr double kBoysH = 0.05;
 constexpr double kBoysTMax = 40.0;

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_j_rows(const double *__restrict__ B, in
 // k = l/16), B = Cs[k][i] (lane: k = l/16, i = l%16); accumulator r holds
 // row P = l/16 + 4r.
 
-enum { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2 };
+enum { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2, OUT_I8 = 3 };
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 struct HTArgs {
@@ -144,7 +144,8 @@ struct HTArgs {
     int32_t ncol;
     const int32_t *hk_off, *hk_row, *hk_nu;
     void *X;                  // [nao][plen][ncol]: aux rows p_begin .. p_begin + plen - 1
-    void *Xlo;                // second plane for the BF16 split
+                              // (int8 slices: [nao][kdim/64][5][64], see kI8Slices)
+    void *Xlo;                // second plane for the BF16 split; block scales for int8
     int64_t p_begin, plen;    // aux slab (multiples of 128)
     const int32_t *order;     // blockIdx.y -> AO function (longest list first)
 };
@@ -157,6 +158,67 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float x)
     return (unsigned short)((u + rounding) >> 16);
 }
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+// Int8 output of one half-transform workgroup (mu, 128 aux rows p0.., the
+// column pass ic0.. of width w = min(NCOL, ncol - ic0), stored w_e = w
+// rounded up to even wide).  Contraction index inside the slab:
+//   k = plen * ic0 + (P - p_begin) * w_e + (col - ic0),
+// so the workgroup owns 128 w_e / 256 whole scale blocks.  Per block: the
+// largest |x| (LDS atomics on the bit pattern, which orders like the value
+// for non-negative doubles), e = the least exponent with 2^e >= |x|max
+// 128/127, the scale 2^e to g.Xlo; then x 2^-e = sum_s a_s 2^{-7(s+1)} by
+// repeated rounding, every step exact in FP64 (a_0 = rint(128 x 2^-e) in
+// [-127, 127], later a_s in [-64, 64]).  The pad column stores zeros.
+template <int NIB>
+__device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB], unsigned long long *bmax,
+                                         int *bexp, int mu, int64_t p0, int ic0, int NCOL, int tid, int lane,
+                                         int wave, int kl)
+{
+    const int w = min(NCOL, g.ncol - ic0), we = w + (w & 1);
+    const int64_t kbase = g.plen * ic0 + (p0 - g.p_begin) * we;     // a multiple of kI8Block
+    const int64_t kdim = g.plen * (int64_t)(g.ncol + (g.ncol & 1));
+    const int64_t nblk = kdim / kI8Block;
+    __syncthreads();   // bmax cleared by every thread (the k loop may not have run)
+#pragma unroll
+    for (int j = 0; j < NIB; ++j) {
+        const int c = j * 16 + (lane & 15);
+        if (c >= w) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int kl_ = (16 * wave + kl + 4 * r) * we + c;
+            atomicMax(&bmax[kl_ / kI8Block], (unsigned long long)__double_as_longlong(fabs(acc[j][r])));
+        }
+    }
+    __syncthreads();
+    const int nb = 128 * we / kI8Block;
+    if (tid < nb) {
+        const double m = __longlong_as_double((long long)bmax[tid]);
+        const int e = m > 0.0 ? ilogb(m * (128.0 / 127.0)) + 1 : 0;
+        bexp[tid] = e;
+        static_cast<double *>(g.Xlo)[(int64_t)mu * nblk + kbase / kI8Block + tid] = ldexp(1.0, e);
+    }
+    __syncthreads();
+    unsigned char *row = static_cast<unsigned char *>(g.X) + (int64_t)mu * kdim * kI8Slices;
+#pragma unroll
+    for (int j = 0; j < NIB; ++j) {
+        const int c = j * 16 + (lane & 15);
+        if (c >= we) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int kl_ = (16 * wave + kl + 4 * r) * we + c;
+            const int64_t k = kbase + kl_;
+            double t = c < w ? ldexp(acc[j][r], -bexp[kl_ / kI8Block]) : 0.0;
+            unsigned char *dst = row + (k / kI8Chunk) * (kI8Chunk * kI8Slices) + (k % kI8Chunk);
+#pragma unroll
+            for (int sl = 0; sl < kI8Slices; ++sl) {
+                t *= 128.0;
+                const double a = rint(t);
+                t -= a;
+                dst[sl * kI8Chunk] = (unsigned char)(signed char)(int)a;
+            }
+        }
+    }
+}
 
 // Workgroup (mu, 128-row P tile, column pass of NIB*16 columns) of eight
 // waves; wave w owns rows p0 + 16w .. +15 (one MFMA fragment).  The k list
@@ -179,6 +241,11 @@ void k_halftrans(HTArgs g)
     constexpr int NLA = KC * 128 / 2 / NT;              // double2 loads per thread per chunk (B) = 2
     __shared__ double Cs[2][KC * LDC];
     __shared__ double As[2][KC * LDA];
+    // int8 output: |x| maxima and exponents of the workgroup's scale blocks
+    // (128 rows x an even pass width w <= 256: at most 128 blocks)
+    __shared__ unsigned long long bmax[OUT == OUT_I8 ? 128 : 1];
+    __shared__ int bexp[OUT == OUT_I8 ? 128 : 1];
+    if (OUT == OUT_I8 && threadIdx.x < 128) bmax[threadIdx.x] = 0ull;
     const int mu = g.order[blockIdx.y];
     const int64_t p0 = g.p_begin + (int64_t)blockIdx.x * 128;
     const int ic0 = blockIdx.z * NCOL;
@@ -271,6 +338,10 @@ void k_halftrans(HTArgs g)
         buf ^= 1;
     }
 
+    if constexpr (OUT == OUT_I8) {
+        store_i8(g, acc, bmax, bexp, mu, p0, ic0, NCOL, tid, lane, wave, kl);
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < NIB; ++j) {
         const int col = ic0 + j * 16 + (lane & 15);
@@ -309,6 +380,16 @@ static void launch_halftrans(const HTArgs &h, int64_t nao, hipStream_t s)
         HT_CASE(9) HT_CASE(10) HT_CASE(11) HT_CASE(12) HT_CASE(13) HT_CASE(14) HT_CASE(15) HT_CASE(16)
     }
 #undef HT_CASE
+}
+
+static void dispatch_halftrans(int precision, const HTArgs &h, int64_t nao, hipStream_t s)
+{
+    switch (precision) {
+    case DFJK_FP64: launch_halftrans<OUT_F64>(h, nao, s); break;
+    case DFJK_MIXED_FP32: launch_halftrans<OUT_F32>(h, nao, s); break;
+    case DFJK_MIXED_BF16X3: launch_halftrans<OUT_BF16X2>(h, nao, s); break;
+    default: launch_halftrans<OUT_I8>(h, nao, s); break;
+    }
 }
 
 // Dense expansion for the D route: Bt[mu][P][nu] = B[f(mu,nu)][P] (0 elsewhere).
@@ -505,6 +586,9 @@ __global__ __launch_bounds__(256) void k_energies_grouped(EnergyGroup grp, doubl
 // (two per CU for these kernels) fit in one round, so no nearly empty last
 // round idles the chip; at least 256 k values per split.
 int mixed_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus);
+int i8_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus);
+void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, const double *sB, int64_t nao,
+                    int64_t kdim, int nsplit, double *part, hipStream_t s);
 
 static int choose_ksplit(int ntiles, int64_t kdim, int num_cus)
 {
@@ -530,7 +614,10 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.ntile = (int)((p.nao + kTileK - 1) / kTileK);
     L.delta = delta;
     // aux slab of the K build: X = nao x slab x ncol elements per operand
-    const size_t esz = precision == DFJK_FP64 ? 8 : (precision == DFJK_MIXED_FP32 ? 4 : 2);
+    // bytes of X per element (both BF16 planes; int8 slices plus block scales)
+    const double esz = precision == DFJK_FP64 ? 8.0
+                     : precision == DFJK_MIXED_FP32 ? 4.0
+                     : precision == DFJK_MIXED_BF16X3 ? 4.0 : kI8Slices + 8.0 / kI8Block;
     // automatic: the largest multiple of 128 whose slab-sized buffers (X, its low part,
     // the expanded B of the density route, the second operand of the increment) stay
     // within kAutoSlabBytes
@@ -542,20 +629,26 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     // GEMM shares the chip with the half transform while they overlap.
     const bool may_overlap = allow_overlap && !with_D && !delta && !p.host_B && p.naux_pad >= 2 * kPadAux;
     const double per_aux = (double)p.nao * L.ncol *
-                           ((double)esz + (precision == DFJK_MIXED_BF16X3 ? 2 : 0) + (with_D ? 8 : 0)) *
+                           (esz + (with_D ? 8 : 0)) *
                            (delta ? 2 : 1) * (may_overlap ? 2 : 1);
     int64_t slab = p.host_B ? p.host_slab
                  : p.aux_slab > 0 ? (int64_t)align_up((size_t)p.aux_slab, kPadAux)
                                   : (int64_t)(kAutoSlabBytes / per_aux) / kPadAux * kPadAux;
+    if (precision == DFJK_MIXED_INT8 && !p.host_B) {   // 128 rows of int8 slices below 4 GiB (32-bit offsets)
+        const int64_t ncol_e = L.ncol + (L.ncol & 1);
+        const int64_t cap = ((int64_t)UINT32_MAX / (128 * kI8Slices) / ncol_e) / kPadAux * kPadAux;
+        if (slab > cap) slab = cap;
+    }
     if (slab < kPadAux) slab = kPadAux;
     if (slab > p.naux_pad) slab = p.naux_pad;
     L.slab = slab;
     L.nslab = (p.naux_pad + slab - 1) / slab;
     L.overlap = may_overlap && L.nslab >= 2;
-    L.kdim = slab * L.ncol;
+    L.kdim = x_kdim(precision, slab, L.ncol);
     const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
-    L.nsplit_k = (precision == DFJK_FP64) ? choose_ksplit(ntiles, L.kdim, p.num_cus)
-                                          : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
+    L.nsplit_k = precision == DFJK_FP64 ? choose_ksplit(ntiles, L.kdim, p.num_cus)
+               : precision == DFJK_MIXED_INT8 ? i8_nsplit(p.nao, L.kdim, !delta, p.num_cus)
+                                              : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
     if (nsplit == 0 && !with_D && !delta) {   // a split count the autotuner measured for this shape
         const auto it = p.tuned_nsplit.find((int64_t)nocc * 4 + precision);
         if (it != p.tuned_nsplit.end()) nsplit = it->second;
@@ -576,16 +669,17 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.o_cpart = take((size_t)L.nsplit_c * p.naux_pad * 8);
     L.o_c = take((size_t)p.naux_pad * 8);
     const size_t nx = (size_t)p.nao * L.kdim;
-    L.o_X = take(nx * esz);
-    L.o_Xlo = precision == DFJK_MIXED_BF16X3 ? take(nx * 2) : 0;
+    const size_t xb = x_bytes(precision, p.nao, L.kdim), xlo = x_lo_bytes(precision, p.nao, L.kdim);
+    L.o_X = take(xb);
+    L.o_Xlo = xlo ? take(xlo) : 0;
     L.o_Bfull = with_D ? take(nx * 8) : 0;
     if (L.overlap) {
-        L.o_Xb = take(nx * esz);
-        L.o_Xblo = precision == DFJK_MIXED_BF16X3 ? take(nx * 2) : 0;
+        L.o_Xb = take(xb);
+        L.o_Xblo = xlo ? take(xlo) : 0;
     }
     if (delta) {
-        L.o_X2 = take(nx * esz);
-        L.o_X2lo = precision == DFJK_MIXED_BF16X3 ? take(nx * 2) : 0;
+        L.o_X2 = take(xb);
+        L.o_X2lo = xlo ? take(xlo) : 0;
         L.o_U = take((size_t)p.nao * nocc * 8);
         L.o_W = take((size_t)p.nao * nocc * 8);
     }
@@ -625,9 +719,7 @@ static void launch_ht(const Plan &p, int precision, const double *C, int32_t nco
                       void *X, void *Xlo, hipStream_t s)
 {
     HTArgs h{p.d.B, p.naux_pad, C, ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen, p.d.hk_order};
-    if (precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, p.nao, s);
-    else if (precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, p.nao, s);
-    else launch_halftrans<OUT_BF16X2>(h, p.nao, s);
+    dispatch_halftrans(precision, h, p.nao, s);
 }
 
 // Steps 5-6 for every aux slab: the half transform of C1 (and of C2 for the
@@ -647,6 +739,9 @@ static void slab_gemm(const BuildLayout &L, bool lower, const void *X, const voi
         g.ksplit = align_up((size_t)((kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
         g.alpha = 1.0; g.lower = lower ? 1 : 0; g.partial = part;
         gemm_f64<kTileK, false>(g, L.nsplit_k, s);
+    } else if (L.precision == DFJK_MIXED_INT8) {
+        launch_gemm_i8(lower, X, static_cast<const double *>(Xlo), Bop, static_cast<const double *>(Bop_lo), nao,
+                       kdim, L.nsplit_k, part, s);
     } else {
         launch_gemm_mixed(L.precision, lower, X, Xlo, Bop, Bop_lo, nao, kdim, L.nsplit_k, part, s);
     }
@@ -706,7 +801,8 @@ static void contract_slabs_overlapped(Plan &p, const BuildLayout &L, const doubl
         if (sl + 1 < L.nslab) ht(sl + 1);
         (void)hipStreamWaitEvent(s, p.ev_ht[b], 0);
         pr.mark(ST_K, true);
-        slab_gemm(L, true, X[b], Xlo[b], X[b], Xlo[b], nao, plen * ncol, Kpart + sl * slab_part, s);
+        slab_gemm(L, true, X[b], Xlo[b], X[b], Xlo[b], nao, x_kdim(L.precision, plen, ncol), Kpart + sl * slab_part,
+                  s);
         pr.mark(ST_K, false);
         (void)hipEventRecord(p.ev_kdone[b], s);
     }
@@ -732,7 +828,7 @@ static void contract_slabs(Plan &p, const BuildLayout &L, const double *C1, cons
     void *X2lo = L.o_X2lo ? scratch + L.o_X2lo : nullptr;
     for (int64_t sl = 0; sl < L.nslab; ++sl) {
         const int64_t pb = sl * L.slab, plen = (ld - pb < L.slab) ? ld - pb : L.slab;
-        const int64_t kdim = plen * ncol;
+        const int64_t kdim = x_kdim(L.precision, plen, ncol);
         pr.mark(ST_HALFTRANS, true);
         launch_ht(p, L.precision, C1, (int32_t)ncol, pb, plen, X, Xlo, s);
         if (L.delta)
@@ -1021,27 +1117,13 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
         pr.mark(ST_HALFTRANS, true);
         HTArgs h{stage[b], plen, C, (int32_t)L.ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, 0, plen,
                  p.d.hk_order};
-        if (L.precision == DFJK_FP64) launch_halftrans<OUT_F64>(h, nao, s);
-        else if (L.precision == DFJK_MIXED_FP32) launch_halftrans<OUT_F32>(h, nao, s);
-        else launch_halftrans<OUT_BF16X2>(h, nao, s);
+        dispatch_halftrans(L.precision, h, nao, s);
         pr.mark(ST_HALFTRANS, false);
         (void)hipEventRecord(p.ev_free[b], s);      // the staging buffer is read
         if (sl + 2 < L.nslab) copy_slab(sl + 2);
         pr.mark(ST_K, true);
-        const int64_t kdim = plen * L.ncol;
-        double *part = Kpart + sl * slab_part;
-        if (L.precision == DFJK_FP64) {
-            GemmArgs g{};
-            g.A = static_cast<const double *>(X); g.lda = kdim;
-            g.B = g.A; g.ldb = kdim;
-            g.M = g.N = nao;
-            g.k_begin = 0; g.k_end = kdim;
-            g.ksplit = align_up((size_t)((kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
-            g.alpha = 1.0; g.lower = 1; g.partial = part;
-            gemm_f64<kTileK, false>(g, L.nsplit_k, s);
-        } else {
-            launch_gemm_mixed(L.precision, true, X, Xlo, X, Xlo, nao, kdim, L.nsplit_k, part, s);
-        }
+        const int64_t kdim = x_kdim(L.precision, plen, L.ncol);
+        slab_gemm(L, true, X, Xlo, X, Xlo, nao, kdim, Kpart + sl * slab_part, s);
         pr.mark(ST_K, false);
     }
     pr.mark(ST_KREDUCE, true);

@@ -20,6 +20,9 @@
 //   both: accumulator r of lane l is D[4(l/16) + r][l%16].
 #include "dfjk_internal.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace dfjk {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -213,6 +216,237 @@ __global__ __launch_bounds__(256) void k_gemm_mixed(MixedArgs g)
                 const int col = wn * 64 + j * 16 + (lane & 15);
                 dst[row * T + col] = acc[i][j][r];
             }
+}
+
+// ---------------------------------------------------------------------------
+// Int8 slices (DFJK_MIXED_INT8), the Ozaki splitting of floating-point
+// products into exact integer ones (Ozaki, Ogita, Oishi & Rump, Numer.
+// Algorithms 59, 2012): with x = 2^{e_x} sum_i a_i 2^{-7(i+1)} and y alike,
+//   x y ~ 2^{e_x + e_y} sum_{t=0}^{4} 2^{-7(t+2)} sum_{i+j=t} a_i b_j,
+// the products of combined order i + j <= 4 (15 of the 25).  Each order t is
+// an exact int32 sum on v_mfma_i32_16x16x64_i8 over one scale block (256 k,
+// |sum| < 5 * 127 * 127 * 256 < 2^31), then the five orders are combined in
+// FP64 and added with the block's scale 2^{e_x + e_y} into FP64
+// accumulators.  The only rounding is the truncation of the slices.
+//
+// Workgroup: 128 rows x 64 columns of the output (half of a 128 x 128
+// partial tile, blockIdx.x = 2 tile + half), four waves of 64 x 32, each
+// 4 x 2 fragments of 16 x 16 with five int32 order accumulators (160
+// registers) and FP64 accumulators (64).  One wave per SIMD.  Operands move
+// straight from global memory into LDS (global_load_lds_dwordx4, no
+// registers): one wave instruction brings one MFMA operand fragment, 16 rows
+// x 64 k bytes of one slice, to 1 KB of LDS in lane order, so each later
+// fragment read is one contiguous 16-byte read per lane.  A chunk of 64 k is
+// 40 fragments of the 128 rows and 20 of the 64 columns (60 KB); two chunk
+// buffers, the next chunk in flight while the current one feeds the MFMAs,
+// one barrier per chunk.
+// 16x16x64 i8 layout: lane l supplies row l%16 and 16 consecutive k bytes of
+// k group l/16 for both operands; accumulator r of lane l is D[4(l/16)+r][l%16].
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+struct I8Args {
+    const unsigned char *A, *B;   // [M][kdim / 64][5][64] slices
+    const double *sA, *sB;        // [M][kdim / 256] block scales
+    int64_t kdim, M, ksplit;      // ksplit: a multiple of kI8Block
+    int ntm;
+    int lower;
+    double *partial;              // [split][tile][128][128]
+};
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_gemm_i8(I8Args g)
+{
+    constexpr int AR = 128, BR = 64;                                     // rows of the two operands
+    constexpr int FA = 8 * kI8Slices, FB = 4 * kI8Slices, NF = FA + FB;   // fragments per chunk
+    constexpr int CH = kI8Slices * kI8Chunk;                             // bytes of one row per chunk
+    static_assert(NF % 4 == 0, "fragments must split over the four waves");
+    __shared__ __attribute__((aligned(1024))) unsigned char sm[2][NF * 1024];
+
+    const int half = blockIdx.x & 1;
+    int tm, tn;
+    mixed_tile(blockIdx.x >> 1, g.lower, g.ntm, tm, tn);
+    const int64_t m0 = (int64_t)tm * T, n0 = (int64_t)tn * T + 64 * half;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+    const int64_t kb = (int64_t)blockIdx.y * g.ksplit;
+    const int64_t ke = min(kb + g.ksplit, g.kdim);
+    const int64_t rowb = g.kdim * kI8Slices;          // bytes per row
+    const int64_t nblk = g.kdim / kI8Block;
+
+    // this lane's byte offset for each fragment its wave loads, relative to
+    // the first row of the operand's 128-row tile (which is < M); rows past
+    // M read row M-1, whose products only reach outputs that are dropped.
+    // The host keeps 128 rows below 4 GiB.
+    const int64_t a0 = m0, b0 = (int64_t)tn * T;
+    uint32_t loff[NF / 4];
+#pragma unroll
+    for (int q = 0; q < NF / 4; ++q) {
+        const int f = wave + 4 * q;
+        const bool isA = f < FA;
+        const int rb = isA ? f % 8 : (f - FA) % 4;
+        const int64_t base = isA ? a0 : b0;
+        const int64_t r = min((isA ? m0 : n0) + rb * 16 + (lane & 15), g.M - 1);
+        loff[q] = (uint32_t)((r - base) * rowb + 16 * (lane >> 4));
+    }
+    auto load = [&](int64_t k0, int buf) {
+        const int64_t cb = (k0 / kI8Chunk) * CH;
+#pragma unroll
+        for (int q = 0; q < NF / 4; ++q) {
+            const int f = wave + 4 * q;
+            const bool isA = f < FA;
+            const int sl = isA ? f / 8 : (f - FA) / 4;
+            const unsigned char *base = (isA ? g.A + a0 * rowb : g.B + b0 * rowb) + cb + sl * kI8Chunk;
+            __builtin_amdgcn_global_load_lds((const void *)(base + loff[q]),
+                                             (__attribute__((address_space(3))) void *)(&sm[buf][f * 1024]), 16,
+                                             0, 0);
+        }
+    };
+
+    double acc[4][2][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+
+    // Block scales of the 128 rows and 64 columns, staged through LDS one
+    // block ahead: thread t < 192 loads its row's (column's) scale of the
+    // next block into a register at the start of a block and writes it to
+    // ssc[next % 2] at the start of the next block, at least three barriers
+    // before the fold of that block reads it.
+    __shared__ double ssc[2][AR + BR];
+    const int64_t srow_t = tid < AR ? m0 + tid : n0 + (tid - AR);
+    const double *sbase_t = tid < AR ? g.sA : g.sB;
+    const bool sown = tid < AR + BR && srow_t < g.M;
+    double snext = 0.0;
+    auto scale_fetch = [&](int64_t blk) {
+        snext = (sown && blk < nblk) ? sbase_t[srow_t * nblk + blk] : 0.0;
+    };
+
+    // One scale block per iteration: four chunks whose five order sums live
+    // only inside the iteration (the first chunk starts them from zero), then
+    // their FP64 fold.
+    if (kb < ke) {
+        scale_fetch(kb / kI8Block);
+        load(kb, 0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        int buf = 0;
+        for (int64_t k0 = kb; k0 < ke; k0 += kI8Block) {
+            const int64_t blk = k0 / kI8Block;
+            if (tid < AR + BR) ssc[blk & 1][tid] = snext;
+            scale_fetch(blk + 1);
+            i32x4 lev[5][4][2];
+#pragma unroll
+            for (int c = 0; c < kI8Block / kI8Chunk; ++c) {
+                const int64_t kc = k0 + c * kI8Chunk;
+                const bool more = kc + kI8Chunk < ke;
+                if (more) load(kc + kI8Chunk, buf ^ 1);
+                const unsigned char *Fa = sm[buf] + (wm * 4) * 1024 + lane * 16;
+                const unsigned char *Fb = sm[buf] + (FA + wn * 2) * 1024 + lane * 16;
+                i32x4 bf[kI8Slices][2];
+#pragma unroll
+                for (int sl = 0; sl < kI8Slices; ++sl)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        bf[sl][j] = *reinterpret_cast<const i32x4 *>(Fb + (sl * 4 + j) * 1024);
+#pragma unroll
+                for (int si = 0; si < kI8Slices; ++si) {
+                    i32x4 af[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        af[i] = *reinterpret_cast<const i32x4 *>(Fa + (si * 8 + i) * 1024);
+#pragma unroll
+                    for (int sj = 0; sj + si < kI8Slices; ++sj)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int j = 0; j < 2; ++j) {
+                                const i32x4 cin = (c == 0 && si == 0) ? i32x4{0, 0, 0, 0} : lev[si + sj][i][j];
+                                lev[si + sj][i][j] =
+                                    __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[sj][j], cin, 0, 0, 0);
+                            }
+                }
+                if (more) {
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                    __syncthreads();
+                    buf ^= 1;
+                }
+            }
+            // FP64 fold: sum_t 2^{-7t} (order t sum) times the block scales
+            const double *sc = ssc[blk & 1];
+            double sb[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) sb[j] = sc[AR + wn * 32 + j * 16 + (lane & 15)] * 0x1p-14;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double sa[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sa[r] = sc[wm * 64 + i * 16 + 4 * (lane >> 4) + r];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        double v = (double)lev[4][i][j][r];
+                        v = fma(v, 0x1p-7, (double)lev[3][i][j][r]);
+                        v = fma(v, 0x1p-7, (double)lev[2][i][j][r]);
+                        v = fma(v, 0x1p-7, (double)lev[1][i][j][r]);
+                        v = fma(v, 0x1p-7, (double)lev[0][i][j][r]);
+                        acc[i][j][r] = fma(v, sa[r] * sb[j], acc[i][j][r]);
+                    }
+            }
+        }
+    }
+    const int ntiles = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
+    double *dst = g.partial + ((int64_t)blockIdx.y * ntiles + (blockIdx.x >> 1)) * (int64_t)(T * T) + 64 * half;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+                const int col = wn * 32 + j * 16 + (lane & 15);
+                dst[row * T + col] = acc[i][j][r];
+            }
+}
+
+// Split count of the int8 K: workgroups run one per CU, all with the same
+// k length, so the time is (rounds of workgroups) x (k per split); take the
+// smallest count within 2% of the best, at least 4 scale blocks per split.
+int i8_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus)
+{
+    const int ntm = (int)((nao + T - 1) / T);
+    const int64_t wg = 2 * (int64_t)(lower ? ntm * (ntm + 1) / 2 : ntm * ntm);
+    const int slots = num_cus > 0 ? num_cus : 256;
+    const int64_t nblk = kdim / kI8Block;
+    const int maxs = (int)std::max<int64_t>(1, std::min<int64_t>(64, nblk / 4));
+    double best = 1e300;
+    std::vector<double> cost(maxs + 1);
+    for (int ns = 1; ns <= maxs; ++ns) {
+        const int64_t per = (nblk + ns - 1) / ns;
+        cost[ns] = (double)((wg * ns + slots - 1) / slots) * (double)per;
+        best = std::min(best, cost[ns]);
+    }
+    for (int ns = 1; ns <= maxs; ++ns)
+        if (cost[ns] <= 1.02 * best) return ns;
+    return 1;
+}
+
+void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, const double *sB, int64_t nao,
+                    int64_t kdim, int nsplit, double *part, hipStream_t s)
+{
+    I8Args g{};
+    g.A = static_cast<const unsigned char *>(A);
+    g.B = static_cast<const unsigned char *>(B);
+    g.sA = sA; g.sB = sB;
+    g.kdim = kdim; g.M = nao;
+    g.ntm = (int)((nao + T - 1) / T);
+    g.lower = lower ? 1 : 0;
+    g.ksplit = (int64_t)align_up((size_t)(((kdim / kI8Block) + nsplit - 1) / nsplit), 1) * kI8Block;
+    g.partial = part;
+    const int ntiles = lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
+    hipLaunchKernelGGL(k_gemm_i8, dim3(2 * ntiles, nsplit), dim3(256), 0, s, g);
 }
 
 // Split count: one round of workgroups (two per CU), each split a multiple

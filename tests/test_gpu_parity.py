@@ -161,20 +161,6 @@ def test_delta_build_mixed_error_shrinks_with_the_step(cluster3_seq, prec):
     assert np.abs(Kd - Kd.T).max() == 0.0
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_mixed_precision_error_is_reported(prec):
-    mol, S, C = case(3)
-    plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
-    J64, K64, E64 = (t.cpu().numpy() for t in plan.build(C=C))
-    J, K, E = (t.cpu().numpy() for t in plan.build(C=C, precision=prec))
-    dEJ, dEK, dK = abs(E[0] - E64[0]), abs(E[1] - E64[1]), np.abs(K - K64).max()
-    print("%s: |dE_J| %.3e |dE_K| %.3e max|dK| %.3e (E_K %.6f)" % (prec, dEJ, dEK, dK, E64[1]))
-    assert np.array_equal(J, J64)          # J and E_J stay FP64
-    assert dEJ == 0.0
-    bound = 1e-5 if prec == "fp32" else 1e-3
-    assert dEK <= bound * abs(E64[1])
-
-
 @pytest.fixture(scope="module")
 def cluster5():
     mol, S, C = case(5)
@@ -246,7 +232,7 @@ def test_uks_closed_shell_matches_rks(cluster5):
     assert abs(E[1] - E1[1]) <= 1e-13 * abs(E1[1])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "int8"])
 def test_build_replays_in_a_hip_graph(cluster3_seq, prec):
     """A whole build captured once in a HIP graph and replayed with new orbitals
     written into the captured input: every replay equals an eager build bitwise
@@ -288,7 +274,7 @@ def batch_set():
     return cases, plans
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "int8"])
 def test_batch_matches_single_builds(batch_set, prec):
     cases, plans = batch_set
     Cs = [C for _, _, C in cases]
@@ -305,9 +291,11 @@ def test_batch_matches_single_builds(batch_set, prec):
             assert abs(E[1] - E1[1]) <= 1e-13 * abs(E1[1])
         else:
             # the batch contracts one aux slab where a single build may use two
-            # (overlapped), which moves the FP32 chunk boundaries
-            assert rel(K, K1) <= 1e-6
-            assert abs(E[1] - E1[1]) <= 1e-6 * abs(E1[1])
+            # (overlapped), which moves the FP32 chunk boundaries (int8: the
+            # scale blocks, at the 2^-33 truncation level)
+            tol = 1e-9 if prec == "int8" else 1e-6
+            assert rel(K, K1) <= tol
+            assert abs(E[1] - E1[1]) <= tol * abs(E1[1])
     if prec == "fp64":   # one molecule against the oracle
         mol, _, C = cases[2]
         ref = oracle.dfjk(mol, C=C)
