@@ -438,6 +438,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--modes", default=None,
+                    help="comma-separated water32 modes after fp64 (default: every mixed mode)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=96)
@@ -509,6 +511,8 @@ def main():
     ref_E = None
     ref_K = None
     modes = ["fp64"] + ([] if args.no_mixed else ["int8", "fp32", "bf16x3", "fp32_incr", "bf16x3_incr"])
+    if args.modes:
+        modes = ["fp64"] + [m for m in args.modes.split(",") if m != "fp64"]
     for prec in modes:
         for w in range(args.warmup):
             run_job(Plan, mol, Cd, prec, bufs, profile=False)

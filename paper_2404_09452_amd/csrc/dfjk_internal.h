@@ -28,6 +28,7 @@ constexpr int kPadF = 64;      // function-pair dimension stored as a multiple o
 // contraction index of a slab runs over column passes of the half transform,
 // then aux rows, then the pass's columns (its width rounded up to even, so
 // every pass region is a whole number of blocks; the pad column is zero).
+constexpr int kXcds = 8;        // accelerator complex dies of an MI355X, each with its own L2
 constexpr int kI8Slices = 5;
 constexpr int kI8Block = 256;
 constexpr int kI8Chunk = 64;

@@ -163,22 +163,26 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_a
 // column pass ic0.. of width w = min(NCOL, ncol - ic0), stored w_e = w
 // rounded up to even wide).  Contraction index inside the slab:
 //   k = plen * ic0 + (P - p_begin) * w_e + (col - ic0),
-// so the workgroup owns 128 w_e / 256 whole scale blocks.  Per block: the
+// so the workgroup owns 128 w_e / 256 whole scale blocks and one contiguous
+// byte range of the row (chunks of 64 k, five slices each).  Per block: the
 // largest |x| (LDS atomics on the bit pattern, which orders like the value
-// for non-negative doubles), e = the least exponent with 2^e >= |x|max
+// for non-negative doubles), e = the least exponent with 2^e > |x|max
 // 128/127, the scale 2^e to g.Xlo; then x 2^-e = sum_s a_s 2^{-7(s+1)} by
 // repeated rounding, every step exact in FP64 (a_0 = rint(128 x 2^-e) in
-// [-127, 127], later a_s in [-64, 64]).  The pad column stores zeros.
+// [-127, 127], later a_s in [-64, 64]).  The pad column stores zeros.  The
+// bytes of 64 aux rows at a time (waves 0-3, then 4-7) are assembled in LDS
+// (`stage`, the operand buffers of the finished k loop) and written out as
+// 16-byte pieces, so every HBM line is written whole.
 template <int NIB>
 __device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB], unsigned long long *bmax,
-                                         int *bexp, int mu, int64_t p0, int ic0, int NCOL, int tid, int lane,
-                                         int wave, int kl)
+                                         int *bexp, unsigned char *stage, int mu, int64_t p0, int ic0, int NCOL,
+                                         int tid, int lane, int wave, int kl)
 {
     const int w = min(NCOL, g.ncol - ic0), we = w + (w & 1);
     const int64_t kbase = g.plen * ic0 + (p0 - g.p_begin) * we;     // a multiple of kI8Block
     const int64_t kdim = g.plen * (int64_t)(g.ncol + (g.ncol & 1));
     const int64_t nblk = kdim / kI8Block;
-    __syncthreads();   // bmax cleared by every thread (the k loop may not have run)
+    __syncthreads();   // bmax cleared by every thread; the k loop's LDS reads are done
 #pragma unroll
     for (int j = 0; j < NIB; ++j) {
         const int c = j * 16 + (lane & 15);
@@ -188,6 +192,7 @@ __device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB
             const int kl_ = (16 * wave + kl + 4 * r) * we + c;
             atomicMax(&bmax[kl_ / kI8Block], (unsigned long long)__double_as_longlong(fabs(acc[j][r])));
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     const int nb = 128 * we / kI8Block;
@@ -198,25 +203,38 @@ __device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB
         static_cast<double *>(g.Xlo)[(int64_t)mu * nblk + kbase / kI8Block + tid] = ldexp(1.0, e);
     }
     __syncthreads();
-    unsigned char *row = static_cast<unsigned char *>(g.X) + (int64_t)mu * kdim * kI8Slices;
+    const int hb = 64 * we * kI8Slices;                               // bytes of 64 aux rows
+    unsigned char *dst0 = static_cast<unsigned char *>(g.X) + (int64_t)mu * kdim * kI8Slices +
+                          (kbase / kI8Chunk) * (kI8Chunk * kI8Slices);
+    for (int h = 0; h < 2; ++h) {
+        if ((wave >> 2) == h) {
 #pragma unroll
-    for (int j = 0; j < NIB; ++j) {
-        const int c = j * 16 + (lane & 15);
-        if (c >= we) continue;
+            for (int j = 0; j < NIB; ++j) {
+                const int c = j * 16 + (lane & 15);
+                if (c >= we) continue;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int kl_ = (16 * wave + kl + 4 * r) * we + c;
-            const int64_t k = kbase + kl_;
-            double t = c < w ? ldexp(acc[j][r], -bexp[kl_ / kI8Block]) : 0.0;
-            unsigned char *dst = row + (k / kI8Chunk) * (kI8Chunk * kI8Slices) + (k % kI8Chunk);
+                for (int r = 0; r < 4; ++r) {
+                    const int kl_ = (16 * wave + kl + 4 * r) * we + c;
+                    const int kh = kl_ - h * 64 * we;
+                    double t = c < w ? ldexp(acc[j][r], -bexp[kl_ / kI8Block]) : 0.0;
+                    unsigned char *d = stage + (kh / kI8Chunk) * (kI8Chunk * kI8Slices) + (kh % kI8Chunk);
 #pragma unroll
-            for (int sl = 0; sl < kI8Slices; ++sl) {
-                t *= 128.0;
-                const double a = rint(t);
-                t -= a;
-                dst[sl * kI8Chunk] = (unsigned char)(signed char)(int)a;
+                    for (int sl = 0; sl < kI8Slices; ++sl) {
+                        t *= 128.0;
+                        const double a = rint(t);
+                        t -= a;
+                        d[sl * kI8Chunk] = (unsigned char)(signed char)(int)a;
+                    }
+                }
+                // one fragment column at a time: keeps the epilogue's live
+                // registers within the k loop's budget
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
+        __syncthreads();
+        for (int i = tid * 16; i < hb; i += 512 * 16)
+            *reinterpret_cast<uint4 *>(dst0 + h * hb + i) = *reinterpret_cast<const uint4 *>(stage + i);
+        __syncthreads();
     }
 }
 
@@ -239,8 +257,12 @@ void k_halftrans(HTArgs g)
     constexpr int LDA = 128 + 16;                       // same for the 128-wide tensor rows
     constexpr int NLC = (KC * NCOL / 2 + NT - 1) / NT;  // double2 loads per thread per chunk (C)
     constexpr int NLA = KC * 128 / 2 / NT;              // double2 loads per thread per chunk (B) = 2
-    __shared__ double Cs[2][KC * LDC];
-    __shared__ double As[2][KC * LDA];
+    // one LDS block for both operand buffers, so the int8 output can reuse
+    // all of it as its staging area after the k loop
+    __shared__ __attribute__((aligned(16))) double smem[2 * KC * LDC + 2 * KC * LDA];
+    double (*Cs)[KC * LDC] = reinterpret_cast<double (*)[KC * LDC]>(smem);
+    double (*As)[KC * LDA] = reinterpret_cast<double (*)[KC * LDA]>(smem + 2 * KC * LDC);
+    static_assert(sizeof(smem) >= (size_t)(kI8Slices * 64) * NCOL, "int8 staging must fit the operand buffers");
     // int8 output: |x| maxima and exponents of the workgroup's scale blocks
     // (128 rows x an even pass width w <= 256: at most 128 blocks)
     __shared__ unsigned long long bmax[OUT == OUT_I8 ? 128 : 1];
@@ -339,7 +361,8 @@ void k_halftrans(HTArgs g)
     }
 
     if constexpr (OUT == OUT_I8) {
-        store_i8(g, acc, bmax, bexp, mu, p0, ic0, NCOL, tid, lane, wave, kl);
+        store_i8(g, acc, bmax, bexp, reinterpret_cast<unsigned char *>(smem), mu, p0, ic0, NCOL, tid, lane, wave,
+                 kl);
         return;
     }
 #pragma unroll

@@ -244,30 +244,68 @@ __global__ __launch_bounds__(256) void k_gemm_mixed(MixedArgs g)
 // k group l/16 for both operands; accumulator r of lane l is D[4(l/16)+r][l%16].
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
+// s_waitcnt immediates (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt
+// 6:4, lgkmcnt 11:8; a field at its maximum does not wait).  Issued through
+// the builtin so the compiler's own wait insertion knows what has retired.
+constexpr int kWaitVm15 = 15 | (7 << 4) | (15 << 8);             // vmcnt(15)
+constexpr int kWaitVm0 = 0 | (7 << 4) | (15 << 8);               // vmcnt(0)
+constexpr int kWaitLgkm0 = 15 | (7 << 4) | (0 << 8) | (3 << 14);  // lgkmcnt(0)
+constexpr int kI8WavesM = 4;   // waves along the 128 rows: 2 (one wave per SIMD) or 4 (two)
+
 struct I8Args {
     const unsigned char *A, *B;   // [M][kdim / 64][5][64] slices
     const double *sA, *sB;        // [M][kdim / 256] block scales
     int64_t kdim, M, ksplit;      // ksplit: a multiple of kI8Block
     int ntm;
     int lower;
+    int nsplit;
     double *partial;              // [split][tile][128][128]
 };
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// WGM x WGN waves, each RB x CB fragments of 16 x 16 (the workgroup tile
+// is always 128 x 64).  Fragments of a chunk are spread over the waves,
+// NFW per wave, padded with loads into a spare LDS slot so that every wave
+// issues the same count (the vmcnt immediate below).
+template <int WGM, int WGN, int RB, int CB>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4)))
 void k_gemm_i8(I8Args g)
 {
-    constexpr int AR = 128, BR = 64;                                     // rows of the two operands
-    constexpr int FA = 8 * kI8Slices, FB = 4 * kI8Slices, NF = FA + FB;   // fragments per chunk
+    constexpr int NW = WGM * WGN, NT = 64 * NW;
+    constexpr int AR = WGM * RB * 16, BR = WGN * CB * 16;                 // rows of the two operands
+    static_assert(AR == T && BR == T / 2, "the workgroup tile is half of a 128 x 128 partial tile");
+    constexpr int RBA = AR / 16, RBB = BR / 16;
+    constexpr int FA = RBA * kI8Slices, FB = RBB * kI8Slices, NF = FA + FB;   // fragments per chunk
+    constexpr int NFW = (NF + NW - 1) / NW, NFS = NFW * NW;              // per wave; slots incl. spares
     constexpr int CH = kI8Slices * kI8Chunk;                             // bytes of one row per chunk
-    static_assert(NF % 4 == 0, "fragments must split over the four waves");
-    __shared__ __attribute__((aligned(1024))) unsigned char sm[2][NF * 1024];
+    static_assert(NFW <= 15, "vmcnt immediate holds 4 bits here");
+    constexpr int kWaitVmNFW = NFW | (7 << 4) | (15 << 8);              // vmcnt(NFW)
+    // two chunk buffers as separate arrays: the compiler can then tell a
+    // read of one from a DMA into the other (which buffer is known at
+    // compile time below) and does not wait for unrelated loads
+    __shared__ __attribute__((aligned(1024))) unsigned char sm0[NFS * 1024];
+    __shared__ __attribute__((aligned(1024))) unsigned char sm1[NFS * 1024];
 
-    const int half = blockIdx.x & 1;
+    // workgroup -> (split, tile, half).  With a split count that is a multiple
+    // of the XCD count, XCD x (workgroups are dispatched round-robin over the
+    // XCDs) runs whole splits x, x + 8, ..., so each XCD's L2 holds one k
+    // range of X for every tile of a split.
+    const int nth = 2 * (g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm);   // tile halves per split
+    int split, th;
+    if (g.nsplit % kXcds == 0) {
+        const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+        split = xcd + kXcds * (local / nth);
+        th = local % nth;
+    } else {
+        split = blockIdx.x / nth;
+        th = blockIdx.x % nth;
+    }
+    const int half = th & 1, tile = th >> 1;
     int tm, tn;
-    mixed_tile(blockIdx.x >> 1, g.lower, g.ntm, tm, tn);
+    mixed_tile(tile, g.lower, g.ntm, tm, tn);
     const int64_t m0 = (int64_t)tm * T, n0 = (int64_t)tn * T + 64 * half;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-    const int64_t kb = (int64_t)blockIdx.y * g.ksplit;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave / WGN, wn = wave % WGN;
+    const int64_t kb = (int64_t)split * g.ksplit;
     const int64_t ke = min(kb + g.ksplit, g.kdim);
     const int64_t rowb = g.kdim * kI8Slices;          // bytes per row
     const int64_t nblk = g.kdim / kI8Block;
@@ -275,37 +313,38 @@ void k_gemm_i8(I8Args g)
     // this lane's byte offset for each fragment its wave loads, relative to
     // the first row of the operand's 128-row tile (which is < M); rows past
     // M read row M-1, whose products only reach outputs that are dropped.
-    // The host keeps 128 rows below 4 GiB.
+    // Spare slots re-read the first A fragment.  The host keeps 128 rows
+    // below 4 GiB.
     const int64_t a0 = m0, b0 = (int64_t)tn * T;
-    uint32_t loff[NF / 4];
+    uint32_t loff[NFW];
 #pragma unroll
-    for (int q = 0; q < NF / 4; ++q) {
-        const int f = wave + 4 * q;
-        const bool isA = f < FA;
-        const int rb = isA ? f % 8 : (f - FA) % 4;
+    for (int q = 0; q < NFW; ++q) {
+        const int f = wave + NW * q;
+        const bool isA = f < FA || f >= NF;
+        const int rb = f >= NF ? 0 : isA ? f % RBA : (f - FA) % RBB;
         const int64_t base = isA ? a0 : b0;
         const int64_t r = min((isA ? m0 : n0) + rb * 16 + (lane & 15), g.M - 1);
         loff[q] = (uint32_t)((r - base) * rowb + 16 * (lane >> 4));
     }
-    auto load = [&](int64_t k0, int buf) {
+    auto load = [&](int64_t k0, unsigned char *dstbuf) {
         const int64_t cb = (k0 / kI8Chunk) * CH;
 #pragma unroll
-        for (int q = 0; q < NF / 4; ++q) {
-            const int f = wave + 4 * q;
-            const bool isA = f < FA;
-            const int sl = isA ? f / 8 : (f - FA) / 4;
+        for (int q = 0; q < NFW; ++q) {
+            const int f = wave + NW * q;
+            const bool isA = f < FA || f >= NF;
+            const int sl = f >= NF ? 0 : isA ? f / RBA : (f - FA) / RBB;
             const unsigned char *base = (isA ? g.A + a0 * rowb : g.B + b0 * rowb) + cb + sl * kI8Chunk;
             __builtin_amdgcn_global_load_lds((const void *)(base + loff[q]),
-                                             (__attribute__((address_space(3))) void *)(&sm[buf][f * 1024]), 16,
+                                             (__attribute__((address_space(3))) void *)(dstbuf + f * 1024), 16,
                                              0, 0);
         }
     };
 
-    double acc[4][2][4];
+    double acc[RB][CB][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < CB; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
 
@@ -325,66 +364,76 @@ void k_gemm_i8(I8Args g)
 
     // One scale block per iteration: four chunks whose five order sums live
     // only inside the iteration (the first chunk starts them from zero), then
-    // their FP64 fold.
+    // their FP64 fold.  Chunks run two ahead: a chunk's fragments are read
+    // from LDS into registers first, then (after a barrier: every wave has
+    // read that buffer) the DMA of the chunk two ahead goes into the same
+    // buffer, then the MFMAs run.  The DMA of the next chunk was issued one
+    // chunk earlier; waiting for it leaves the NFW newer loads of each wave
+    // in flight (vmcnt counts a wave's loads and they retire in order).
+    // Barriers without memory fences keep those loads outstanding across them.
+    const int64_t nch = (ke - kb) / kI8Chunk;
     if (kb < ke) {
         scale_fetch(kb / kI8Block);
-        load(kb, 0);
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        int buf = 0;
+        // every chunk step issues one DMA (past the end: the last chunk again,
+        // never read), so each wait below keeps exactly one chunk in flight
+        auto chunk_k = [&](int64_t ci) { return kb + min(ci, nch - 1) * kI8Chunk; };
+        load(chunk_k(0), sm0);
+        load(chunk_k(1), sm1);
+        __builtin_amdgcn_s_waitcnt(kWaitVmNFW);
+        __builtin_amdgcn_s_barrier();
         for (int64_t k0 = kb; k0 < ke; k0 += kI8Block) {
             const int64_t blk = k0 / kI8Block;
             if (tid < AR + BR) ssc[blk & 1][tid] = snext;
             scale_fetch(blk + 1);
-            i32x4 lev[5][4][2];
+            i32x4 lev[5][RB][CB];
 #pragma unroll
             for (int c = 0; c < kI8Block / kI8Chunk; ++c) {
-                const int64_t kc = k0 + c * kI8Chunk;
-                const bool more = kc + kI8Chunk < ke;
-                if (more) load(kc + kI8Chunk, buf ^ 1);
-                const unsigned char *Fa = sm[buf] + (wm * 4) * 1024 + lane * 16;
-                const unsigned char *Fb = sm[buf] + (FA + wn * 2) * 1024 + lane * 16;
-                i32x4 bf[kI8Slices][2];
+                const int64_t ci = (k0 - kb) / kI8Chunk + c;     // chunk index in this split (ci % 2 == c % 2)
+                unsigned char *cur = (c & 1) ? sm1 : sm0;
+                const unsigned char *Fa = cur + (wm * RB) * 1024 + lane * 16;
+                const unsigned char *Fb = cur + (FA + wn * CB) * 1024 + lane * 16;
+                i32x4 bf[kI8Slices][CB], af[kI8Slices][RB];
 #pragma unroll
-                for (int sl = 0; sl < kI8Slices; ++sl)
+                for (int sl = 0; sl < kI8Slices; ++sl) {
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        bf[sl][j] = *reinterpret_cast<const i32x4 *>(Fb + (sl * 4 + j) * 1024);
+                    for (int j = 0; j < CB; ++j)
+                        bf[sl][j] = *reinterpret_cast<const i32x4 *>(Fb + (sl * RBB + j) * 1024);
 #pragma unroll
-                for (int si = 0; si < kI8Slices; ++si) {
-                    i32x4 af[4];
+                    for (int i = 0; i < RB; ++i)
+                        af[sl][i] = *reinterpret_cast<const i32x4 *>(Fa + (sl * RBA + i) * 1024);
+                }
+                __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+                __builtin_amdgcn_s_barrier();
+                load(chunk_k(ci + 2), cur);
+                __builtin_amdgcn_sched_barrier(0);   // the DMA goes out before the MFMAs
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        af[i] = *reinterpret_cast<const i32x4 *>(Fa + (si * 8 + i) * 1024);
+                for (int si = 0; si < kI8Slices; ++si)
 #pragma unroll
                     for (int sj = 0; sj + si < kI8Slices; ++sj)
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
+                        for (int i = 0; i < RB; ++i)
 #pragma unroll
-                            for (int j = 0; j < 2; ++j) {
+                            for (int j = 0; j < CB; ++j) {
                                 const i32x4 cin = (c == 0 && si == 0) ? i32x4{0, 0, 0, 0} : lev[si + sj][i][j];
                                 lev[si + sj][i][j] =
-                                    __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[sj][j], cin, 0, 0, 0);
+                                    __builtin_amdgcn_mfma_i32_16x16x64_i8(af[si][i], bf[sj][j], cin, 0, 0, 0);
                             }
-                }
-                if (more) {
-                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                    __syncthreads();
-                    buf ^= 1;
-                }
+                __builtin_amdgcn_sched_barrier(0);   // and the wait stays after them
+                __builtin_amdgcn_s_waitcnt(kWaitVmNFW);
+                __builtin_amdgcn_s_barrier();
             }
             // FP64 fold: sum_t 2^{-7t} (order t sum) times the block scales
             const double *sc = ssc[blk & 1];
-            double sb[2];
+            double sb[CB];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) sb[j] = sc[AR + wn * 32 + j * 16 + (lane & 15)] * 0x1p-14;
+            for (int j = 0; j < CB; ++j) sb[j] = sc[AR + (wn * CB + j) * 16 + (lane & 15)] * 0x1p-14;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < RB; ++i) {
                 double sa[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sa[r] = sc[wm * 64 + i * 16 + 4 * (lane >> 4) + r];
+                for (int r = 0; r < 4; ++r) sa[r] = sc[(wm * RB + i) * 16 + 4 * (lane >> 4) + r];
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < CB; ++j)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         double v = (double)lev[4][i][j][r];
@@ -396,36 +445,41 @@ void k_gemm_i8(I8Args g)
                     }
             }
         }
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);   // no DMA into LDS outlives the workgroup
     }
-    const int ntiles = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
-    double *dst = g.partial + ((int64_t)blockIdx.y * ntiles + (blockIdx.x >> 1)) * (int64_t)(T * T) + 64 * half;
+    double *dst = g.partial + ((int64_t)split * (nth / 2) + tile) * (int64_t)(T * T) + 64 * half;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < CB; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-                const int col = wn * 32 + j * 16 + (lane & 15);
+                const int row = (wm * RB + i) * 16 + 4 * (lane >> 4) + r;
+                const int col = (wn * CB + j) * 16 + (lane & 15);
                 dst[row * T + col] = acc[i][j][r];
             }
 }
 
 // Split count of the int8 K: workgroups run one per CU, all with the same
-// k length, so the time is (rounds of workgroups) x (k per split); take the
-// smallest count within 2% of the best, at least 4 scale blocks per split.
+// k length, so the time is (rounds of workgroups) x (k per split).  Counts
+// that are multiples of the XCD count run whole splits per XCD (rounds
+// counted per XCD); smaller k lengths fall back to any count.  The smallest
+// count within 2% of the best wins; at least 4 scale blocks per split.
 int i8_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus)
 {
     const int ntm = (int)((nao + T - 1) / T);
     const int64_t wg = 2 * (int64_t)(lower ? ntm * (ntm + 1) / 2 : ntm * ntm);
     const int slots = num_cus > 0 ? num_cus : 256;
+    const int xslots = std::max(1, slots / kXcds);
     const int64_t nblk = kdim / kI8Block;
     const int maxs = (int)std::max<int64_t>(1, std::min<int64_t>(64, nblk / 4));
+    std::vector<double> cost(maxs + 1, 1e300);
     double best = 1e300;
-    std::vector<double> cost(maxs + 1);
     for (int ns = 1; ns <= maxs; ++ns) {
         const int64_t per = (nblk + ns - 1) / ns;
-        cost[ns] = (double)((wg * ns + slots - 1) / slots) * (double)per;
+        const int64_t rounds = ns % kXcds == 0 ? (wg * (ns / kXcds) + xslots - 1) / xslots
+                                               : (wg * ns + slots - 1) / slots;
+        cost[ns] = (double)rounds * (double)per;
         best = std::min(best, cost[ns]);
     }
     for (int ns = 1; ns <= maxs; ++ns)
@@ -445,8 +499,10 @@ void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, 
     g.lower = lower ? 1 : 0;
     g.ksplit = (int64_t)align_up((size_t)(((kdim / kI8Block) + nsplit - 1) / nsplit), 1) * kI8Block;
     g.partial = part;
+    g.nsplit = nsplit;
     const int ntiles = lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
-    hipLaunchKernelGGL(k_gemm_i8, dim3(2 * ntiles, nsplit), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_i8<kI8WavesM, 2, 8 / kI8WavesM, 2>), dim3(2 * ntiles * nsplit), dim3(64 * 2 * kI8WavesM),
+                       0, s, g);
 }
 
 // Split count: one round of workgroups (two per CU), each split a multiple
