@@ -190,6 +190,23 @@ int dfjk_build(dfjk_plan *plan, const double *d_C, int32_t nocc, const double *d
                int32_t precision, double *d_J, double *d_K, double *d_E,
                void *d_scratch, size_t scratch_bytes, void *stream);
 
+/* The same build as dfjk_build, for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it takes no scratch argument and allocates nothing.  Its
+ * scratch is a static device array of DFJK_STATIC_SCRATCH_BYTES (64 MiB)
+ * inside the library, one per GPU, held until the process ends; the build
+ * uses the widest aux slab whose scratch fits (single stream), so its J and
+ * K equal dfjk_build's up to the order of the split-K sums.  Arguments,
+ * outputs and errors as for dfjk_build, plus DFJK_E_OOM (nothing enqueued)
+ * when even the narrowest slab needs more than the array holds (molecules
+ * beyond about ten waters of the test basis); use dfjk_build there.  Every
+ * call on a GPU shares that GPU's array, and nothing in it is assumed zero
+ * or kept between calls: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller. */
+#define DFJK_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int dfjk_build_static(dfjk_plan *plan, const double *d_C, int32_t nocc, const double *d_D, int32_t precision,
+                      double *d_J, double *d_K, double *d_E, void *stream);
+
 /* Incremental build for later SCF iterations, after the proposal of single
  * precision in later iterations (paper, "Limitations and Future Development:
  * Mixed Precision").  With D = 2 C C^T and D0 = 2 C0 C0^T,

@@ -41,6 +41,7 @@ SIGNATURES = {
     "dfjk_setup": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
     "dfjk_build_bytes": (c_i32, [c_vp, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "dfjk_build": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "dfjk_build_static": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "dfjk_build_delta_bytes": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "dfjk_build_delta": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "dfjk_build_batch_bytes": (c_i32, [c_i32, ctypes.POINTER(c_vp), P_i32, c_i32, ctypes.POINTER(c_sz)]),

@@ -283,8 +283,9 @@ struct BuildLayout {
 };
 // nsplit: 0 = the autotuned count when there is one, else the built-in
 // choice; -1 = the built-in choice; > 0 = that count (capped by the length)
+// force_slab > 0: that many aux functions per slab (a multiple of kPadAux)
 BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta = false,
-                         int nsplit = 0, bool allow_overlap = true);
+                         int nsplit = 0, bool allow_overlap = true, int64_t force_slab = 0);
 int batch_nsplit(const Plan *const *plans, int n);
 void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const double *const *C, double *const *J,
                         double *const *K, double *const *E, char *const *scratch, hipStream_t s);

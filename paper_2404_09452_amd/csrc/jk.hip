@@ -624,7 +624,7 @@ static int choose_ksplit(int ntiles, int64_t kdim, int num_cus)
 }
 
 BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta, int nsplit,
-                         bool allow_overlap)
+                         bool allow_overlap, int64_t force_slab)
 {
     BuildLayout L{};
     L.nao = p.nao;
@@ -655,6 +655,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
                            (esz + (with_D ? 8 : 0)) *
                            (delta ? 2 : 1) * (may_overlap ? 2 : 1);
     int64_t slab = p.host_B ? p.host_slab
+                 : force_slab > 0 ? force_slab
                  : p.aux_slab > 0 ? (int64_t)align_up((size_t)p.aux_slab, kPadAux)
                                   : (int64_t)(kAutoSlabBytes / per_aux) / kPadAux * kPadAux;
     if (precision == DFJK_MIXED_INT8 && !p.host_B) {   // 128 rows of int8 slices below 4 GiB (32-bit offsets)

@@ -153,6 +153,33 @@ class Plan:
                                   _ptr(K), _ptr(E), _ptr(scr), scr.numel(), _stream_handle(stream)))
         return J, K, E
 
+    def build_static(self, C=None, D=None, precision="fp64", out=None, stream=None):
+        """As build, through dfjk_build_static: the library's static device
+        scratch instead of a workspace, so the call allocates nothing in the
+        library (outputs are allocated here unless `out` is given)."""
+        if (C is None) == (D is None):
+            raise ValueError("give exactly one of C and D")
+        dev = torch.device("cuda")
+        if C is not None:
+            C = torch.as_tensor(C, dtype=torch.float64, device=dev).contiguous()
+            if C.dim() != 2 or C.shape[0] != self.nao:
+                raise ValueError("C must be (nao, nocc)")
+            nocc = C.shape[1]
+        else:
+            D = torch.as_tensor(D, dtype=torch.float64, device=dev).contiguous()
+            if tuple(D.shape) != (self.nao, self.nao):
+                raise ValueError("D must be (nao, nao)")
+            nocc = 0
+        if out is None:
+            J = torch.empty((self.nao, self.nao), dtype=torch.float64, device=dev)
+            K = torch.empty_like(J)
+            E = torch.empty(2, dtype=torch.float64, device=dev)
+        else:
+            J, K, E = out
+        _check(N.lib().dfjk_build_static(self._h, _ptr(C), int(nocc), _ptr(D), PRECISION[precision], _ptr(J),
+                                         _ptr(K), _ptr(E), _stream_handle(stream)))
+        return J, K, E
+
     def build_delta_bytes(self, nocc, precision="fp32"):
         n = ctypes.c_size_t()
         _check(N.lib().dfjk_build_delta_bytes(self._h, int(nocc), PRECISION[precision], ctypes.byref(n)))
