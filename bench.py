@@ -33,6 +33,23 @@ PEAK_F64_TFLOPS = 78.6
 PEAK_F32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_BYTES = 8.0e12
+PEAK_INT8_TOPS = 5000.0          # dense int8 MFMA
+I8_PRODUCTS = 15                 # int8 slice products per FP64-equivalent product (five slices, orders <= 4)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "water32.json")
+
+
+def golden_errors(E, K_last):
+    """Errors of one mode's water32 job against the oracle's stored values
+    (tests/golden/water32.json, written by the CPU oracle alone): |dE_J|,
+    |dE_K| of builds 0 and 9, max |dK| over the stored K rows of build 9."""
+    import numpy as np
+    g = json.load(open(GOLDEN))
+    dEJ = max(abs(E[int(k)][0] - b["E_J"]) for k, b in g["builds"].items())
+    dEK = max(abs(E[int(k)][1] - b["E_K"]) for k, b in g["builds"].items())
+    last = str(len(E) - 1)
+    dK = float(np.abs(K_last[g["rows"]] - np.asarray(g["builds"][last]["K_rows"])).max()) if last in g["builds"] else None
+    return {"max_abs_dE_J_vs_oracle": float(dEJ), "max_abs_dE_K_vs_oracle": float(dEK),
+            "max_abs_dK_rows_vs_oracle": dK, "builds_compared": sorted(int(k) for k in g["builds"])}
 
 
 def committed_traffic():
@@ -373,8 +390,8 @@ def large_bench(nbuild=2):
            "setup_stage_ms": {k: round(v[0], 3) for k, v in st.items() if k.startswith("setup.")},
            "B_resident_GB": round(info["nf"] * info["naux_pad"] * 8 / 1e9, 2)}
     ref = None
-    for prec, peak in (("fp64", PEAK_F64_TFLOPS), ("fp32", PEAK_F32_TFLOPS), ("bf16x3", PEAK_BF16_TFLOPS / 3.0),
-                       ("fp32_incr", PEAK_F32_TFLOPS)):
+    for prec, peak in (("fp64", PEAK_F64_TFLOPS), ("int8", PEAK_INT8_TOPS / I8_PRODUCTS),
+                       ("fp32", PEAK_F32_TFLOPS), ("bf16x3", PEAK_BF16_TFLOPS / 3.0), ("fp32_incr", PEAK_F32_TFLOPS)):
         incr = prec.endswith("_incr")
         Es = []
         torch.cuda.synchronize()
@@ -398,6 +415,8 @@ def large_bench(nbuild=2):
         if not incr:
             r["K_tflops"] = round(k_flops / (kms * 1e-3) / 1e12, 2)
             r["K_frac_of_peak"] = round(k_flops / (kms * 1e-3) / 1e12 / peak, 4)
+            if prec == "int8":
+                r["K_int8_tops"] = round(I8_PRODUCTS * k_flops / (kms * 1e-3) / 1e12, 1)
         if prec == "fp64":
             ref = E
         else:
@@ -411,7 +430,7 @@ def large_bench(nbuild=2):
     plan.offload()
     torch.cuda.empty_cache()
     hb = {"B_host_GB": round(info["nf"] * info["naux_pad"] * 8 / 1e9, 2)}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "int8", "fp32"):
         plan.build(C=Cs[0], precision=prec)
         torch.cuda.synchronize()
         plan.profile_read()
@@ -430,6 +449,21 @@ def large_bench(nbuild=2):
     plan.close()
     torch.cuda.empty_cache()
     return out
+
+
+def _mixed_summary(results):
+    """The fastest mixed mode whose energies stay within 1e-6 Eh of the oracle
+    on the water32 job, against the FP64 build of the same job."""
+    f64 = results["fp64"]
+    ok = {k: v for k, v in results.items() if k != "fp64" and v.get("meets_1e-6_Eh")}
+    if not ok:
+        return {"mode": None}
+    k, v = max(ok.items(), key=lambda kv: kv[1]["builds_per_s"])
+    return {"mode": k, "builds_per_s": round(v["builds_per_s"], 3), "fp64_builds_per_s": round(f64["builds_per_s"], 3),
+            "speedup": round(v["builds_per_s"] / f64["builds_per_s"], 3),
+            "ms_per_build": round(v["ms_per_build_steady"], 3), "fp64_ms_per_build": round(f64["ms_per_build_steady"], 3),
+            "max_abs_dE_J_vs_oracle": v["max_abs_dE_J_vs_oracle"], "max_abs_dE_K_vs_oracle": v["max_abs_dE_K_vs_oracle"],
+            "max_abs_dK_rows_vs_oracle": v["max_abs_dK_rows_vs_oracle"]}
 
 
 def main():
@@ -549,14 +583,15 @@ def main():
             "E_J": E[:, 0].tolist(),
             "E_K": E[:, 1].tolist(),
         }
+        r.update(golden_errors(E, K_last))
         if prec == "fp64":
             ref_E, ref_K = E, K_last
             r["screening"] = {k: info[k] for k in ("sig_shell_pairs", "nshell_pairs", "nf", "triplets_kept")}
         else:
-            r["max_abs_dE_J"] = float(np.abs(E[:, 0] - ref_E[:, 0]).max())
-            r["max_abs_dE_K"] = float(np.abs(E[:, 1] - ref_E[:, 1]).max())
-            r["max_abs_dK"] = float(np.abs(K_last - ref_K).max())
-            r["meets_1e-6_Eh"] = bool(max(r["max_abs_dE_J"], r["max_abs_dE_K"]) <= 1e-6)
+            r["max_abs_dE_J_vs_fp64"] = float(np.abs(E[:, 0] - ref_E[:, 0]).max())
+            r["max_abs_dE_K_vs_fp64"] = float(np.abs(E[:, 1] - ref_E[:, 1]).max())
+            r["max_abs_dK_vs_fp64"] = float(np.abs(K_last - ref_K).max())
+            r["meets_1e-6_Eh"] = bool(max(r["max_abs_dE_J_vs_oracle"], r["max_abs_dE_K_vs_oracle"]) <= 1e-6)
         results[prec] = r
         print("bench: %s %.2f builds/s, %.3f ms/build steady, setup %.1f ms" %
               (prec, r["builds_per_s"], build_ms, setup_ms), file=sys.stderr, flush=True)
@@ -595,12 +630,15 @@ def main():
                   "shell_triplets": scr["triplets_kept"],
                   "note": "FP64 VALU fraction from counters: profiles/water128_int3c_and_k.md"},
     }
-    for prec, peak in (("fp32", PEAK_F32_TFLOPS), ("bf16x3", PEAK_BF16_TFLOPS / 3.0)):
+    for prec, peak in (("int8", PEAK_INT8_TOPS / I8_PRODUCTS), ("fp32", PEAK_F32_TFLOPS),
+                       ("bf16x3", PEAK_BF16_TFLOPS / 3.0)):
         if prec in results:
             n_l = results[prec]["stage_launches"]["build.K"] / (args.steps * NBUILDS)
             ms = results[prec]["stages_ms_per_launch"]["build.K"] * n_l        # per build
             results[prec]["K_tflops"] = round(k_flops / (ms * 1e-3) / 1e12, 2)
             results[prec]["K_frac_of_peak"] = round(k_flops / (ms * 1e-3) / 1e12 / peak, 4)
+            if prec == "int8":
+                results[prec]["K_int8_tops"] = round(I8_PRODUCTS * k_flops / (ms * 1e-3) / 1e12, 1)
 
     direct = None
     if not args.no_direct:
@@ -610,7 +648,8 @@ def main():
     # split-count autotuner on the same molecule (outside the timed steps)
     tplan = Plan.from_molecule(mol, schwarz_thresh=1e-14).screen().setup()
     chosen, cand_ms = tplan.autotune(Cd[0])
-    autotune = {"chosen_nsplit": chosen, "ms_per_build_by_nsplit": {str(k): round(v, 3) for k, v in cand_ms.items()}}
+    autotune = {"chosen_tile": chosen[0], "chosen_nsplit": chosen[1],
+                "ms_per_build_by_tile_and_nsplit": {"%dx%d" % k: round(v, 3) for k, v in cand_ms.items()}}
     tplan.close()
     del bufs, Cd
     torch.cuda.empty_cache()
@@ -653,6 +692,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": {k: v for k, v in results.items() if k != "fp64"},
+        "mixed_vs_fp64": _mixed_summary(results),
         "serving": serving,
         "water128": large,
         "direct_scf": direct,

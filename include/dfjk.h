@@ -99,6 +99,13 @@ typedef struct {
                                     of the density route, the second operand
                                     of dfjk_build_delta) stay within 48 GB.
                                     Negative values are DFJK_INVALID.         */
+    int32_t k_tile;              /* output tile of the FP64 K contraction
+                                    (syrk): 0 = dfjk_autotune's choice for the
+                                    shape, else 64 where 128-wide tiles would
+                                    execute over 14% more products (ragged
+                                    nao), else 128; 64 or 128 = that tile
+                                    for every FP64 syrk of the plan.  Other
+                                    values are DFJK_E_INVALID.                */
 } dfjk_options;
 
 typedef struct dfjk_plan dfjk_plan;
@@ -246,17 +253,20 @@ int dfjk_build_batch(int32_t n, dfjk_plan *const *plans, const double *const *d_
                      int32_t precision, double *const *d_J, double *const *d_K, double *const *d_E,
                      void *d_scratch, size_t scratch_bytes, void *stream);
 
-/* Autotuner for the split count of the K contraction of the closed-shell
- * C-route build (dfjk_build with d_C, this nocc and precision): each
- * candidate (half, one, two and four times the built-in choice, within the
- * contraction length) runs one warm-up and three timed builds with d_C on
- * `stream` (HIP events; synchronises the stream), and the fastest is kept
- * in the plan for later builds of that shape.  A different split count only
- * reorders the FP64 sums of the split-K reduction, which stays fixed and
+/* Autotuner for the K contraction of the closed-shell C-route build
+ * (dfjk_build with d_C, this nocc and precision): its tile shape and split
+ * count.  Candidates are half, one, two and four times the built-in split
+ * count (within the contraction length) of the 128-wide output tiles and,
+ * for FP64, of 64-wide tiles (which leave less of the syrk's work above the
+ * diagonal or past nao).  Each runs one warm-up and three timed builds with
+ * d_C on `stream` (HIP events; synchronises the stream), and the fastest is
+ * kept in the plan for later builds of that shape.  Tile and split count
+ * only reorder the FP64 sums of the split-K reduction, which stays fixed and
  * deterministic for a given choice.  dfjk_build_bytes may grow afterwards.
- * d_scratch must hold dfjk_autotune_bytes.  On return *chosen is the kept
- * count; with ncand != NULL, *ncand (capacity in, count out) candidates and
- * their ms per build are written to cand and ms (host arrays, may be NULL). */
+ * d_scratch must hold dfjk_autotune_bytes.  A candidate is reported as
+ * 1000 * tile + split count: on return *chosen is the kept one; with
+ * ncand != NULL, *ncand (capacity in, count out) candidates and their ms per
+ * build are written to cand and ms (host arrays, may be NULL). */
 int dfjk_autotune_bytes(const dfjk_plan *plan, int32_t nocc, int32_t precision, size_t *bytes);
 int dfjk_autotune(dfjk_plan *plan, const double *d_C, int32_t nocc, int32_t precision, void *d_scratch,
                   size_t scratch_bytes, void *stream, int32_t *chosen, int32_t *ncand, int32_t *cand,

@@ -20,7 +20,7 @@ class Basis(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("schwarz_thresh", c_dbl), ("aux_slab", c_i32)]
+    _fields_ = [("schwarz_thresh", c_dbl), ("aux_slab", c_i32), ("k_tile", c_i32)]
 
 
 class Info(ctypes.Structure):

@@ -28,6 +28,7 @@ constexpr int kPadF = 64;      // function-pair dimension stored as a multiple o
 // contraction index of a slab runs over column passes of the half transform,
 // then aux rows, then the pass's columns (its width rounded up to even, so
 // every pass region is a whole number of blocks; the pad column is zero).
+constexpr int kTileK = 128;     // K output tile of the split-K partials and the reductions
 constexpr int kXcds = 8;        // accelerator complex dies of an MI355X, each with its own L2
 constexpr int kI8Slices = 5;
 constexpr int kI8Block = 256;
@@ -151,6 +152,7 @@ struct Plan {
     int64_t naux = 0, naux_pad = 0;
     double thresh = 1e-14;
     int32_t aux_slab = 0;               // requested K-build aux slab (0 = automatic)
+    int32_t k_tile = 0;                 // requested FP64 K tile (0 = automatic)
     // host-resident B (after dfjk_offload): slab-major pinned copy, the slab
     // width of that layout, and the stream and events of the slab copies
     bool host_B = false;
@@ -164,6 +166,7 @@ struct Plan {
     // split counts chosen by dfjk_autotune for the closed-shell C-route build,
     // keyed by nocc * 4 + precision
     std::map<int64_t, int> tuned_nsplit;
+    std::map<int64_t, int> tuned_ktile;   // the FP64 K GEMM tile kept with that split count
     int device = 0;
     int num_cus = 256;
     int stage = 0;
@@ -272,6 +275,7 @@ struct BuildLayout {
     int nsplit_c;
     int ntile;                          // syrk output tiles per side (128 wide)
     int nsplit_k;                       // k splits per slab
+    int ktile;                          // FP64 K GEMM tile (128, or 64 written into the 128-wide partials)
     int64_t slab, nslab;                // aux functions per slab (multiple of 128), slab count
     int64_t kdim;                       // slab * ncol: contraction length of one slab
     size_t bytes;
@@ -283,9 +287,11 @@ struct BuildLayout {
 };
 // nsplit: 0 = the autotuned count when there is one, else the built-in
 // choice; -1 = the built-in choice; > 0 = that count (capped by the length)
-// force_slab > 0: that many aux functions per slab (a multiple of kPadAux)
+// force_slab > 0: that many aux functions per slab (a multiple of kPadAux);
+// ktile: 0 = the autotuned FP64 K tile when there is one (with nsplit 0),
+// else 128; 64 or 128 = that tile
 BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta = false,
-                         int nsplit = 0, bool allow_overlap = true, int64_t force_slab = 0);
+                         int nsplit = 0, bool allow_overlap = true, int64_t force_slab = 0, int ktile = 0);
 int batch_nsplit(const Plan *const *plans, int n);
 void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const double *const *C, double *const *J,
                         double *const *K, double *const *E, char *const *scratch, hipStream_t s);

@@ -17,7 +17,7 @@
 
 namespace dfjk {
 
-constexpr int kTileK = 128;      // syrk output tile
+
 constexpr int kCSplitRows = 512; // f rows per partial of c
 constexpr double kAutoSlabBytes = 48e9;  // automatic aux slab: slab-sized K buffers up to this
 
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void k_k_reduce_delta(const double *__restrict
 // Split-K reduction of the K tiles: K[m][n] = scale * sum_s partial[s][t][..]
 // in a fixed order, mirrored for off-diagonal tiles, plus per-block partial
 // sums of D[m][n] K[m][n] (weight 2 off the diagonal tiles) for E_K.
-__device__ __forceinline__ void reduce_tile(const double *__restrict__ part, int nsplit, int ntm, int64_t nao,
+__device__ __forceinline__ void reduce_tile(const double *__restrict__ part, int nsplit, int ntm, int T, int64_t nao,
                                             double scale, const double *__restrict__ D, double *__restrict__ K,
                                             double *__restrict__ Epart, const int t, const int chunk)
 {
@@ -503,14 +503,14 @@ __device__ __forceinline__ void reduce_tile(const double *__restrict__ part, int
     while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
     const int tn = t - tm * (tm + 1) / 2;
     double e = 0.0;
-    for (int q = threadIdx.x; q < 16 * kTileK; q += 256) {
-        const int row = chunk * 16 + q / kTileK, col = q % kTileK;
-        const int64_t m = (int64_t)tm * kTileK + row, n = (int64_t)tn * kTileK + col;
+    for (int q = threadIdx.x; q < 16 * T; q += 256) {
+        const int row = chunk * 16 + q / T, col = q % T;
+        const int64_t m = (int64_t)tm * T + row, n = (int64_t)tn * T + col;
         // the upper half of a diagonal tile is mirrored from its lower half
         if (m >= nao || n >= nao || n > m) continue;
-        const int64_t off = (int64_t)t * kTileK * kTileK + row * kTileK + col;
+        const int64_t off = (int64_t)t * T * T + row * T + col;
         double s = 0.0;
-        for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t)sp * ntiles * kTileK * kTileK + off];
+        for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t)sp * ntiles * T * T + off];
         s *= scale;
         K[m * nao + n] = s;
         double w = 1.0;
@@ -526,15 +526,15 @@ __device__ __forceinline__ void reduce_tile(const double *__restrict__ part, int
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) Epart[(int64_t)t * (kTileK / 16) + chunk] = red[0];
+    if (threadIdx.x == 0) Epart[(int64_t)t * (T / 16) + chunk] = red[0];
 }
 
-// block (t, chunk): lower tile t, rows 16 chunk .. 16 chunk + 15
-__global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ part, int nsplit, int ntm,
+// block (t, chunk): lower tile t (T wide), rows 16 chunk .. 16 chunk + 15
+__global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ part, int nsplit, int ntm, int T,
                                                   int64_t nao, double scale, const double *__restrict__ D,
                                                   double *__restrict__ K, double *__restrict__ Epart)
 {
-    reduce_tile(part, nsplit, ntm, nao, scale, D, K, Epart, blockIdx.x, blockIdx.y);
+    reduce_tile(part, nsplit, ntm, T, nao, scale, D, K, Epart, blockIdx.x, blockIdx.y);
 }
 
 // Grouped reduction for a batch: blocks blk_start[p] .. blk_start[p+1]-1 (times
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(256) void k_k_reduce_grouped(ReduceGroup grp, doubl
     const int b = blockIdx.x;
     int p = 0;
     while (p + 1 < grp.n && b >= grp.blk_start[p + 1]) ++p;
-    reduce_tile(grp.part[p], grp.nsplit[p], grp.ntm[p], grp.nao[p], scale, grp.D[p], grp.K[p], grp.Epart[p],
+    reduce_tile(grp.part[p], grp.nsplit[p], grp.ntm[p], kTileK, grp.nao[p], scale, grp.D[p], grp.K[p], grp.Epart[p],
                 b - grp.blk_start[p], blockIdx.y);
 }
 
@@ -613,9 +613,9 @@ int i8_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus);
 void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, const double *sB, int64_t nao,
                     int64_t kdim, int nsplit, double *part, hipStream_t s);
 
-static int choose_ksplit(int ntiles, int64_t kdim, int num_cus)
+static int choose_ksplit(int ntiles, int64_t kdim, int num_cus, int per_cu = 2)
 {
-    const int slots = 2 * (num_cus > 0 ? num_cus : 256);
+    const int slots = per_cu * (num_cus > 0 ? num_cus : 256);
     int ns = ntiles >= slots ? 1 : slots / ntiles;
     const int64_t maxs = kdim / 256;
     if (ns > maxs) ns = (int)(maxs > 0 ? maxs : 1);
@@ -624,7 +624,7 @@ static int choose_ksplit(int ntiles, int64_t kdim, int num_cus)
 }
 
 BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta, int nsplit,
-                         bool allow_overlap, int64_t force_slab)
+                         bool allow_overlap, int64_t force_slab, int ktile)
 {
     BuildLayout L{};
     L.nao = p.nao;
@@ -634,7 +634,27 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.precision = precision;
     L.with_D = with_D;
     L.nsplit_c = (int)((p.nf_pad + kCSplitRows - 1) / kCSplitRows);
-    L.ntile = (int)((p.nao + kTileK - 1) / kTileK);
+    // The FP64 syrk (C and density routes) may run on 64-wide tiles, whose
+    // partials and reduction then use that width: less of its work above the
+    // diagonal or past nao.  The autotuner's choice for the shape, or the
+    // caller's, wins; otherwise 64 when the 128-wide tiles would execute over
+    // 14% more products (the 64-wide kernel sustains about 70% of the FP64
+    // MFMA peak, the 128-wide one 80%).  Mixed precision, the increment and
+    // batches keep 128.
+    L.ktile = kTileK;
+    if (precision == DFJK_FP64 && !delta) {
+        int kt = ktile != 0 ? ktile : p.k_tile;
+        if (kt == 0 && nsplit == 0 && !with_D) {
+            const auto it = p.tuned_ktile.find((int64_t)nocc * 4 + precision);
+            if (it != p.tuned_ktile.end()) kt = it->second;
+        }
+        if (kt == 0) {
+            auto executed = [&](int64_t t) { const int64_t n = (p.nao + t - 1) / t; return n * (n + 1) / 2 * t * t; };
+            if ((double)executed(kTileK) > 1.14 * (double)executed(64)) kt = 64;
+        }
+        if (kt == 64) L.ktile = 64;
+    }
+    L.ntile = (int)((p.nao + L.ktile - 1) / L.ktile);
     L.delta = delta;
     // aux slab of the K build: X = nao x slab x ncol elements per operand
     // bytes of X per element (both BF16 planes; int8 slices plus block scales)
@@ -670,7 +690,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.overlap = may_overlap && L.nslab >= 2;
     L.kdim = x_kdim(precision, slab, L.ncol);
     const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
-    L.nsplit_k = precision == DFJK_FP64 ? choose_ksplit(ntiles, L.kdim, p.num_cus)
+    L.nsplit_k = precision == DFJK_FP64 ? choose_ksplit(ntiles, L.kdim, p.num_cus, L.ktile == 64 ? 4 : 2)
                : precision == DFJK_MIXED_INT8 ? i8_nsplit(p.nao, L.kdim, !delta, p.num_cus)
                                               : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
     if (nsplit == 0 && !with_D && !delta) {   // a split count the autotuner measured for this shape
@@ -707,12 +727,12 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
         L.o_U = take((size_t)p.nao * nocc * 8);
         L.o_W = take((size_t)p.nao * nocc * 8);
     }
-    L.o_Kpart = take((size_t)L.nslab * L.nsplit_k * ntiles * kTileK * kTileK * 8);
+    L.o_Kpart = take((size_t)L.nslab * L.nsplit_k * ntiles * L.ktile * L.ktile * 8);
     if (p.host_B) {   // two staging buffers for slabs of the host-resident B
         L.o_stage[0] = take((size_t)p.nf_pad * L.slab * 8);
         L.o_stage[1] = take((size_t)p.nf_pad * L.slab * 8);
     }
-    L.o_Epart = take((size_t)L.ntile * (L.ntile + 1) / 2 * (kTileK / 16) * 8);
+    L.o_Epart = take((size_t)L.ntile * (L.ntile + 1) / 2 * (L.ktile / 16) * 8);
     L.bytes = align_up(off, 256);
     return L;
 }
@@ -762,7 +782,8 @@ static void slab_gemm(const BuildLayout &L, bool lower, const void *X, const voi
         g.k_begin = 0; g.k_end = kdim;
         g.ksplit = align_up((size_t)((kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
         g.alpha = 1.0; g.lower = lower ? 1 : 0; g.partial = part;
-        gemm_f64<kTileK, false>(g, L.nsplit_k, s);
+        if (L.ktile == 64) gemm_f64<64, false>(g, L.nsplit_k, s);
+        else gemm_f64<kTileK, false>(g, L.nsplit_k, s);
     } else if (L.precision == DFJK_MIXED_INT8) {
         launch_gemm_i8(lower, X, static_cast<const double *>(Xlo), Bop, static_cast<const double *>(Bop_lo), nao,
                        kdim, L.nsplit_k, part, s);
@@ -803,7 +824,7 @@ static void contract_slabs_overlapped(Plan &p, const BuildLayout &L, const doubl
     void *Xlo[2] = {L.o_Xlo ? scratch + L.o_Xlo : nullptr, L.o_Xblo ? scratch + L.o_Xblo : nullptr};
     double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
     const int ntiles = L.ntile * (L.ntile + 1) / 2;
-    const size_t slab_part = (size_t)L.nsplit_k * ntiles * kTileK * kTileK;
+    const size_t slab_part = (size_t)L.nsplit_k * ntiles * L.ktile * L.ktile;
     hipStream_t hs = p.ht_stream;
     (void)hipEventRecord(p.ev_fork, s);
     (void)hipStreamWaitEvent(hs, p.ev_fork, 0);
@@ -847,7 +868,7 @@ static void contract_slabs(Plan &p, const BuildLayout &L, const double *C1, cons
     double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
     const bool lower = !L.delta;
     const int ntiles = lower ? L.ntile * (L.ntile + 1) / 2 : L.ntile * L.ntile;
-    const size_t slab_part = (size_t)L.nsplit_k * ntiles * kTileK * kTileK;
+    const size_t slab_part = (size_t)L.nsplit_k * ntiles * L.ktile * L.ktile;
     void *X2 = L.delta ? scratch + L.o_X2 : nullptr;
     void *X2lo = L.o_X2lo ? scratch + L.o_X2lo : nullptr;
     for (int64_t sl = 0; sl < L.nslab; ++sl) {
@@ -911,10 +932,9 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
                            (int)(L.nslab * L.nsplit_k),
                            L.ntile, nao, L.K0, D, K, Epart);
     else
-        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
-                           L.ntile, nao,
-                           L.with_D ? 1.0 : 2.0, D, K, Epart);
-    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (kTileK / 16), -0.25,
+        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, L.ktile / 16), dim3(256), 0, s, Kpart,
+                           (int)(L.nslab * L.nsplit_k), L.ntile, L.ktile, nao, L.with_D ? 1.0 : 2.0, D, K, Epart);
+    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (L.ktile / 16), -0.25,
                        E);
     pr.mark(ST_KREDUCE, false);
 }
@@ -934,7 +954,7 @@ BuildLayout build_layout_uks(const Plan &p, int32_t nocc_a, int32_t nocc_b, int3
     };
     L.o_Da = take((size_t)p.nao * p.nao * 8);
     L.o_Db = take((size_t)p.nao * p.nao * 8);
-    L.o_Epart = take((size_t)2 * L.ntile * (L.ntile + 1) / 2 * (kTileK / 16) * 8);   // one block per spin
+    L.o_Epart = take((size_t)2 * L.ntile * (L.ntile + 1) / 2 * (L.ktile / 16) * 8);   // one block per spin
     L.bytes = align_up(off, 256);
     return L;
 }
@@ -955,7 +975,7 @@ void launch_build_uks(Plan &p, const BuildLayout &L, const double *Ca, const dou
     double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
     double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
     const int nlower = L.ntile * (L.ntile + 1) / 2;
-    const int64_t nep = (int64_t)nlower * (kTileK / 16);
+    const int64_t nep = (int64_t)nlower * (L.ktile / 16);
     Profiler &pr = p.prof;
     pr.stream = s;
 
@@ -978,8 +998,8 @@ void launch_build_uks(Plan &p, const BuildLayout &L, const double *Ca, const dou
         }
         contract_slabs(p, L, Cs[sp], nullptr, nocc[sp], scratch, s);
         pr.mark(ST_KREDUCE, true);
-        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
-                           L.ntile, nao, 1.0, Ds[sp], Ks[sp], Epart + sp * nep);
+        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, L.ktile / 16), dim3(256), 0, s, Kpart,
+                           (int)(L.nslab * L.nsplit_k), L.ntile, L.ktile, nao, 1.0, Ds[sp], Ks[sp], Epart + sp * nep);
         pr.mark(ST_KREDUCE, false);
     }
     pr.mark(ST_KREDUCE, true);
@@ -1099,7 +1119,7 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
     void *X = scratch + L.o_X;
     void *Xlo = L.o_Xlo ? scratch + L.o_Xlo : nullptr;
     const int ntiles = L.ntile * (L.ntile + 1) / 2;
-    const size_t slab_part = (size_t)L.nsplit_k * ntiles * kTileK * kTileK;
+    const size_t slab_part = (size_t)L.nsplit_k * ntiles * L.ktile * L.ktile;
     Profiler &pr = p.prof;
     pr.stream = s;
     hipStream_t cs = p.copy_stream;
@@ -1152,9 +1172,9 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
     }
     pr.mark(ST_KREDUCE, true);
     const int nlower = L.ntile * (L.ntile + 1) / 2;
-    hipLaunchKernelGGL(k_k_reduce, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
-                       L.ntile, nao, 2.0, D, K, Epart);
-    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (kTileK / 16), -0.25,
+    hipLaunchKernelGGL(k_k_reduce, dim3(nlower, L.ktile / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
+                       L.ntile, L.ktile, nao, 2.0, D, K, Epart);
+    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (L.ktile / 16), -0.25,
                        E);
     pr.mark(ST_KREDUCE, false);
 }

@@ -52,7 +52,7 @@ class Plan:
     coords: (natm, 3) Bohr; ao and aux: (atom, l, exponent) arrays."""
 
     def __init__(self, coords, ao_atom, ao_l, ao_exp, aux_atom, aux_l, aux_exp, schwarz_thresh=1e-14,
-                 aux_slab=0):
+                 aux_slab=0, k_tile=0):
         L = N.lib()
         self._keep = []
         coords = np.ascontiguousarray(coords, dtype=np.float64)
@@ -67,7 +67,7 @@ class Plan:
 
         ao = basis(ao_atom, ao_l, ao_exp)
         aux = basis(aux_atom, aux_l, aux_exp)
-        opt = N.Options(float(schwarz_thresh), int(aux_slab))
+        opt = N.Options(float(schwarz_thresh), int(aux_slab), int(k_tile))
         h = ctypes.c_void_p()
         _check(L.dfjk_plan_create(len(coords), coords.ctypes.data_as(N.P_dbl), ctypes.byref(ao),
                                   ctypes.byref(aux), ctypes.byref(opt), ctypes.byref(h)))
@@ -79,9 +79,9 @@ class Plan:
         self.nao, self.naux = inf["nao"], inf["naux"]
 
     @classmethod
-    def from_molecule(cls, mol, schwarz_thresh=1e-14, aux_slab=0):
+    def from_molecule(cls, mol, schwarz_thresh=1e-14, aux_slab=0, k_tile=0):
         return cls(mol.coords, mol.ao_atom, mol.ao_l, mol.ao_exp, mol.aux_atom, mol.aux_l, mol.aux_exp,
-                   schwarz_thresh=schwarz_thresh, aux_slab=aux_slab)
+                   schwarz_thresh=schwarz_thresh, aux_slab=aux_slab, k_tile=k_tile)
 
     # -- facts -------------------------------------------------------------
     def info(self):
@@ -242,20 +242,22 @@ class Plan:
         return J, Ka, Kb, E
 
     def autotune(self, C, precision="fp64", stream=None):
-        """Time the candidate split counts of the K contraction for this C shape
-        (dfjk_autotune) and keep the fastest; returns (chosen, {split: ms})."""
+        """Time the candidate tile shapes and split counts of the K contraction
+        for this C shape (dfjk_autotune) and keep the fastest; returns
+        ((tile, split), {(tile, split): ms})."""
         C = torch.as_tensor(C, dtype=torch.float64, device="cuda").contiguous()
         nocc = C.shape[1]
         nb = ctypes.c_size_t()
         _check(N.lib().dfjk_autotune_bytes(self._h, int(nocc), PRECISION[precision], ctypes.byref(nb)))
         scr = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
-        chosen, ncand = ctypes.c_int32(), ctypes.c_int32(8)
-        cand = (ctypes.c_int32 * 8)()
-        ms = (ctypes.c_double * 8)()
+        chosen, ncand = ctypes.c_int32(), ctypes.c_int32(16)
+        cand = (ctypes.c_int32 * 16)()
+        ms = (ctypes.c_double * 16)()
         _check(N.lib().dfjk_autotune(self._h, _ptr(C), int(nocc), PRECISION[precision], _ptr(scr), scr.numel(),
                                      _stream_handle(stream), ctypes.byref(chosen), ctypes.byref(ncand), cand, ms))
         self._scratch = {}          # build sizes may have changed
-        return chosen.value, {int(cand[i]): float(ms[i]) for i in range(ncand.value)}
+        dec = lambda c: (int(c) // 1000, int(c) % 1000)   # noqa: E731  (1000 * tile + split)
+        return dec(chosen.value), {dec(cand[i]): float(ms[i]) for i in range(ncand.value)}
 
     def offload(self, stream=None):
         """Move B to page-locked host memory (dfjk_offload); later builds stream
@@ -462,7 +464,7 @@ def build_host(coords, ao_atom, ao_l, ao_exp, aux_atom, aux_l, aux_exp, C=None, 
     xyz = arr(coords, np.float64)
     ao, aux = basis(ao_atom, ao_l, ao_exp), basis(aux_atom, aux_l, aux_exp)
     nao = int(np.sum(2 * np.asarray(ao_l) + 1))
-    opt = N.Options(float(schwarz_thresh), 0)
+    opt = N.Options(float(schwarz_thresh), 0, 0)
     Cin = arr(C, np.float64) if C is not None else None
     Din = arr(D, np.float64) if D is not None else None
     nocc = Cin.shape[1] if Cin is not None else 0

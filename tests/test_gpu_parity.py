@@ -403,6 +403,22 @@ def test_host_resident_B_matches_device_B(cluster5, slab):
     dev.close()
 
 
+@pytest.mark.parametrize("n,tile", [(3, 64), (5, 64), (3, 128), (5, 128)])
+def test_k_tile_choices(n, tile):
+    """The FP64 syrk, its partials and reduction on 64- and 128-wide tiles
+    (ragged last tile row: nao 90 and 150), C and density routes, against
+    the oracle."""
+    mol, S, C = case(n)
+    plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU, k_tile=tile).screen().setup()
+    J, K, E = (t.cpu().numpy() for t in plan.build(C=C))
+    ref = oracle.dfjk(mol, C=C)
+    assert rel(K, ref["K"]) <= 1e-10 and rel(J, ref["J"]) <= 1e-10
+    assert abs(E[1] - ref["EK"]) <= 1e-10 * abs(ref["EK"])
+    J2, K2, E2 = (t.cpu().numpy() for t in plan.build(D=oracle.density(C)))
+    assert rel(K2, ref["K"]) <= 1e-10
+    plan.close()
+
+
 def test_autotuned_split_count(cluster5):
     """The autotuner keeps one of its candidates; builds then use it and still
     agree with the oracle."""
