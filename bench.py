@@ -281,7 +281,8 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
     import torch
 
     import workload as W
-    from paper_2404_09452_amd.serve import BatchedGpuExecutor, GpuExecutor, Request, Server, summarize
+    from paper_2404_09452_amd.serve import (RUNTIME_RESERVE_BYTES, BatchedGpuExecutor, GpuExecutor, Request,
+                                            Server, default_budget, summarize)
     _, sizes = W.poisson_stream(nreq, 1.0, seed, 1, nmax)
     pool = {}
     for n in sorted(set(int(s) for s in sizes)):
@@ -290,14 +291,13 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
         S = W.overlap_by_quadrature(mol)
         C0 = W.occupied_orbitals(S, mol.nelec // 2, n)
         pool[n] = (mol, [W.perturbed_orbitals(C0, S, k, eps=1e-2, seed=1000) for k in range(NBUILDS)])
-    # Cap torch's caching allocator below the device size: cached blocks of
-    # finished molecules of other sizes would otherwise fill HBM and leave the
-    # runtime no room for its own allocations (spill scratch per queue).
-    torch.cuda.set_per_process_memory_fraction(0.85)
-    free, _ = torch.cuda.mem_get_info()
-    budget = int(budget_frac * free)
+    # the executors cap torch's allocator (serve.ALLOCATOR_FRACTION) and the
+    # server keeps serve.RUNTIME_RESERVE_BYTES of the budget for the runtime
+    GpuExecutor(keep_results=False)
+    budget = default_budget(budget_frac)
     out = {"requests": nreq, "sizes": "uniform 1..%d waters" % nmax, "builds_per_request": NBUILDS,
-           "max_active": max_active, "hbm_budget_GB": round(budget / 1e9, 1)}
+           "max_active": max_active, "hbm_budget_GB": round(budget / 1e9, 1),
+           "runtime_reserve_GB": round(RUNTIME_RESERVE_BYTES / 1e9, 1), "loads_x_saturation": list(loads)}
     for mode in modes:
         prec, batched = mode.split("+")[0], mode.endswith("+batched")
         torch.cuda.synchronize()
@@ -320,9 +320,10 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
                           file=sys.stderr, flush=True)
             return done
         # an untimed pass first, so that the timed runs meet a warm allocator
-        Server(executor(), max_active=max_active, hbm_budget_bytes=budget,
+        Server(executor(), max_active=max_active, hbm_budget_bytes=budget, runtime_reserve_bytes=RUNTIME_RESERVE_BYTES,
                on_done=progress("warm-up")).serve(reqs(np.zeros(nreq)))
-        srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget, on_done=progress("closed loop"))
+        srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget,
+                     runtime_reserve_bytes=RUNTIME_RESERVE_BYTES, on_done=progress("closed loop"))
         t0 = time.perf_counter()
         closed = srv.serve(reqs(np.zeros(nreq)))
         wall = time.perf_counter() - t0
@@ -337,7 +338,7 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
         for load in loads:
             arr, _ = W.poisson_stream(nreq, load * mu, seed, 1, nmax)
             srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget,
-                         on_done=progress("load %.2f" % load))
+                         runtime_reserve_bytes=RUNTIME_RESERVE_BYTES, on_done=progress("load %.2f" % load))
             t0 = time.perf_counter()
             done = srv.serve(reqs(arr))
             wall = time.perf_counter() - t0
@@ -476,10 +477,11 @@ def main():
                     help="comma-separated water32 modes after fp64 (default: every mixed mode)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=96)
-    ap.add_argument("--serve-max-waters", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests per serving run (each load point and the closed loop)")
+    ap.add_argument("--serve-max-waters", type=int, default=64)
     ap.add_argument("--no-large", action="store_true", help="skip the 128-water leg")
-    ap.add_argument("--serve-modes", default="fp64,fp64+batched,bf16x3_incr")
+    ap.add_argument("--serve-modes", default="fp64,int8+batched")
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only run the serving stream: --serve-requests requests of 1..64 waters, Poisson "
                          "loads 0.5..1.1 x saturation, for each of --serve-modes; print its JSON")
@@ -495,6 +497,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (scales HBM byte counters)")
     args = ap.parse_args()
+    # serving molecules of 1..64 waters needs unsplit large blocks (set before
+    # torch touches the GPU; see serve.configure_allocator)
+    if not args.no_serve or args.serve_sweep:
+        from paper_2404_09452_amd.serve import configure_allocator
+        configure_allocator()
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
@@ -509,12 +516,6 @@ def main():
               "(the build would shard over aux slabs with one all-reduce of J and K).", file=sys.stderr)
         sys.exit(2)
     if args.serve_sweep:
-        # Molecules of 1..64 waters: blocks above 512 MB are never split, so a
-        # finished molecule's workspace goes back as whole segments that torch
-        # can release when a larger one needs the room (set before torch
-        # touches the GPU).  The default run's 1..32 stream does better
-        # without it (fewer device allocations).
-        os.environ.setdefault("PYTORCH_ALLOC_CONF", "max_split_size_mb:512")
         print(json.dumps({"serving_sweep": serving_bench(args.serve_modes.split(","), args.serve_requests, 64,
                                                          loads=(0.5, 0.75, 0.9, 1.1))}))
         return
@@ -661,8 +662,8 @@ def main():
     serving = None
     if not args.no_serve:
         print("bench: serving stream", file=sys.stderr, flush=True)
-        serving = serving_bench(["fp64", "fp64+batched", "bf16x3_incr"], args.serve_requests,
-                                args.serve_max_waters)
+        serving = serving_bench(args.serve_modes.split(","), args.serve_requests, args.serve_max_waters,
+                                loads=(0.5, 0.9, 1.1))
 
     cpu = None
     if not args.no_cpu:

@@ -25,9 +25,11 @@ constexpr int kPadF = 64;      // function-pair dimension stored as a multiple o
 // x ~ 2^e sum_{s<kI8Slices} a_s 2^{-7(s+1)}, a_0 in [-127, 127], a_s in
 // [-64, 64].  Storage per row: chunks of kI8Chunk elements, each chunk the
 // kI8Slices slices one after another ([chunk][slice][64] bytes).  The
-// contraction index of a slab runs over column passes of the half transform,
-// then aux rows, then the pass's columns (its width rounded up to even, so
-// every pass region is a whole number of blocks; the pad column is zero).
+// contraction index of a slab runs over column passes of the half transform
+// (ceil(ncol/16) fragments of 16 columns spread evenly over
+// ceil(fragments/12) passes, all full but the last), then aux rows, then the
+// pass's columns (its width rounded up to even, so every pass region is a
+// whole number of blocks; the pad column is zero).
 constexpr int kTileK = 128;     // K output tile of the split-K partials and the reductions
 constexpr int kXcds = 8;        // accelerator complex dies of an MI355X, each with its own L2
 constexpr int kI8Slices = 5;

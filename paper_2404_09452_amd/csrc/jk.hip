@@ -392,9 +392,13 @@ void k_halftrans(HTArgs g)
 template <int OUT>
 static void launch_halftrans(const HTArgs &h, int64_t nao, hipStream_t s)
 {
+    // column passes of at most 16 fragments (12 for the int8 output, whose
+    // slicing epilogue needs the registers: wider passes spill), the
+    // fragments spread evenly over the passes for the int8 output
     const int nib_needed = (h.ncol + 15) / 16;
-    const int nib = nib_needed < 16 ? nib_needed : 16;
-    const int passes = (nib_needed + nib - 1) / nib;
+    const int cap = OUT == OUT_I8 ? 12 : 16;
+    const int passes = (nib_needed + cap - 1) / cap;
+    const int nib = OUT == OUT_I8 ? (nib_needed + passes - 1) / passes : (nib_needed < cap ? nib_needed : cap);
     dim3 grid((unsigned)(h.plen / 128), (unsigned)nao, (unsigned)passes);
 #define HT_CASE(N) \
     case N: hipLaunchKernelGGL((k_halftrans<OUT, N>), grid, dim3(512), 0, s, h); break;

@@ -17,12 +17,44 @@ batched calls (grouped launches across molecules).
 from __future__ import annotations
 
 import dataclasses
+import os
 import queue
 import threading
 import time
 from typing import Callable, List, Optional
 
 import numpy as np
+
+# Device memory the HIP runtime needs besides the caching allocator's blocks:
+# the private (spill) segments of the integral kernels are allocated by the
+# runtime per queue when a kernel is dispatched, and a dispatch that finds no
+# room aborts the process.  The server keeps this much out of its budget and
+# caps torch's allocator below the device size.
+RUNTIME_RESERVE_BYTES = 4 << 30
+ALLOCATOR_FRACTION = 0.85
+
+
+def configure_allocator():
+    """Allocator settings for serving molecules of very different sizes; call
+    before torch first touches the GPU.  Blocks above 512 MB are never split,
+    so a finished molecule's workspace returns as whole segments that can be
+    released when a larger molecule needs the room (without it, fragmentation
+    left cached blocks unusable and large requests failed inside their
+    admitted budget).  Returns False (and changes nothing) when the process
+    has already initialised the GPU."""
+    import torch
+    if torch.cuda.is_initialized():
+        return False
+    os.environ.setdefault("PYTORCH_ALLOC_CONF", "max_split_size_mb:512")
+    return True
+
+
+def default_budget(frac=0.6):
+    """An HBM budget: `frac` of the device memory torch may use after the
+    allocator cap (pass it to Server with runtime_reserve_bytes)."""
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    return int(frac * min(free, int(ALLOCATOR_FRACTION * total)))
 
 
 @dataclasses.dataclass
@@ -64,7 +96,7 @@ class Executor:
 class GpuExecutor(Executor):
     """Runs requests through the DF-J/K library, one HIP stream per request."""
 
-    def __init__(self, keep_results=True, schwarz_thresh=1e-14):
+    def __init__(self, keep_results=True, schwarz_thresh=1e-14, allocator_fraction=ALLOCATOR_FRACTION):
         import torch
 
         from .dfjk import Plan
@@ -73,6 +105,10 @@ class GpuExecutor(Executor):
         self.keep = keep_results
         self.thresh = schwarz_thresh
         self._plans = {}
+        # cached blocks of finished molecules must not take the memory the
+        # runtime needs for its own allocations (see RUNTIME_RESERVE_BYTES)
+        if allocator_fraction is not None:
+            torch.cuda.set_per_process_memory_fraction(allocator_fraction)
 
     def prepare(self, req):
         torch = self.torch
@@ -124,16 +160,22 @@ class GpuExecutor(Executor):
 
 
 class BatchedGpuExecutor(GpuExecutor):
-    """Step-level batching of the builds.  Each admitted request sets up on its
-    own stream as before; once set up it joins a build loop that, at every
-    step, issues the next build of every joined request as one batched call
-    (grouped K, reduction and energy launches across the molecules).
-    Requests join and leave between steps, so a molecule that arrives while
-    others are mid-run rides along from its first build.  Direct precisions
-    only (fp64, fp32, bf16x3)."""
+    """Step-level batching of the builds of small molecules.  Each admitted
+    request sets up on its own stream as before.  A molecule with fewer than
+    `batch_below_nao` AO functions then joins a build loop that, at every
+    step, issues the next build of every joined molecule as one batched call
+    (grouped K, reduction and energy launches across the molecules, where the
+    launch overhead of separate builds would dominate); requests join and
+    leave between steps, so one that arrives while others are mid-run rides
+    along from its first build.  Larger molecules, whose kernels fill the
+    device by themselves, keep building on their own streams, free of the
+    steps, overlapping with the batches.  Direct precisions only (fp64, int8,
+    fp32, bf16x3)."""
 
-    def __init__(self, keep_results=True, schwarz_thresh=1e-14):
-        super().__init__(keep_results, schwarz_thresh)
+    def __init__(self, keep_results=True, schwarz_thresh=1e-14, allocator_fraction=ALLOCATOR_FRACTION,
+                 batch_below_nao=300):
+        super().__init__(keep_results, schwarz_thresh, allocator_fraction)
+        self.batch_below_nao = batch_below_nao
         from .dfjk import Batch
         self.Batch = Batch
         self._cv = threading.Condition()
@@ -146,9 +188,12 @@ class BatchedGpuExecutor(GpuExecutor):
 
     def run(self, req):
         torch = self.torch
-        if req.precision not in ("fp64", "fp32", "bf16x3"):
+        if req.precision not in ("fp64", "int8", "fp32", "bf16x3"):
             raise ValueError("the batched executor runs direct builds only")
         plan, stream = self._plans[req.rid]
+        if plan.nao >= self.batch_below_nao:
+            super().run(req)
+            return
         with torch.cuda.stream(stream):
             plan.setup(stream=stream)
             nao = plan.nao
@@ -219,16 +264,24 @@ class BatchedGpuExecutor(GpuExecutor):
 
 
 class Server:
-    """Admission by slots and an HBM byte budget; FIFO order."""
+    """Admission by slots and an HBM byte budget; FIFO order.  The budget
+    counts every byte the library and the request's buffers take
+    (Executor.prepare); `runtime_reserve_bytes` of it are kept back for the
+    HIP runtime's own allocations (kernel spill segments), so requests are
+    admitted against hbm_budget_bytes - runtime_reserve_bytes."""
 
     def __init__(self, executor: Executor, max_active=4, hbm_budget_bytes=64 << 30,
                  clock: Callable[[], float] = time.perf_counter,
-                 on_done: Optional[Callable[[Request], None]] = None):
+                 on_done: Optional[Callable[[Request], None]] = None,
+                 runtime_reserve_bytes: int = 0):
         if max_active < 1:
             raise ValueError("max_active must be >= 1")
         self.ex = executor
         self.max_active = max_active
-        self.budget = int(hbm_budget_bytes)
+        self.reserve = int(runtime_reserve_bytes)
+        self.budget = int(hbm_budget_bytes) - self.reserve
+        if self.budget <= 0:
+            raise ValueError("the runtime reserve leaves no budget")
         self.clock = clock
         self.in_use = 0
         self.peak_in_use = 0

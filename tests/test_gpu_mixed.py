@@ -38,7 +38,14 @@ if not torch.cuda.is_available():
 from paper_2404_09452_amd import dfjk as G  # noqa: E402
 
 TAU = 1e-14
-HT_COLS = 256          # columns per pass of the half transform (16 fragments of 16)
+
+
+def int8_pass_width(ncol):
+    """Columns per pass of the int8 half transform: at most 12 fragments of
+    16 columns per pass, the fragments spread evenly over the passes."""
+    need = (ncol + 15) // 16
+    passes = (need + 11) // 12
+    return 16 * ((need + passes - 1) // passes)
 
 
 def case(n, nocc=None, cseed=None):
@@ -69,15 +76,16 @@ def internal_x(mol, plan, C, U=None, V=None):
 
 def int8_rows(Xp, slab):
     """Per aux slab, the rows mu of X in the int8 layout's contraction order:
-    column passes of 256, then aux rows, then the pass's columns (width
+    column passes (int8_pass_width), then aux rows, then the pass's columns (width
     rounded up to even, the pad column zero)."""
     npad, nao, ncol = Xp.shape
+    pw = int8_pass_width(ncol)
     out = []
     for pb in range(0, npad, slab):
         Xs = Xp[pb:pb + slab]
         parts = []
-        for c0 in range(0, ncol, HT_COLS):
-            w = min(HT_COLS, ncol - c0)
+        for c0 in range(0, ncol, pw):
+            w = min(pw, ncol - c0)
             blk = np.zeros((Xs.shape[0], nao, w + (w & 1)))
             blk[:, :, :w] = Xs[:, :, c0:c0 + w]
             parts.append(blk.transpose(1, 0, 2).reshape(nao, -1))
@@ -161,7 +169,7 @@ def test_int8_several_slabs_and_a_ragged_last_slab():
 @pytest.mark.parametrize("n,nocc", [(9, 160), (11, 291)])
 def test_int8_column_passes(n, nocc):
     """160 orbitals (one pass of 160 columns, the 32-water shape) and 291
-    (two passes of 256 and 35 + 1 pad columns) against the oracle; FP64 of
+    (two passes of 160 and 131 + 1 pad columns) against the oracle; FP64 of
     the same case at 1e-10."""
     mol, S, C = case(n, nocc=nocc)
     plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU).screen().setup()
