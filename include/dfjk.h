@@ -220,7 +220,12 @@ int dfjk_build_static(dfjk_plan *plan, const double *d_C, int32_t nocc, const do
  *   D - D0 = U W^T + W U^T,  U = C + C0,  W = C - C0,
  *   K(D) = K0 + G + G^T,     G = X_U X_W^T,
  * where K0 = K(D0) comes from an earlier FP64 dfjk_build with C0 on this plan
- * and X_U, X_W are the half-transforms of U and W.  G is formed in
+ * and X_U, X_W are the half-transforms of U and W.  C is first rotated onto
+ * C0 (C -> C Q, Q the orthogonal polar factor of C^T C0, the orthogonal
+ * Procrustes solution; D is unchanged) so that a sign flip or a rotation of
+ * the occupied orbitals among themselves does not inflate W; if the rotation
+ * cannot be formed to 1e-13 (C and C0 spanning different spaces), C is used
+ * as given.  G is formed in
  * `precision` (its error scales with |C - C0|); J and both energies are FP64.
  * d_C, d_C0: nao x nocc; d_K0: nao x nao (read only, must not alias d_K).
  * d_scratch must hold dfjk_build_delta_bytes(plan, nocc, precision). */

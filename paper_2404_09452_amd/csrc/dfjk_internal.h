@@ -283,6 +283,7 @@ struct BuildLayout {
     size_t bytes;
     // offsets into the scratch
     size_t o_D, o_d, o_cpart, o_c, o_X, o_Xlo, o_Bfull, o_X2, o_X2lo, o_U, o_W, o_Kpart, o_Epart, o_Da, o_Db;
+    size_t o_Cr, o_align;               // increment: C rotated onto C0, and the alignment's work
     size_t o_stage[2];                  // staging of host-resident B slabs
     bool overlap;                       // half transform of the next slab beside the K GEMM
     size_t o_Xb, o_Xblo;                // the second X buffer of the overlapped schedule
@@ -318,6 +319,11 @@ void launch_direct_build(const Plan &p, const DirectLayout &L, const double *C, 
                          const double *D0, const double *J0, const double *K0, double *J, double *K, double *E,
                          char *scratch, hipStream_t s);
 void launch_density(const double *C, int64_t nao, int32_t nocc, double scale, double *D, hipStream_t s);
+
+// align.hip: Cr = C Q, Q the orthogonal polar factor of C^T C0 (Procrustes)
+size_t align_work_doubles(int32_t nocc);
+void launch_align(const double *C, const double *C0, int64_t nao, int32_t nocc, double *work, double *Cr,
+                  hipStream_t s);
 
 // export.hip
 void launch_zero(double *p, int64_t n, hipStream_t s);

@@ -730,6 +730,8 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
         L.o_X2lo = xlo ? take(xlo) : 0;
         L.o_U = take((size_t)p.nao * nocc * 8);
         L.o_W = take((size_t)p.nao * nocc * 8);
+        L.o_Cr = take((size_t)p.nao * nocc * 8);
+        L.o_align = take(align_work_doubles(nocc) * 8);
     }
     L.o_Kpart = take((size_t)L.nslab * L.nsplit_k * ntiles * L.ktile * L.ktile * 8);
     if (p.host_B) {   // two staging buffers for slabs of the host-resident B
@@ -913,10 +915,13 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
     } else {
         (void)hipMemcpyAsync(D, Din, (size_t)nao * nao * 8, hipMemcpyDeviceToDevice, s);
     }
-    if (L.delta)
-        hipLaunchKernelGGL(k_uw, dim3((unsigned)((nao * L.ncol + 255) / 256)), dim3(256), 0, s, C, L.C0, nao,
+    if (L.delta) {   // U, W from C rotated onto C0 (D is unchanged by the rotation)
+        double *Cr = reinterpret_cast<double *>(scratch + L.o_Cr);
+        launch_align(C, L.C0, nao, (int32_t)L.ncol, reinterpret_cast<double *>(scratch + L.o_align), Cr, s);
+        hipLaunchKernelGGL(k_uw, dim3((unsigned)((nao * L.ncol + 255) / 256)), dim3(256), 0, s, Cr, L.C0, nao,
                            (int32_t)L.ncol, reinterpret_cast<double *>(scratch + L.o_U),
                            reinterpret_cast<double *>(scratch + L.o_W));
+    }
     pr.mark(ST_DENSITY, false);
     // 2-4. J (always FP64)
     pr.mark(ST_J, true);

@@ -7,6 +7,7 @@ with torch and passes torch's current HIP stream.
 from __future__ import annotations
 
 import ctypes
+import functools
 
 import numpy as np
 import torch
@@ -33,6 +34,20 @@ def _check(rc):
     if rc != 0:
         msg = N.lib().dfjk_last_error()
         raise DFJKError(rc, msg.decode() if msg else "")
+
+
+def _on_stream(fn):
+    """Run a call's own device work (input copies, output and scratch
+    allocations) on the stream the library is given, so that the library
+    never reads an input before its copy, nor memory that the caching
+    allocator has already handed to work on another stream."""
+    @functools.wraps(fn)
+    def wrapper(*args, stream=None, **kw):
+        if stream is None:
+            return fn(*args, stream=None, **kw)
+        with torch.cuda.stream(stream):
+            return fn(*args, stream=stream, **kw)
+    return wrapper
 
 
 def _stream_handle(stream):
@@ -95,6 +110,7 @@ class Plan:
         return out
 
     # -- phases ------------------------------------------------------------
+    @_on_stream
     def screen(self, stream=None):
         n = ctypes.c_size_t()
         _check(N.lib().dfjk_screen_bytes(self._h, ctypes.byref(n)))
@@ -107,6 +123,7 @@ class Plan:
         _check(N.lib().dfjk_setup_bytes(self._h, ctypes.byref(n)))
         return n.value
 
+    @_on_stream
     def setup(self, stream=None):
         nbytes = self.setup_bytes()
         if self._ws is None or self._ws.numel() < nbytes:
@@ -127,6 +144,7 @@ class Plan:
                                              dtype=torch.uint8, device="cuda")
         return self._scratch[key]
 
+    @_on_stream
     def build(self, C=None, D=None, precision="fp64", out=None, stream=None):
         """J, K (nao x nao) and E = [E_J, E_K] as float64 CUDA tensors."""
         if (C is None) == (D is None):
@@ -153,6 +171,7 @@ class Plan:
                                   _ptr(K), _ptr(E), _ptr(scr), scr.numel(), _stream_handle(stream)))
         return J, K, E
 
+    @_on_stream
     def build_static(self, C=None, D=None, precision="fp64", out=None, stream=None):
         """As build, through dfjk_build_static: the library's static device
         scratch instead of a workspace, so the call allocates nothing in the
@@ -185,6 +204,7 @@ class Plan:
         _check(N.lib().dfjk_build_delta_bytes(self._h, int(nocc), PRECISION[precision], ctypes.byref(n)))
         return n.value
 
+    @_on_stream
     def build_delta(self, C, C0, K0, precision="fp32", out=None, stream=None):
         """K = K0 + K(D - D0) with the correction in `precision`; J, E in FP64.
         K0 must be the FP64 K of C0 from build() on this plan."""
@@ -212,6 +232,7 @@ class Plan:
                                         _ptr(J), _ptr(K), _ptr(E), _ptr(scr), scr.numel(), _stream_handle(stream)))
         return J, K, E
 
+    @_on_stream
     def build_uks(self, Ca, Cb, precision="fp64", out=None, stream=None):
         """Open-shell build: J (from D_a + D_b), K_a, K_b and E = [E_J, E_K] with
         D_s = C_s C_s^T; Cb (or Ca) may have zero columns."""
@@ -241,6 +262,7 @@ class Plan:
                                       _stream_handle(stream)))
         return J, Ka, Kb, E
 
+    @_on_stream
     def autotune(self, C, precision="fp64", stream=None):
         """Time the candidate tile shapes and split counts of the K contraction
         for this C shape (dfjk_autotune) and keep the fastest; returns
@@ -259,6 +281,7 @@ class Plan:
         dec = lambda c: (int(c) // 1000, int(c) % 1000)   # noqa: E731  (1000 * tile + split)
         return dec(chosen.value), {dec(cand[i]): float(ms[i]) for i in range(ncand.value)}
 
+    @_on_stream
     def offload(self, stream=None):
         """Move B to page-locked host memory (dfjk_offload); later builds stream
         it back slab by slab.  Frees the device setup workspace."""
@@ -287,6 +310,7 @@ class Plan:
         _check(N.lib().dfjk_profile_read(self._h, ms.ctypes.data_as(N.P_dbl), cnt.ctypes.data_as(N.P_i32)))
         return {N.lib().dfjk_stage_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(self.NSTAGES)}
 
+    @_on_stream
     def export(self, kind, stream=None):
         if kind in (EXPORT_INT3C, EXPORT_B):
             shape = (self.naux, self.nao, self.nao)
@@ -296,6 +320,7 @@ class Plan:
         _check(N.lib().dfjk_export(self._h, int(kind), _ptr(out), _stream_handle(stream)))
         return out
 
+    @_on_stream
     def sample(self, kind, idx, stream=None):
         idx = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device="cuda").contiguous()
         n = idx.shape[0]
@@ -304,6 +329,7 @@ class Plan:
         return out
 
     # -- four-centre direct J/K ---------------------------------------------
+    @_on_stream
     def direct_setup(self, stream=None):
         """Pair tables of the four-centre direct path (needs screen(), not setup())."""
         n = ctypes.c_size_t()
@@ -321,6 +347,7 @@ class Plan:
         _check(N.lib().dfjk_direct_stats(self._h, pairs, ctypes.byref(q)))
         return {"pairs": [int(x) for x in pairs], "quartets": int(q.value)}
 
+    @_on_stream
     def direct_build(self, C=None, D=None, out=None, stream=None):
         """Exact J, K and E = [E_J, E_K] from four-centre integrals (FP64);
         give exactly one of C (nao x nocc, D = 2 C C^T) and D (symmetric)."""
@@ -350,6 +377,7 @@ class Plan:
                                          _ptr(scr), scr.numel(), _stream_handle(stream)))
         return J, K, E
 
+    @_on_stream
     def direct_build_delta(self, D, D0, J0, K0, out=None, stream=None):
         """Incremental exact J, K = J0, K0 + J, K(D - D0) with the
         density-weighted Schwarz screen; E from the full D."""
@@ -420,6 +448,7 @@ class Batch:
         else:
             self.scratch = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
 
+    @_on_stream
     def build(self, Cs, outs=None, stream=None):
         """Cs: list of (nao_i, nocc_i) orbitals; returns [(J, K, E), ...]."""
         dev = torch.device("cuda")

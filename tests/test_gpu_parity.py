@@ -148,6 +148,32 @@ def test_delta_build_fp64_reproduces_direct_build(cluster3_seq):
     assert rel(K, r["K"]) <= 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp32", "int8"])
+def test_increment_is_invariant_to_the_orbital_gauge(cluster3_seq, prec):
+    """Orbitals with one column's sign flipped and two columns rotated into each
+    other give the same density; the increment rotates C onto C0 first, so its
+    error stays that of the small step (without the alignment W = C - C0 would
+    be O(1) and the error that of a direct mixed build)."""
+    d = cluster3_seq
+    plan, C1 = d["plan"], d["C1"]
+    Cg = C1.copy()
+    Cg[:, 0] *= -1.0
+    c, s_ = np.cos(0.7), np.sin(0.7)
+    a, b = Cg[:, 1].copy(), Cg[:, 2].copy()
+    Cg[:, 1], Cg[:, 2] = c * a - s_ * b, s_ * a + c * b
+    J1, K1, E1 = d["ref"]
+    _, Kp, Ep = (t.cpu().numpy() for t in plan.build_delta(C1, d["C0"], d["K0"], precision=prec))
+    Jg, Kg, Eg = (t.cpu().numpy() for t in plan.build_delta(Cg, d["C0"], d["K0"], precision=prec))
+    _, Km, Em = (t.cpu().numpy() for t in plan.build(C=C1, precision=prec))
+    err_p, err_g, err_direct = abs(Ep[1] - E1[1]), abs(Eg[1] - E1[1]), abs(Em[1] - E1[1])
+    print("%s: |dE_K| aligned-step %.3e  gauge-changed %.3e  direct %.3e" % (prec, err_p, err_g, err_direct))
+    assert rel(Jg, J1) <= 1e-12                               # J comes from D itself
+    assert err_g <= 4.0 * err_p + 1e-11
+    assert rel(Kg, K1) <= 4.0 * rel(Kp, K1) + 1e-12
+    if prec == "fp32":
+        assert err_g <= 0.2 * err_direct
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_delta_build_mixed_error_shrinks_with_the_step(cluster3_seq, prec):
     d = cluster3_seq
