@@ -26,8 +26,7 @@ constexpr int kPadF = 64;      // function-pair dimension stored as a multiple o
 // [-64, 64].  Storage per row: chunks of kI8Chunk elements, each chunk the
 // kI8Slices slices one after another ([chunk][slice][64] bytes).  The
 // contraction index of a slab runs over column passes of the half transform
-// (ceil(ncol/16) fragments of 16 columns spread evenly over
-// ceil(fragments/12) passes, all full but the last), then aux rows, then the
+// (ht_pass_frags below), then aux rows, then the
 // pass's columns (its width rounded up to even, so every pass region is a
 // whole number of blocks; the pad column is zero).
 constexpr int kTileK = 128;     // K output tile of the split-K partials and the reductions
@@ -35,6 +34,26 @@ constexpr int kXcds = 8;        // accelerator complex dies of an MI355X, each w
 constexpr int kI8Slices = 5;
 constexpr int kI8Block = 256;
 constexpr int kI8Chunk = 64;
+
+// Half transform: each AO function's partner list (hk_*) is padded to a
+// multiple of kHtChunk entries (a padding entry names a real B row and the
+// zero coefficient row nao), and the coefficient columns run in passes of at
+// most kHtMaxFrag fragments of 16 columns: the fewest passes, the fragments
+// spread evenly over them.  The coefficients go to a zero-padded copy of
+// nao + 1 rows of ht_ldc(ncol) columns.
+constexpr int kHtChunk = 16;
+constexpr int kHtMaxFrag = 10;
+inline int ht_pass_frags(int64_t ncol)
+{
+    const int64_t need = (ncol + 15) / 16, passes = (need + kHtMaxFrag - 1) / kHtMaxFrag;
+    return passes > 0 ? (int)((need + passes - 1) / passes) : 1;
+}
+inline int64_t ht_passes(int64_t ncol)
+{
+    const int64_t f = ht_pass_frags(ncol);
+    return ((ncol + 15) / 16 + f - 1) / f;
+}
+inline int64_t ht_ldc(int64_t ncol) { return ht_passes(ncol) * ht_pass_frags(ncol) * 16; }
 
 // Contraction length of one aux slab of plen rows with ncol columns as the
 // precision stores it, and the bytes of its X buffers (main and second plane).
@@ -284,6 +303,7 @@ struct BuildLayout {
     // offsets into the scratch
     size_t o_D, o_d, o_cpart, o_c, o_X, o_Xlo, o_Bfull, o_X2, o_X2lo, o_U, o_W, o_Kpart, o_Epart, o_Da, o_Db;
     size_t o_Cr, o_align;               // increment: C rotated onto C0, and the alignment's work
+    size_t o_Cp, o_Cp2;                 // zero-padded coefficients read by the half transform (two for the increment)
     size_t o_stage[2];                  // staging of host-resident B slabs
     bool overlap;                       // half transform of the next slab beside the K GEMM
     size_t o_Xb, o_Xblo;                // the second X buffer of the overlapped schedule

@@ -140,9 +140,10 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 struct HTArgs {
     const double *B;          // [f][ld]
     int64_t ld;               // naux_pad
-    const double *C;          // [nao][ncol]
-    int32_t ncol;
-    const int32_t *hk_off, *hk_row, *hk_nu;
+    const double *C;          // [nao + 1][ldc]: coefficients zero-padded to ldc columns, row nao zero
+    int32_t ncol;             // columns of the coefficients
+    int32_t ldc;
+    const int32_t *hk_off, *hk_row, *hk_nu;   // partner lists, each padded to a multiple of kHtChunk
     void *X;                  // [nao][plen][ncol]: aux rows p_begin .. p_begin + plen - 1
                               // (int8 slices: [nao][kdim/64][5][64], see kI8Slices)
     void *Xlo;                // second plane for the BF16 split; block scales for int8
@@ -159,6 +160,17 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float x)
 }
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
+// LDS of one k chunk of the half transform: kHtChunk rows of the 128-wide B
+// tile (the MFMA A operand, LDA apart), then kHtChunk rows of the pass's NCOL
+// coefficient columns (LDC apart).  The row pitches put the four k rows that
+// one fragment read touches on alternating halves of the banks.
+template <int NCOL> struct HtLds {
+    static constexpr int PAD = (16 - NCOL % 32 + 32) % 32;
+    static constexpr int LDC = NCOL + PAD;
+    static constexpr int LDA = 128 + 16;
+    static constexpr int DOUBLES = kHtChunk * (LDA + LDC);
+};
+
 // Int8 output of one half-transform workgroup (mu, 128 aux rows p0.., the
 // column pass ic0.. of width w = min(NCOL, ncol - ic0), stored w_e = w
 // rounded up to even wide).  Contraction index inside the slab:
@@ -169,20 +181,29 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_a
 // for non-negative doubles), e = the least exponent with 2^e > |x|max
 // 128/127, the scale 2^e to g.Xlo; then x 2^-e = sum_s a_s 2^{-7(s+1)} by
 // repeated rounding, every step exact in FP64 (a_0 = rint(128 x 2^-e) in
-// [-127, 127], later a_s in [-64, 64]).  The pad column stores zeros.  The
-// bytes of 64 aux rows at a time (waves 0-3, then 4-7) are assembled in LDS
-// (`stage`, the operand buffers of the finished k loop) and written out as
-// 16-byte pieces, so every HBM line is written whole.
+// [-127, 127], later a_s in [-64, 64]).  The pad column stores zeros.
+// Slicing runs from LDS, 32 aux rows at a time: the two waves that hold them
+// write their FP64 values to the first operand buffer in k order, then every
+// thread slices four consecutive k and stores one 4-byte word per slice, so
+// the registers of the accumulators are the only large live state.  The
+// block maxima and exponents sit at the end of the second buffer.
 template <int NIB>
-__device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB], unsigned long long *bmax,
-                                         int *bexp, unsigned char *stage, int mu, int64_t p0, int ic0, int NCOL,
-                                         int tid, int lane, int wave, int kl)
+__device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB], double *st,
+                                         unsigned char *tab, int mu, int64_t p0, int ic0, int tid, int lane,
+                                         int wave, int kl)
 {
+    constexpr int NCOL = NIB * 16;
+    static_assert(32 * NCOL * 8 <= HtLds<NCOL>::DOUBLES * 8, "32 rows of FP64 must fit a buffer");
+    static_assert(128 * 12 <= HtLds<NCOL>::DOUBLES * 8, "block tables must fit a buffer");
+    unsigned long long *bmax = reinterpret_cast<unsigned long long *>(tab);
+    int *bexp = reinterpret_cast<int *>(tab + 128 * 8);
     const int w = min(NCOL, g.ncol - ic0), we = w + (w & 1);
     const int64_t kbase = g.plen * ic0 + (p0 - g.p_begin) * we;     // a multiple of kI8Block
     const int64_t kdim = g.plen * (int64_t)(g.ncol + (g.ncol & 1));
     const int64_t nblk = kdim / kI8Block;
-    __syncthreads();   // bmax cleared by every thread; the k loop's LDS reads are done
+    __syncthreads();   // the k loop's LDS reads are done
+    if (tid < 128) bmax[tid] = 0ull;
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < NIB; ++j) {
         const int c = j * 16 + (lane & 15);
@@ -192,7 +213,6 @@ __device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB
             const int kl_ = (16 * wave + kl + 4 * r) * we + c;
             atomicMax(&bmax[kl_ / kI8Block], (unsigned long long)__double_as_longlong(fabs(acc[j][r])));
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     const int nb = 128 * we / kI8Block;
@@ -202,167 +222,144 @@ __device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB
         bexp[tid] = e;
         static_cast<double *>(g.Xlo)[(int64_t)mu * nblk + kbase / kI8Block + tid] = ldexp(1.0, e);
     }
-    __syncthreads();
-    const int hb = 64 * we * kI8Slices;                               // bytes of 64 aux rows
-    unsigned char *dst0 = static_cast<unsigned char *>(g.X) + (int64_t)mu * kdim * kI8Slices +
-                          (kbase / kI8Chunk) * (kI8Chunk * kI8Slices);
-    for (int h = 0; h < 2; ++h) {
-        if ((wave >> 2) == h) {
+    unsigned char *dst = static_cast<unsigned char *>(g.X) + (int64_t)mu * kdim * kI8Slices +
+                         (kbase / kI8Chunk) * (kI8Chunk * kI8Slices);
+    const int qk = 32 * we;                                            // k of 32 aux rows
+    for (int q = 0; q < 4; ++q) {
+        __syncthreads();   // exponents written; the previous quarter's values read
+        if ((wave >> 1) == q) {
 #pragma unroll
             for (int j = 0; j < NIB; ++j) {
                 const int c = j * 16 + (lane & 15);
                 if (c >= we) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int kl_ = (16 * wave + kl + 4 * r) * we + c;
-                    const int kh = kl_ - h * 64 * we;
-                    double t = c < w ? ldexp(acc[j][r], -bexp[kl_ / kI8Block]) : 0.0;
-                    unsigned char *d = stage + (kh / kI8Chunk) * (kI8Chunk * kI8Slices) + (kh % kI8Chunk);
-#pragma unroll
-                    for (int sl = 0; sl < kI8Slices; ++sl) {
-                        t *= 128.0;
-                        const double a = rint(t);
-                        t -= a;
-                        d[sl * kI8Chunk] = (unsigned char)(signed char)(int)a;
-                    }
-                }
-                // one fragment column at a time: keeps the epilogue's live
-                // registers within the k loop's budget
-                __builtin_amdgcn_sched_barrier(0);
+                for (int r = 0; r < 4; ++r)
+                    st[(16 * (wave & 1) + kl + 4 * r) * we + c] = c < w ? acc[j][r] : 0.0;
             }
         }
         __syncthreads();
-        for (int i = tid * 16; i < hb; i += 512 * 16)
-            *reinterpret_cast<uint4 *>(dst0 + h * hb + i) = *reinterpret_cast<const uint4 *>(stage + i);
-        __syncthreads();
+        for (int it = tid; it < qk / 4; it += 512) {
+            const int kq = 4 * it, k = q * qk + kq;                  // k within the workgroup's range
+            const int e = bexp[k / kI8Block];                        // four k share a block
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t[u] = ldexp(st[kq + u], -e);
+            unsigned char *d = dst + (k / kI8Chunk) * (kI8Chunk * kI8Slices) + (k % kI8Chunk);
+#pragma unroll
+            for (int sl = 0; sl < kI8Slices; ++sl) {
+                unsigned int word = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    t[u] *= 128.0;
+                    const double a = rint(t[u]);
+                    t[u] -= a;
+                    word |= (unsigned int)(unsigned char)(signed char)(int)a << (8 * u);
+                }
+                *reinterpret_cast<unsigned int *>(d + sl * kI8Chunk) = word;
+            }
+        }
     }
 }
 
+// s_waitcnt immediate for vmcnt(0) (gfx9 encoding; expcnt and lgkmcnt at
+// their maxima do not wait), issued through the builtin so the compiler's own
+// wait insertion knows the loads have retired.
+constexpr int kHtWaitVm0 = 0 | (7 << 4) | (15 << 8);
+
 // Workgroup (mu, 128-row P tile, column pass of NIB*16 columns) of eight
-// waves; wave w owns rows p0 + 16w .. +15 (one MFMA fragment).  The k list
-// of mu is walked in chunks of 16.  Both operands of a chunk go through
-// double-buffered LDS: the gathered tensor rows B[row_k][p0 .. p0+127]
-// (1 KB contiguous per k) and the gathered coefficient rows C[nu_k][cols].
-// The next chunk is loaded into registers while the current one feeds the
-// MFMAs, with its row indices read one chunk earlier; one barrier per chunk.
-// Eight single-fragment waves keep four waves per SIMD for up to 160 columns.
+// waves, each 16 aux rows x NIB fragments: X[mu][P][i] = sum over mu's
+// partners k of B[row_k][P] C[nu_k][i].  The partners run in chunks of
+// kHtChunk; each chunk's B rows (1 KB each) and coefficient rows move from
+// global memory straight into one of two LDS buffers (global_load_lds, 16
+// bytes a lane, no registers), the next chunk in flight while the MFMAs use
+// the current one, one barrier per chunk.  Wave w brings rows 2w and 2w+1 of
+// both operands; the partner indices of the chunk after next are loaded
+// into a register (lane l: entry l of the chunk) with the DMA, so issuing a
+// chunk never waits on an index load.  The padded partner lists make every
+// chunk whole; the padded coefficients keep every 16-byte piece in bounds.
 template <int OUT, int NIB>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NIB <= 10 ? 4 : 2)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_halftrans(HTArgs g)
 {
-    constexpr int NT = 512, KC = 16;
-    constexpr int NCOL = NIB * 16;
-    constexpr int PAD = (16 - NCOL % 32 + 32) % 32;     // k rows of a fragment read land on opposite bank halves
-    constexpr int LDC = NCOL + PAD;
-    constexpr int LDA = 128 + 16;                       // same for the 128-wide tensor rows
-    constexpr int NLC = (KC * NCOL / 2 + NT - 1) / NT;  // double2 loads per thread per chunk (C)
-    constexpr int NLA = KC * 128 / 2 / NT;              // double2 loads per thread per chunk (B) = 2
-    // one LDS block for both operand buffers, so the int8 output can reuse
-    // all of it as its staging area after the k loop
-    __shared__ __attribute__((aligned(16))) double smem[2 * KC * LDC + 2 * KC * LDA];
-    double (*Cs)[KC * LDC] = reinterpret_cast<double (*)[KC * LDC]>(smem);
-    double (*As)[KC * LDA] = reinterpret_cast<double (*)[KC * LDA]>(smem + 2 * KC * LDC);
-    static_assert(sizeof(smem) >= (size_t)(kI8Slices * 64) * NCOL, "int8 staging must fit the operand buffers");
-    // int8 output: |x| maxima and exponents of the workgroup's scale blocks
-    // (128 rows x an even pass width w <= 256: at most 128 blocks)
-    __shared__ unsigned long long bmax[OUT == OUT_I8 ? 128 : 1];
-    __shared__ int bexp[OUT == OUT_I8 ? 128 : 1];
-    if (OUT == OUT_I8 && threadIdx.x < 128) bmax[threadIdx.x] = 0ull;
+    constexpr int KC = kHtChunk, NCOL = NIB * 16;
+    constexpr int LDA = HtLds<NCOL>::LDA, LDC = HtLds<NCOL>::LDC;
+    constexpr int NPR = (NCOL + 127) / 128;             // DMA instructions per coefficient row
+    // two chunk buffers as separate arrays: the compiler then tells a read of
+    // one from a DMA into the other and does not wait for unrelated loads
+    __shared__ __attribute__((aligned(1024))) double sb0[HtLds<NCOL>::DOUBLES];
+    __shared__ __attribute__((aligned(1024))) double sb1[HtLds<NCOL>::DOUBLES];
     const int mu = g.order[blockIdx.y];
     const int64_t p0 = g.p_begin + (int64_t)blockIdx.x * 128;
     const int ic0 = blockIdx.z * NCOL;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int kb = g.hk_off[mu], ke = g.hk_off[mu + 1];
+    const int nch = (ke - kb) / KC;
     const int kl = lane >> 4;   // k within an MFMA step
 
     f64x4 acc[NIB];
 #pragma unroll
     for (int j = 0; j < NIB; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    auto load_rows = [&](int kc, int (&r)[NLA]) {
+    // partner indices of chunk ci (lane l: entry l % 16; past the list: its last entry)
+    int rowv = 0, nuv = 0;
+    auto load_idx = [&](int ci) {
+        const int k = min(kb + ci * KC + (lane & 15), ke - 1);
+        rowv = g.hk_row[k];
+        nuv = g.hk_nu[k];
+    };
+    auto dma = [&](double *buf) {
 #pragma unroll
-        for (int it = 0; it < NLA; ++it) {
-            const int k = kc + (tid + NT * it) / 64;
-            r[it] = (k < ke) ? g.hk_row[k] : -1;
+        for (int i = 0; i < 2; ++i) {
+            const int r = 2 * wave + i;
+            const int row = __builtin_amdgcn_readlane(rowv, r);
+            const int nu = __builtin_amdgcn_readlane(nuv, r);
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(g.B + (int64_t)row * g.ld + p0 + 2 * lane),
+                (__attribute__((address_space(3))) void *)(buf + r * LDA), 16, 0, 0);
+#pragma unroll
+            for (int q = 0; q < NPR; ++q)
+                if (q * 128 + 2 * lane < NCOL)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(g.C + (int64_t)nu * g.ldc + ic0 + q * 128 + 2 * lane),
+                        (__attribute__((address_space(3))) void *)(buf + KC * LDA + r * LDC + q * 128), 16, 0, 0);
         }
     };
-    // B rows and X are streamed once; non-temporal accesses keep them from
-    // evicting the coefficient rows C, which every workgroup re-reads from L2
-    auto load_a = [&](const int (&r)[NLA], double2 (&a)[NLA]) {
-#pragma unroll
-        for (int it = 0; it < NLA; ++it) {
-            const int pp = ((tid + NT * it) % 64) * 2;
-            if (r[it] >= 0) {
-                const f64x2 v = __builtin_nontemporal_load(
-                    reinterpret_cast<const f64x2 *>(g.B + (int64_t)r[it] * g.ld + p0 + pp));
-                a[it] = double2{v[0], v[1]};
-            } else {
-                a[it] = double2{0.0, 0.0};
-            }
-        }
-    };
-    auto load_c = [&](int kc, double2 (&c)[NLC]) {
-#pragma unroll
-        for (int it = 0; it < NLC; ++it) {
-            const int e = tid + NT * it;              // double2 index in the KC x NCOL chunk
-            const int kk = e / (NCOL / 2), cc = (e % (NCOL / 2)) * 2;
-            double2 v{0.0, 0.0};
-            if (e < KC * NCOL / 2 && kc + kk < ke) {
-                const double *src = g.C + (int64_t)g.hk_nu[kc + kk] * g.ncol + ic0 + cc;
-                if (ic0 + cc + 1 < g.ncol) v = double2{src[0], src[1]};
-                else if (ic0 + cc < g.ncol) v.x = src[0];
-            }
-            c[it] = v;
-        }
-    };
-    auto store = [&](int buf, const double2 (&a)[NLA], const double2 (&c)[NLC]) {
-#pragma unroll
-        for (int it = 0; it < NLA; ++it) {
-            const int e = tid + NT * it, kk = e / 64, pp = (e % 64) * 2;
-            *reinterpret_cast<double2 *>(&As[buf][kk * LDA + pp]) = a[it];
-        }
-#pragma unroll
-        for (int it = 0; it < NLC; ++it) {
-            const int e = tid + NT * it;
-            if (e < KC * NCOL / 2) {
-                const int kk = e / (NCOL / 2), cc = (e % (NCOL / 2)) * 2;
-                Cs[buf][kk * LDC + cc] = c[it].x;
-                Cs[buf][kk * LDC + cc + 1] = c[it].y;
-            }
-        }
-    };
-
-    int rows[NLA];
-    double2 areg[NLA], creg[NLC];
-    load_rows(kb, rows);
-    load_a(rows, areg);
-    load_c(kb, creg);
-    load_rows(kb + KC, rows);
-    int buf = 0;
-    for (int kc = kb; kc < ke; kc += KC) {
-        store(buf, areg, creg);
+    // one chunk: wait for its DMA (every wave's, through the barrier, which
+    // also tells that every wave has finished reading `nxt`), start the next
+    // chunk's DMA into `nxt`, then the MFMAs on `cur`
+    auto step = [&](const double *cur, double *nxt, int c) {
+        __builtin_amdgcn_s_waitcnt(kHtWaitVm0);
         __syncthreads();
-        const bool more = kc + KC < ke;
-        if (more) {
-            load_a(rows, areg);
-            load_c(kc + KC, creg);
-            load_rows(kc + 2 * KC, rows);
+        if (c + 1 < nch) {
+            dma(nxt);
+            load_idx(c + 2);
         }
-        const double *as = As[buf] + kl * LDA + 16 * wave + (lane & 15);
-        const double *cs = Cs[buf] + kl * LDC + (lane & 15);
+        __builtin_amdgcn_sched_barrier(0);
+        const double *as = cur + kl * LDA + 16 * wave + (lane & 15);
+        const double *cs = cur + KC * LDA + kl * LDC + (lane & 15);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
+        for (int ks = 0; ks < KC / 4; ++ks) {
             const double a = as[ks * 4 * LDA];
 #pragma unroll
             for (int j = 0; j < NIB; ++j)
                 acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cs[ks * 4 * LDC + j * 16], acc[j], 0, 0, 0);
         }
-        buf ^= 1;
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    if (nch > 0) {
+        load_idx(0);
+        dma(sb0);
+        load_idx(1);
+        for (int c = 0; c < nch; c += 2) {
+            step(sb0, sb1, c);
+            if (c + 1 < nch) step(sb1, sb0, c + 1);
+        }
     }
 
     if constexpr (OUT == OUT_I8) {
-        store_i8(g, acc, bmax, bexp, reinterpret_cast<unsigned char *>(smem), mu, p0, ic0, NCOL, tid, lane, wave,
-                 kl);
+        store_i8(g, acc, sb0, reinterpret_cast<unsigned char *>(sb1), mu, p0, ic0, tid, lane, wave, kl);
         return;
     }
 #pragma unroll
@@ -389,25 +386,31 @@ void k_halftrans(HTArgs g)
     }
 }
 
+// Coefficients for the half transform: Cp[nao + 1][ldc] with C in the first
+// ncol columns of the first nao rows and zeros elsewhere.
+__global__ __launch_bounds__(256) void k_pad_coef(const double *__restrict__ C, int64_t nao, int32_t ncol,
+                                                  int32_t ldc, double *__restrict__ Cp)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (nao + 1) * ldc) return;
+    const int64_t r = i / ldc, c = i % ldc;
+    Cp[i] = (r < nao && c < ncol) ? C[r * ncol + c] : 0.0;
+}
+
 template <int OUT>
 static void launch_halftrans(const HTArgs &h, int64_t nao, hipStream_t s)
 {
-    // column passes of at most 16 fragments (12 for the int8 output, whose
-    // slicing epilogue needs the registers: wider passes spill), the
-    // fragments spread evenly over the passes for the int8 output
-    const int nib_needed = (h.ncol + 15) / 16;
-    const int cap = OUT == OUT_I8 ? 12 : 16;
-    const int passes = (nib_needed + cap - 1) / cap;
-    const int nib = OUT == OUT_I8 ? (nib_needed + passes - 1) / passes : (nib_needed < cap ? nib_needed : cap);
-    dim3 grid((unsigned)(h.plen / 128), (unsigned)nao, (unsigned)passes);
+    const int nib = ht_pass_frags(h.ncol);
+    dim3 grid((unsigned)(h.plen / 128), (unsigned)nao, (unsigned)ht_passes(h.ncol));
 #define HT_CASE(N) \
     case N: hipLaunchKernelGGL((k_halftrans<OUT, N>), grid, dim3(512), 0, s, h); break;
     switch (nib) {
         HT_CASE(1) HT_CASE(2) HT_CASE(3) HT_CASE(4) HT_CASE(5) HT_CASE(6) HT_CASE(7) HT_CASE(8)
-        HT_CASE(9) HT_CASE(10) HT_CASE(11) HT_CASE(12) HT_CASE(13) HT_CASE(14) HT_CASE(15) HT_CASE(16)
+        HT_CASE(9) HT_CASE(10)
     }
 #undef HT_CASE
 }
+static_assert(kHtMaxFrag == 10, "launch_halftrans instantiates 1..kHtMaxFrag fragments");
 
 static void dispatch_halftrans(int precision, const HTArgs &h, int64_t nao, hipStream_t s)
 {
@@ -432,7 +435,8 @@ __global__ __launch_bounds__(256) void k_expand_B(const double *__restrict__ B, 
     const int64_t P = p_begin + pl;
     double *dst = Bt + ((int64_t)mu * plen + pl) * nao;
     for (int64_t n = 0; n < nao; ++n) dst[n] = 0.0;
-    for (int k = hk_off[mu]; k < hk_off[mu + 1]; ++k) dst[hk_nu[k]] = B[(int64_t)hk_row[k] * ld + P];
+    for (int k = hk_off[mu]; k < hk_off[mu + 1]; ++k)
+        if (hk_nu[k] < nao) dst[hk_nu[k]] = B[(int64_t)hk_row[k] * ld + P];   // padding entries name row nao
 }
 
 // [U | W] = [C + C0 | C - C0] (nao x 2 nocc): 2(C C^T - C0 C0^T) = U W^T + W U^T.
@@ -694,7 +698,11 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.overlap = may_overlap && L.nslab >= 2;
     L.kdim = x_kdim(precision, slab, L.ncol);
     const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
-    L.nsplit_k = precision == DFJK_FP64 ? choose_ksplit(ntiles, L.kdim, p.num_cus, L.ktile == 64 ? 4 : 2)
+    // FP64: the 128-wide tiles fill two slots per CU; the 64-wide tiles need
+    // about four times the workgroups (16 per CU: 64 x 34 splits measured
+    // like 64 x 32, the fastest shape on the 32-water cluster, 12.1-12.4 ms
+    // per build, against 12.7-12.9 ms at 8 splits)
+    L.nsplit_k = precision == DFJK_FP64 ? choose_ksplit(ntiles, L.kdim, p.num_cus, L.ktile == 64 ? 16 : 2)
                : precision == DFJK_MIXED_INT8 ? i8_nsplit(p.nao, L.kdim, !delta, p.num_cus)
                                               : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
     if (nsplit == 0 && !with_D && !delta) {   // a split count the autotuner measured for this shape
@@ -721,6 +729,9 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.o_X = take(xb);
     L.o_Xlo = xlo ? take(xlo) : 0;
     L.o_Bfull = with_D ? take(nx * 8) : 0;
+    const size_t cpad = (size_t)(p.nao + 1) * ht_ldc(L.ncol) * 8;
+    L.o_Cp = take(cpad);
+    L.o_Cp2 = delta ? take(cpad) : 0;
     if (L.overlap) {
         L.o_Xb = take(xb);
         L.o_Xblo = xlo ? take(xlo) : 0;
@@ -765,10 +776,23 @@ static void launch_j(Plan &p, const BuildLayout &L, const double *D, double *J, 
                            p.d.f_nu, p.d.f_w, p.nf, nao, 0, J);
 }
 
-static void launch_ht(const Plan &p, int precision, const double *C, int32_t ncol, int64_t p_begin, int64_t plen,
-                      void *X, void *Xlo, hipStream_t s)
+// The zero-padded copy of the coefficients that the half transform reads
+// (k_pad_coef), in the build scratch at `off`.
+static const double *pad_coef(const Plan &p, const double *C, int32_t ncol, char *scratch, size_t off, hipStream_t s)
 {
-    HTArgs h{p.d.B, p.naux_pad, C, ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen, p.d.hk_order};
+    double *Cp = reinterpret_cast<double *>(scratch + off);
+    const int64_t ldc = ht_ldc(ncol), n = (p.nao + 1) * ldc;
+    hipLaunchKernelGGL(k_pad_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, p.nao, ncol, (int32_t)ldc,
+                       Cp);
+    return Cp;
+}
+
+// Half transform of one aux slab of B (rows ld apart) with padded coefficients Cp.
+static void launch_ht(const Plan &p, int precision, const double *B, int64_t ld, const double *Cp, int32_t ncol,
+                      int64_t p_begin, int64_t plen, void *X, void *Xlo, hipStream_t s)
+{
+    HTArgs h{B, ld, Cp, ncol, (int32_t)ht_ldc(ncol), p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen,
+             p.d.hk_order};
     dispatch_halftrans(precision, h, p.nao, s);
 }
 
@@ -832,6 +856,7 @@ static void contract_slabs_overlapped(Plan &p, const BuildLayout &L, const doubl
     const int ntiles = L.ntile * (L.ntile + 1) / 2;
     const size_t slab_part = (size_t)L.nsplit_k * ntiles * L.ktile * L.ktile;
     hipStream_t hs = p.ht_stream;
+    const double *Cp = pad_coef(p, C, (int32_t)ncol, scratch, L.o_Cp, s);
     (void)hipEventRecord(p.ev_fork, s);
     (void)hipStreamWaitEvent(hs, p.ev_fork, 0);
     auto ht = [&](int64_t sl) {
@@ -840,7 +865,7 @@ static void contract_slabs_overlapped(Plan &p, const BuildLayout &L, const doubl
         if (sl >= 2) (void)hipStreamWaitEvent(hs, p.ev_kdone[b], 0);
         pr.stream = hs;
         pr.mark(ST_HALFTRANS, true);
-        launch_ht(p, L.precision, C, (int32_t)ncol, pb, plen, X[b], Xlo[b], hs);
+        launch_ht(p, L.precision, p.d.B, ld, Cp, (int32_t)ncol, pb, plen, X[b], Xlo[b], hs);
         pr.mark(ST_HALFTRANS, false);
         pr.stream = s;
         (void)hipEventRecord(p.ev_ht[b], hs);
@@ -877,13 +902,15 @@ static void contract_slabs(Plan &p, const BuildLayout &L, const double *C1, cons
     const size_t slab_part = (size_t)L.nsplit_k * ntiles * L.ktile * L.ktile;
     void *X2 = L.delta ? scratch + L.o_X2 : nullptr;
     void *X2lo = L.o_X2lo ? scratch + L.o_X2lo : nullptr;
+    const double *Cp1 = pad_coef(p, C1, (int32_t)ncol, scratch, L.o_Cp, s);
+    const double *Cp2 = L.delta ? pad_coef(p, C2, (int32_t)ncol, scratch, L.o_Cp2, s) : nullptr;
     for (int64_t sl = 0; sl < L.nslab; ++sl) {
         const int64_t pb = sl * L.slab, plen = (ld - pb < L.slab) ? ld - pb : L.slab;
         const int64_t kdim = x_kdim(L.precision, plen, ncol);
         pr.mark(ST_HALFTRANS, true);
-        launch_ht(p, L.precision, C1, (int32_t)ncol, pb, plen, X, Xlo, s);
+        launch_ht(p, L.precision, p.d.B, ld, Cp1, (int32_t)ncol, pb, plen, X, Xlo, s);
         if (L.delta)
-            launch_ht(p, L.precision, C2, (int32_t)ncol, pb, plen, X2, X2lo, s);
+            launch_ht(p, L.precision, p.d.B, ld, Cp2, (int32_t)ncol, pb, plen, X2, X2lo, s);
         else if (L.with_D)
             hipLaunchKernelGGL(k_expand_B, dim3((unsigned)((plen + 255) / 256), (unsigned)nao), dim3(256), 0, s,
                                p.d.B, ld, p.d.hk_off, p.d.hk_row, p.d.hk_nu, nao, pb, plen, Bt);
@@ -1054,7 +1081,8 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         p.prof.mark(ST_J, false);
         if (L.nslab == 1 && L.precision == DFJK_FP64) {
             p.prof.mark(ST_HALFTRANS, true);
-            launch_ht(p, DFJK_FP64, C[i], (int32_t)L.ncol, 0, p.naux_pad, sc + L.o_X, nullptr, s);
+            const double *Cp = pad_coef(p, C[i], (int32_t)L.ncol, sc, L.o_Cp, s);
+            launch_ht(p, DFJK_FP64, p.d.B, p.naux_pad, Cp, (int32_t)L.ncol, 0, p.naux_pad, sc + L.o_X, nullptr, s);
             p.prof.mark(ST_HALFTRANS, false);
             GemmArgs g{};
             g.A = reinterpret_cast<const double *>(sc + L.o_X); g.lda = L.kdim;
@@ -1154,6 +1182,7 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
     hipLaunchKernelGGL(k_gather_d, dim3((unsigned)((p.nf_pad + 255) / 256)), dim3(256), 0, s, D, nao, p.d.f_mu,
                        p.d.f_nu, p.d.f_w, p.nf, p.nf_pad, dvec);
     fill(J, nao * nao, 0.0, s);
+    const double *Cp = pad_coef(p, C, (int32_t)L.ncol, scratch, L.o_Cp, s);
     for (int64_t sl = 0; sl < L.nslab; ++sl) {
         const int b = (int)(sl & 1);
         const int64_t pb = sl * L.slab, plen = (ld - pb < L.slab) ? ld - pb : L.slab;
@@ -1168,9 +1197,7 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
                                p.d.f_mu, p.d.f_nu, p.d.f_w, p.nf, nao, 1, J);
         pr.mark(ST_J, false);
         pr.mark(ST_HALFTRANS, true);
-        HTArgs h{stage[b], plen, C, (int32_t)L.ncol, p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, 0, plen,
-                 p.d.hk_order};
-        dispatch_halftrans(L.precision, h, nao, s);
+        launch_ht(p, L.precision, stage[b], plen, Cp, (int32_t)L.ncol, 0, plen, X, Xlo, s);
         pr.mark(ST_HALFTRANS, false);
         (void)hipEventRecord(p.ev_free[b], s);      // the staging buffer is read
         if (sl + 2 < L.nslab) copy_slab(sl + 2);

@@ -41,10 +41,10 @@ TAU = 1e-14
 
 
 def int8_pass_width(ncol):
-    """Columns per pass of the int8 half transform: at most 12 fragments of
-    16 columns per pass, the fragments spread evenly over the passes."""
+    """Columns per pass of the half transform: at most 10 fragments of 16
+    columns per pass, the fragments spread evenly over the fewest passes."""
     need = (ncol + 15) // 16
-    passes = (need + 11) // 12
+    passes = (need + 9) // 10
     return 16 * ((need + passes - 1) // passes)
 
 
