@@ -52,10 +52,10 @@ def golden_errors(E, K_last):
             "max_abs_dK_rows_vs_oracle": dK, "builds_compared": sorted(int(k) for k in g["builds"])}
 
 
-def committed_traffic():
+def committed_traffic(shape):
     """HBM bytes per launch of the FP64 K kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source changed
-    since those counters were taken."""
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source or its
+    launch shape (tile, split count) changed since those counters were taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "k_gemm_f64_water32.md")
@@ -67,7 +67,10 @@ def committed_traffic():
         return None
     b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
     h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
-    if not b or not h or h.group(1) != sha:
+    k = re.search(r"kernel_shape:\s*(\d+)x(\d+)", text)
+    if not b or not h or h.group(1) != sha or not k:
+        return None
+    if (int(k.group(1)), int(k.group(2))) != (shape["k_tile"], shape["nsplit"]):
         return None
     return int(b.group(1))
 
@@ -599,15 +602,19 @@ def main():
 
     f64 = results["fp64"]
     naux, nocc = mol.naux, mol.nelec // 2
+    # the FP64 build's K launch shape (tile, split count) before any autotuning
+    tplan = Plan.from_molecule(mol, schwarz_thresh=1e-14).screen()
+    shape = tplan.build_shape(nocc)
     k_flops = float(nao) * (nao + 1) * naux * nocc        # lower triangle of 2 X X^T per build, useful flops
     # the K contraction of a build runs as one launch per aux slab (equal slabs
     # here); per launch: the build's flops over the launches, the mean duration
     k_launches = f64["stage_launches"]["build.K"] / (args.steps * NBUILDS)
     k_ms = f64["stages_ms_per_launch"]["build.K"]
     achieved = k_flops / k_launches / (k_ms * 1e-3) / 1e12
-    roofline = {"kernel": "build.K (FP64 MFMA X X^T, k_gemm_f64<128>)", "bound": "mfma",
+    roofline = {"kernel": "build.K (FP64 MFMA X X^T, k_gemm_f64<%d>, %d splits)" % (shape["k_tile"], shape["nsplit"]),
+                "bound": "mfma",
                 "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": committed_traffic(),
+                "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": committed_traffic(shape),
                 "traffic_source": "profiles/k_gemm_f64_water32.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, per launch)",
                 "flops_per_launch": k_flops / k_launches, "ms_per_launch": k_ms, "launches_per_build": k_launches}
     # the other steps of an FP64 build against their bounds (HIP-event stage times;
@@ -647,7 +654,7 @@ def main():
         direct = direct_bench(mol, Cd, nbuild=args.direct_builds, E_df=ref_E, S=S)
 
     # split-count autotuner on the same molecule (outside the timed steps)
-    tplan = Plan.from_molecule(mol, schwarz_thresh=1e-14).screen().setup()
+    tplan.setup()
     chosen, cand_ms = tplan.autotune(Cd[0])
     autotune = {"chosen_tile": chosen[0], "chosen_nsplit": chosen[1],
                 "ms_per_build_by_tile_and_nsplit": {"%dx%d" % k: round(v, 3) for k, v in cand_ms.items()}}

@@ -277,6 +277,14 @@ int dfjk_autotune(dfjk_plan *plan, const double *d_C, int32_t nocc, int32_t prec
                   size_t scratch_bytes, void *stream, int32_t *chosen, int32_t *ncand, int32_t *cand,
                   double *ms);
 
+/* The launch shape a closed-shell C-route dfjk_build with this nocc and
+ * precision will use (after dfjk_screen; the autotuner's or dfjk_options'
+ * choice included): shape[0] the K output tile (64 or 128), shape[1] the
+ * split count of the K contraction, shape[2] aux functions per slab,
+ * shape[3] the number of slabs.  shape is a host array of 4.  For profiling
+ * and reporting; no device work. */
+int dfjk_build_shape(const dfjk_plan *plan, int32_t nocc, int32_t precision, int32_t *shape);
+
 /* Host-resident B, the paper's large-system storage (paper, Section 2.1
  * "Dataset and Performance": integrals held in host memory and moved to the
  * GPU asynchronously).  After dfjk_setup, dfjk_offload copies the whitened

@@ -262,6 +262,13 @@ class Plan:
                                       _stream_handle(stream)))
         return J, Ka, Kb, E
 
+    def build_shape(self, nocc, precision="fp64"):
+        """The K launch shape of a C-route build (dfjk_build_shape):
+        {"k_tile", "nsplit", "aux_slab", "nslab"}."""
+        out = (ctypes.c_int32 * 4)()
+        _check(N.lib().dfjk_build_shape(self._h, int(nocc), PRECISION[precision], out))
+        return dict(zip(("k_tile", "nsplit", "aux_slab", "nslab"), (int(v) for v in out)))
+
     @_on_stream
     def autotune(self, C, precision="fp64", stream=None):
         """Time the candidate tile shapes and split counts of the K contraction

@@ -97,6 +97,9 @@ def test_call_order_is_enforced_without_device():
     assert lib.dfjk_build_static(plan._h, ctypes.c_void_p(8), 5, None, 0, ctypes.c_void_p(8), ctypes.c_void_p(8),
                                  ctypes.c_void_p(8), None) == 7
     assert b"setup" in lib.dfjk_last_error()
+    shape = (ctypes.c_int32 * 4)()
+    assert lib.dfjk_build_shape(plan._h, 5, 0, shape) == 7                 # not screened
+    assert lib.dfjk_build_shape(plan._h, 5, 0, None) == 1
     assert lib.dfjk_build_uks(plan._h, ctypes.c_void_p(8), 3, ctypes.c_void_p(8), 2, 0, ctypes.c_void_p(8),
                               ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(8), ctypes.c_void_p(8),
                               1 << 20, None) == 7

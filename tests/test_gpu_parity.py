@@ -436,6 +436,8 @@ def test_k_tile_choices(n, tile):
     the oracle."""
     mol, S, C = case(n)
     plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU, k_tile=tile).screen().setup()
+    shape = plan.build_shape(C.shape[1])
+    assert shape["k_tile"] == tile and shape["nsplit"] >= 1 and shape["nslab"] == 1
     J, K, E = (t.cpu().numpy() for t in plan.build(C=C))
     ref = oracle.dfjk(mol, C=C)
     assert rel(K, ref["K"]) <= 1e-10 and rel(J, ref["J"]) <= 1e-10
@@ -452,6 +454,8 @@ def test_autotuned_split_count(cluster5):
     plan = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU).screen().setup()
     chosen, times = plan.autotune(d["C"])
     assert chosen in times and len(times) >= 2 and all(t > 0 for t in times.values())
+    shape = plan.build_shape(d["C"].shape[1])
+    assert (shape["k_tile"], shape["nsplit"]) == chosen
     print("split candidates (ms per build):", times, "chosen", chosen)
     J, K, E = (t.cpu().numpy() for t in plan.build(C=d["C"]))
     assert rel(K, d["ref"]["K"]) <= 1e-10
