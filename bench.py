@@ -190,9 +190,12 @@ def make_inputs(n=32, box=10.0, geom_seed=1, cocc_seed=1):
 
 
 def run_job(Plan, mol, Cd, precision, bufs, profile):
-    """One job: setup + NBUILDS builds.  precision 'fp64' / 'fp32' / 'bf16x3'
-    builds every K directly; '<p>_incr' builds K(C_0) in FP64 and each later
-    K as K(C_0) + K(D - D_0) with the increment in precision <p>."""
+    """One job: setup + NBUILDS builds.  precision 'fp64' / 'int8' / 'fp32' /
+    'bf16x3' builds every K directly; '<p>_incr' builds K(C_0) in FP64 and
+    each later K as K(C_0) + K(D - D_0) with the increment in precision <p>;
+    'checked' runs dfjk_build_checked (int8 when its energy-error bound is
+    within 1e-6 Eh, else FP64; 'checked_<budget>' another budget) and logs
+    each build's choice and bound."""
     plan = Plan.from_molecule(mol, schwarz_thresh=1e-14)
     if profile:
         plan.profile(True)
@@ -200,9 +203,14 @@ def run_job(Plan, mol, Cd, precision, bufs, profile):
     outs = []
     incr = precision.endswith("_incr")
     base = precision[:-5] if incr else precision
+    plan.checked_log = []
     for k, C in enumerate(Cd):
         J, K, E = bufs[k]
-        if incr and k > 0:
+        if precision.startswith("checked"):
+            budget = float(precision.split("_")[1]) if "_" in precision else 1e-6
+            _, _, _, chosen, bound = plan.build_checked(C, budget=budget, out=(J, K, E))
+            plan.checked_log.append((chosen, bound))
+        elif incr and k > 0:
             plan.build_delta(C, Cd[0], bufs[0][1], precision=base, out=(J, K, E))
         else:
             plan.build(C=C, precision="fp64" if incr else base, out=(J, K, E))
@@ -548,7 +556,8 @@ def main():
     results = {}
     ref_E = None
     ref_K = None
-    modes = ["fp64"] + ([] if args.no_mixed else ["int8", "fp32", "bf16x3", "fp32_incr", "bf16x3_incr"])
+    modes = ["fp64"] + ([] if args.no_mixed else ["int8", "checked", "checked_1e-5", "fp32", "bf16x3", "fp32_incr",
+                                                      "bf16x3_incr"])
     if args.modes:
         modes = ["fp64"] + [m for m in args.modes.split(",") if m != "fp64"]
     for prec in modes:
@@ -568,6 +577,7 @@ def main():
                 stage_ms[k] = stage_ms.get(k, 0.0) + ms
                 stage_n[k] = stage_n.get(k, 0) + n
             info = plan.info()
+            checked_log = plan.checked_log
             plan.close()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -588,6 +598,9 @@ def main():
             "E_K": E[:, 1].tolist(),
         }
         r.update(golden_errors(E, K_last))
+        if prec.startswith("checked"):
+            r["per_build_choice"] = [c for c, _ in checked_log]
+            r["per_build_bound_Eh"] = [float("%.4g" % b) for _, b in checked_log]
         if prec == "fp64":
             ref_E, ref_K = E, K_last
             r["screening"] = {k: info[k] for k in ("sig_shell_pairs", "nshell_pairs", "nf", "triplets_kept")}

@@ -67,13 +67,14 @@ typedef enum {
     DFJK_MIXED_FP32 = 1,     /* X stored FP32, K on FP32 MFMA, FP64 chunk sums   */
     DFJK_MIXED_BF16X3 = 2,   /* X split into BF16 hi+lo, K = hi.hi + hi.lo +
                                 lo.hi on BF16 MFMA, FP32 chunks, FP64 sums       */
-    DFJK_MIXED_INT8 = 3      /* X split into five int8 slices under a power-of-
-                                two scale per 256-element block of each row
-                                (Ozaki scheme); K from the 15 slice products
-                                of combined order <= 6 on int8 MFMA with exact
-                                int32 sums, folded into FP64 once per block.
-                                Per product the dropped part is below
-                                2^-33 of the product of the two block scales */
+    DFJK_MIXED_INT8 = 3      /* X split into five int8 slices a_0..a_4 under a
+                                power-of-two scale per 256-element block of
+                                each row (Ozaki scheme); K from the 15 slice
+                                products a_i b_j with i + j <= 4 on int8 MFMA
+                                with exact int32 sums, folded into FP64 once
+                                per block.  Per product the dropped part is
+                                below 2^-33 of the product of the two block
+                                scales */
 } dfjk_precision;
 
 /* One basis (AO or auxiliary): nshell uncontracted shells on atoms. */
@@ -276,6 +277,32 @@ int dfjk_autotune_bytes(const dfjk_plan *plan, int32_t nocc, int32_t precision, 
 int dfjk_autotune(dfjk_plan *plan, const double *d_C, int32_t nocc, int32_t precision, void *d_scratch,
                   size_t scratch_bytes, void *stream, int32_t *chosen, int32_t *ncand, int32_t *cand,
                   double *ms);
+
+/* Precision chosen per build against an energy-error budget (paper,
+ * Section 5 "Limitations and Future Development: Mixed Precision": lower
+ * precision where an error estimate shows it is enough).  Runs the int8
+ * C-route build, then a rigorous bound on |E_K(int8) - E_K| with E_K the
+ * exact contraction of the same half-transformed tensor X, computed on the
+ * device from the stored int8 digits of X and from C (Cauchy-Schwarz in the
+ * seminorm of D = 2 C C^T, which is positive semidefinite):
+ *   bound = 1/2 [2 sqrt(Q lambda R) + lambda R + lambda T] + F,
+ *   lambda >= lambda_max(D) from |(C^T C)^16|_F^(1/16),
+ *   A_s = sum over X of (a_s 2^{e - 7(s+1)})^2, T = sum_{i+j>=5} sqrt(A_i A_j),
+ *   R = sum over blocks of 256 2^{2e-72} (the slices' remainders),
+ *   Q = 2 |E_K(int8)| + lambda T + 2F, F the FP64 rounding of the folds.
+ * E_J is FP64 in both precisions.  If bound <= budget (Eh) the int8 result
+ * stands and *chosen = DFJK_MIXED_INT8; else the build is redone in FP64 and
+ * *chosen = DFJK_FP64.  *bound receives the bound either way.  Outputs as for
+ * dfjk_build (d_E[2] = {E_J, E_K}); chosen and bound are host pointers.
+ * d_scratch must hold dfjk_build_checked_bytes(plan, nocc).  Synchronises
+ * `stream` (the choice is read on the host), so it cannot be captured in a
+ * HIP graph.  Errors: DFJK_E_STATE before dfjk_setup; DFJK_E_INVALID for NULL
+ * pointers, nocc out of range or budget <= 0; DFJK_E_OOM for scratch below
+ * the size query. */
+int dfjk_build_checked_bytes(const dfjk_plan *plan, int32_t nocc, size_t *bytes);
+int dfjk_build_checked(dfjk_plan *plan, const double *d_C, int32_t nocc, double budget, double *d_J,
+                       double *d_K, double *d_E, void *d_scratch, size_t scratch_bytes, void *stream,
+                       int32_t *chosen, double *bound);
 
 /* The launch shape a closed-shell C-route dfjk_build with this nocc and
  * precision will use (after dfjk_screen; the autotuner's or dfjk_options'

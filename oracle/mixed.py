@@ -102,3 +102,46 @@ def int8_scale_envelope(A, B, block=256, nslices=5):
         _, e = int8_slices(X, block, nslices)
         return np.where(m > 0, np.ldexp(1.0, e), 0.0)   # an all-zero block is exact
     return block * (scales(A) @ scales(B).T)
+
+
+def gram_lambda_bound(C, squarings=4):
+    """An upper bound of lambda_max(C^T C): |(C^T C)^(2^s)|_F^(2^-s), each
+    square normalised by its Frobenius norm (the Frobenius norm bounds the
+    spectral one)."""
+    M = np.asarray(C, np.float64).T @ np.asarray(C, np.float64)
+    f0 = np.linalg.norm(M)
+    if f0 == 0.0:
+        return 0.0, 0.0
+    P = M / f0
+    log_l = np.log(f0)
+    for t in range(1, squarings + 1):
+        P = P @ P
+        g = np.linalg.norm(P)
+        P = P / g
+        log_l += np.log(g) / 2 ** t
+    return f0, np.exp(log_l)
+
+
+def int8_energy_bound(A, C, EK_int8, nsums, block=256):
+    """Bound on |E_K(int8) - E_K(exact)| for K = 2 A A^T (rows A[mu], k),
+    E_K = -1/4 Tr(D K), D = 2 C C^T, by Cauchy-Schwarz in the D-seminorm:
+      1/2 [2 sqrt(Q lam R) + lam R + lam T] + F
+    with A_s the sums of squares of the scaled digits, R the remainders'
+    block-scale bound, T = sum_{i+j>=5} sqrt(A_i A_j), lam >= lambda_max(D),
+    Q = 2 |E_K(int8)| + lam T + 2F, F the FP64 fold rounding (nsums sums).
+    Returns a dict with the bound and its parts."""
+    A = np.asarray(A, np.float64)
+    n, kdim = A.shape
+    a, e = int8_slices(A, block)
+    E = np.repeat(e, block, axis=1)
+    As = [float((np.ldexp(a[s], E - 7 * (s + 1)) ** 2).sum()) for s in range(len(a))]
+    R = float((256.0 * np.ldexp(1.0, 2 * e - 72)).sum())
+    ns = len(a)
+    T = sum(np.sqrt(As[i] * As[j]) for i in range(1, ns) for j in range(1, ns) if i + j >= ns)
+    f0, lmax = gram_lambda_bound(C)
+    lam = 2.0 * lmax
+    u = 2.0 ** -53
+    F = nsums * u / (1 - nsums * u) * 2.0 * f0 * sum(np.sqrt(x) for x in As) ** 2
+    Q = 2.0 * abs(EK_int8) + lam * T + 2.0 * F
+    bound = 0.5 * (2.0 * np.sqrt(Q * lam * R) + lam * R + lam * T) + F
+    return dict(bound=bound, lam=lam, R=R, T=T, Q=Q, A=As, F=F)

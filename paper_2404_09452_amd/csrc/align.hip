@@ -148,3 +148,62 @@ void launch_align(const double *C, const double *C0, int64_t nao, int32_t nocc, 
 }
 
 }  // namespace dfjk
+
+namespace dfjk {
+
+// stat[s] = |P|_F for the s-th squaring's product, then P /= stat[s]
+__global__ __launch_bounds__(256) void k_frob_scale(double *__restrict__ P, int64_t n, double *__restrict__ stat)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < n; e += 256) s += P[e] * P[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double f = sqrt(red[0]);
+    __syncthreads();
+    if (threadIdx.x == 0) stat[0] = f;
+    if (f > 0.0)
+        for (int64_t e = threadIdx.x; e < n; e += 256) P[e] /= f;
+}
+
+// out[0] = |M|_F, out[1] >= lambda_max(M), M = C^T C: |M^16|_F^(1/16) =
+// f_0 g_1^(1/2) g_2^(1/4) g_3^(1/8) g_4^(1/16) with f_0 = |M|_F and g_t the
+// norm of the t-th normalised square (the Frobenius norm bounds the spectral
+// one, and |M^16|_2 = lambda_max^16), times 1 + 1e-12 for the rounding of
+// the products.
+__global__ void k_gram_bound(const double *__restrict__ stat, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double l = stat[0];
+    for (int t = 1; t <= kGramSquarings; ++t) l *= pow(stat[t], 1.0 / (double)(1 << t));
+    out[0] = stat[0];
+    out[1] = l * (1.0 + 1e-12);
+}
+
+size_t gram_work_doubles(int32_t nocc) { return (size_t)2 * nocc * nocc + 16; }
+
+void launch_gram_bound(const double *C, int64_t nao, int32_t nocc, double *work, double *out, hipStream_t s)
+{
+    const int n = nocc;
+    const int64_t nn = (int64_t)n * n;
+    double *P = work, *P2 = P + nn, *stat = P2 + nn;
+    const dim3 g_small((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32));
+    hipLaunchKernelGGL((k_gemm_small<true, false>), g_small, dim3(256), 0, s, n, n, (int)nao, C, n, C, n, P, n,
+                       1.0, 0.0);
+    hipLaunchKernelGGL(k_frob_scale, dim3(1), dim3(256), 0, s, P, nn, stat);
+    for (int t = 1; t <= kGramSquarings; ++t) {
+        hipLaunchKernelGGL((k_gemm_small<false, false>), g_small, dim3(256), 0, s, n, n, n, P, n, P, n, P2, n, 1.0,
+                           0.0);
+        hipLaunchKernelGGL(k_frob_scale, dim3(1), dim3(256), 0, s, P2, nn, stat + t);
+        double *tmp = P;
+        P = P2;
+        P2 = tmp;
+    }
+    hipLaunchKernelGGL(k_gram_bound, dim3(1), dim3(64), 0, s, stat, out);
+}
+
+}  // namespace dfjk

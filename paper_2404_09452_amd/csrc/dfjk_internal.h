@@ -34,6 +34,7 @@ constexpr int kXcds = 8;        // accelerator complex dies of an MI355X, each w
 constexpr int kI8Slices = 5;
 constexpr int kI8Block = 256;
 constexpr int kI8Chunk = 64;
+constexpr int64_t kI8AutoSlab = 1024;   // largest automatic aux slab of an int8 build
 
 // Half transform: each AO function's partner list (hk_*) is padded to a
 // multiple of kHtChunk entries (a padding entry names a real B row and the
@@ -304,6 +305,8 @@ struct BuildLayout {
     size_t o_D, o_d, o_cpart, o_c, o_X, o_Xlo, o_Bfull, o_X2, o_X2lo, o_U, o_W, o_Kpart, o_Epart, o_Da, o_Db;
     size_t o_Cr, o_align;               // increment: C rotated onto C0, and the alignment's work
     size_t o_Cp, o_Cp2;                 // zero-padded coefficients read by the half transform (two for the increment)
+    bool norms;                         // int8: add each slab's digit sums into o_norms (dfjk_build_checked)
+    size_t o_norms;
     size_t o_stage[2];                  // staging of host-resident B slabs
     bool overlap;                       // half transform of the next slab beside the K GEMM
     size_t o_Xb, o_Xblo;                // the second X buffer of the overlapped schedule
@@ -341,6 +344,16 @@ void launch_direct_build(const Plan &p, const DirectLayout &L, const double *C, 
 void launch_density(const double *C, int64_t nao, int32_t nocc, double scale, double *D, hipStream_t s);
 
 // align.hip: Cr = C Q, Q the orthogonal polar factor of C^T C0 (Procrustes)
+// Gram bound (align.hip): out[0] = |C^T C|_F, out[1] >= lambda_max(C^T C)
+// from |(C^T C)^16|_F^(1/16); work of gram_work_doubles(nocc) doubles.
+constexpr int kGramSquarings = 4;
+size_t gram_work_doubles(int32_t nocc);
+void launch_gram_bound(const double *C, int64_t nao, int32_t nocc, double *work, double *out, hipStream_t s);
+// Int8 energy-error bound (bound.hip)
+size_t i8_bound_work_doubles(int64_t nao, int32_t nocc);
+void launch_i8_norms(const void *X, const double *scales, int64_t nao, int64_t kdim, double *acc, hipStream_t s);
+void launch_i8_bound(const double *C, int64_t nao, int32_t nocc, const double *acc, const double *E, int nsums,
+                     double *work, double *out, hipStream_t s);
 size_t align_work_doubles(int32_t nocc);
 void launch_align(const double *C, const double *C0, int64_t nao, int32_t nocc, double *work, double *Cr,
                   hipStream_t s);

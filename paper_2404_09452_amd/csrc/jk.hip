@@ -694,6 +694,12 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
         const int64_t ncol_e = L.ncol + (L.ncol & 1);
         const int64_t cap = ((int64_t)UINT32_MAX / (128 * kI8Slices) / ncol_e) / kPadAux * kPadAux;
         if (slab > cap) slab = cap;
+        // an int8 build that needs several automatic slabs takes slabs of at
+        // most 1,024 aux: on the 128-water cluster (640 orbitals) 512 / 768 /
+        // 1024 / 1536 / 2048 / 3840 aux per slab measured 1.17 / 1.16 / 1.15 /
+        // 1.18 / 1.28 / 1.43 s per build (the GEMM's k range per workgroup
+        // grows with the slab).  A molecule that fits one slab keeps it.
+        if (force_slab <= 0 && p.aux_slab <= 0 && slab < p.naux_pad && slab > kI8AutoSlab) slab = kI8AutoSlab;
     }
     if (slab < kPadAux) slab = kPadAux;
     if (slab > p.naux_pad) slab = p.naux_pad;
@@ -913,6 +919,9 @@ static void contract_slabs(Plan &p, const BuildLayout &L, const double *C1, cons
         const int64_t kdim = x_kdim(L.precision, plen, ncol);
         pr.mark(ST_HALFTRANS, true);
         launch_ht(p, L.precision, p.d.B, ld, Cp1, (int32_t)ncol, pb, plen, X, Xlo, s);
+        if (L.norms)
+            launch_i8_norms(X, static_cast<const double *>(Xlo), nao, kdim, reinterpret_cast<double *>(scratch + L.o_norms),
+                            s);
         if (L.delta)
             launch_ht(p, L.precision, p.d.B, ld, Cp2, (int32_t)ncol, pb, plen, X2, X2lo, s);
         else if (L.with_D)
@@ -1202,6 +1211,9 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
         pr.mark(ST_J, false);
         pr.mark(ST_HALFTRANS, true);
         launch_ht(p, L.precision, stage[b], plen, Cp, (int32_t)L.ncol, 0, plen, X, Xlo, s);
+        if (L.norms)
+            launch_i8_norms(X, static_cast<const double *>(Xlo), nao, x_kdim(L.precision, plen, L.ncol),
+                            reinterpret_cast<double *>(scratch + L.o_norms), s);
         pr.mark(ST_HALFTRANS, false);
         (void)hipEventRecord(p.ev_free[b], s);      // the staging buffer is read
         if (sl + 2 < L.nslab) copy_slab(sl + 2);

@@ -172,6 +172,36 @@ class Plan:
         return J, K, E
 
     @_on_stream
+    def build_checked(self, C, budget=1e-6, out=None, stream=None):
+        """The precision chosen against an energy-error budget (Eh) through
+        dfjk_build_checked: int8 when its rigorous bound is within the
+        budget, else FP64.  Returns (J, K, E, chosen, bound) with chosen
+        "int8" or "fp64"."""
+        dev = torch.device("cuda")
+        C = torch.as_tensor(C, dtype=torch.float64, device=dev).contiguous()
+        if C.dim() != 2 or C.shape[0] != self.nao:
+            raise ValueError("C must be (nao, nocc)")
+        nocc = C.shape[1]
+        if out is None:
+            J = torch.empty((self.nao, self.nao), dtype=torch.float64, device=dev)
+            K = torch.empty_like(J)
+            E = torch.empty(2, dtype=torch.float64, device=dev)
+        else:
+            J, K, E = out
+        key = (int(nocc), "checked", False)
+        if key not in self._scratch:
+            n = ctypes.c_size_t()
+            _check(N.lib().dfjk_build_checked_bytes(self._h, int(nocc), ctypes.byref(n)))
+            self._scratch[key] = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        scr = self._scratch[key]
+        chosen, bound = ctypes.c_int32(), ctypes.c_double()
+        _check(N.lib().dfjk_build_checked(self._h, _ptr(C), int(nocc), float(budget), _ptr(J), _ptr(K), _ptr(E),
+                                          _ptr(scr), scr.numel(), _stream_handle(stream), ctypes.byref(chosen),
+                                          ctypes.byref(bound)))
+        name = {v: k for k, v in PRECISION.items()}[chosen.value]
+        return J, K, E, name, bound.value
+
+    @_on_stream
     def build_static(self, C=None, D=None, precision="fp64", out=None, stream=None):
         """As build, through dfjk_build_static: the library's static device
         scratch instead of a workspace, so the call allocates nothing in the

@@ -100,6 +100,14 @@ def test_call_order_is_enforced_without_device():
     shape = (ctypes.c_int32 * 4)()
     assert lib.dfjk_build_shape(plan._h, 5, 0, shape) == 7                 # not screened
     assert lib.dfjk_build_shape(plan._h, 5, 0, None) == 1
+    assert lib.dfjk_build_checked_bytes(plan._h, 5, ctypes.byref(n)) == 7         # not screened
+    chosen, bound = ctypes.c_int32(), ctypes.c_double()
+    assert lib.dfjk_build_checked(plan._h, ctypes.c_void_p(8), 5, 1e-6, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                  ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 20, None, ctypes.byref(chosen),
+                                  ctypes.byref(bound)) == 7
+    assert lib.dfjk_build_checked(plan._h, ctypes.c_void_p(8), 5, 1e-6, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                  ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 20, None, None,
+                                  ctypes.byref(bound)) == 7                         # state is checked first
     assert lib.dfjk_build_uks(plan._h, ctypes.c_void_p(8), 3, ctypes.c_void_p(8), 2, 0, ctypes.c_void_p(8),
                               ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(8), ctypes.c_void_p(8),
                               1 << 20, None) == 7

@@ -68,3 +68,30 @@ def test_water32_mixed_against_golden(water32, prec):
         assert relJ <= 1e-10 and dEJ <= 1e-10 * abs(b["E_J"])     # J stays FP64
         if prec == "int8":
             assert dEK <= 1e-6
+
+
+def test_water32_checked_sequence(water32):
+    """The ten builds of the SCF-like sequence through dfjk_build_checked
+    (budget 1e-6 Eh): every build's choice and bound are reported, every
+    int8 build stays within its bound of the FP64 build of the same orbitals,
+    and builds 0 and 9 are within 1e-6 Eh of the oracle's stored values."""
+    g, plan, Cs = water32
+    inp = g["inputs"]
+    z, xyz = W.water_cluster(inp["n_waters"], inp["box_angstrom"], inp["geometry_seed"])
+    mol = W.make_molecule(z, xyz)
+    S = W.overlap_by_quadrature(mol)
+    C0 = W.occupied_orbitals(S, g["nocc"], inp["orbital_seed"])
+    for k in range(10):
+        C = W.perturbed_orbitals(C0, S, k)
+        J, K, E, chosen, bound = plan.build_checked(C, budget=1e-6)
+        E = E.cpu().numpy()
+        E64 = plan.build(C=C)[2].cpu().numpy()
+        print("build %d: %s, bound %.3e Eh, |E_K - E_K(fp64)| %.3e" % (k, chosen, bound, abs(E[1] - E64[1])))
+        assert abs(E[0] - E64[0]) <= 1e-10 * abs(E64[0])
+        if chosen == "int8":
+            assert bound <= 1e-6 and abs(E[1] - E64[1]) <= bound + 1e-9
+        else:
+            assert bound > 1e-6 and E[1] == E64[1]
+        if str(k) in g["builds"]:
+            b = g["builds"][str(k)]
+            assert abs(E[0] - b["E_J"]) <= 1e-6 and abs(E[1] - b["E_K"]) <= 1e-6

@@ -628,3 +628,54 @@ def test_mixed_mutations_break_the_device_checks():
     acc = 2.0 ** -15 * 2 * (ab @ ab.T)
     Kdrop = 2 * (hi @ hi.T + lo @ hi.T)
     assert (np.abs(Kdrop - Kf) / acc).max() > 4.0
+
+
+def test_int8_energy_error_decomposition_and_bound():
+    """The int8 energy-error bound of dfjk_build_checked, term by term, on
+    3 waters: the error of E_K = -1/2 sum_k x_k^T D x_k equals
+    1/2 sum_k [2 x~^T D r + r^T D r + sum_{i+j>=5} alpha_i^T D alpha_j]
+    (an identity, to FP64 rounding); each term is within its Cauchy-Schwarz
+    bound in the D-seminorm; lambda bounds lambda_max(D) and R bounds the
+    remainders; the assembled bound covers the actual error.  Mutations of
+    the derivation (a dropped remainder term, the dropped-order sum over
+    i + j >= 4) break the identity."""
+    from oracle import mixed as M
+    A = _x_rows_water3()
+    z, x = W.water_cluster(3, W.cluster_box(3), 103)
+    mol = W.make_molecule(z, x)
+    S = W.overlap_by_quadrature(mol)
+    C = W.occupied_orbitals(S, mol.nelec // 2, 10)
+    # the rows of A are (P, i) pairs with i over nocc + pad columns: expand C to match
+    nao, kdim = A.shape
+    D = 2 * C @ C.T
+    Eex = -0.5 * np.einsum("mk,mn,nk->", A, D, A)
+    Kq = 2 * M.int8_product(A, A)
+    Eq = -0.25 * (D * Kq).sum()
+    a, e = M.int8_slices(A)
+    Ee = np.repeat(e, 256, axis=1)
+    alpha = [np.ldexp(a[s], Ee - 7 * (s + 1)) for s in range(5)]
+    xt = sum(alpha)
+    r = A - xt
+    t1 = np.einsum("mk,mn,nk->", xt, D, r)
+    t2 = np.einsum("mk,mn,nk->", r, D, r)
+    t3 = sum(np.einsum("mk,mn,nk->", alpha[i], D, alpha[j]) for i in range(5) for j in range(5) if i + j >= 5)
+    ident = 0.5 * (2 * t1 + t2 + t3)
+    tol = 1e-13 * abs(Eex)                     # FP64 rounding of the two energies
+    print("identity residual %.2e, error %.2e, terms %.2e %.2e %.2e" % (abs((Eq - Eex) - ident), Eq - Eex, t1, t2, t3))
+    assert abs((Eq - Eex) - ident) <= tol
+    # mutations of the decomposition
+    assert abs((Eq - Eex) - 0.5 * (t1 + t2 + t3)) > 3 * tol
+    t3m = sum(np.einsum("mk,mn,nk->", alpha[i], D, alpha[j]) for i in range(5) for j in range(5) if i + j >= 4)
+    assert abs((Eq - Eex) - 0.5 * (2 * t1 + t2 + t3m)) > 1e3 * tol
+    b = M.int8_energy_bound(A, C, Eq, nsums=kdim // 256 + 16)
+    lam_exact = 2 * np.linalg.eigvalsh(C.T @ C).max()
+    assert lam_exact <= b["lam"] <= 1.2 * lam_exact
+    assert (r ** 2).sum() <= b["R"]
+    assert np.isclose(sum(b["A"]) + 0.0, sum(float((al ** 2).sum()) for al in alpha), rtol=1e-12)
+    Q = np.einsum("mk,mn,nk->", xt, D, xt)
+    assert Q <= b["Q"]
+    assert abs(t1) <= np.sqrt(Q * b["lam"] * b["R"])
+    assert abs(t2) <= b["lam"] * b["R"]
+    assert abs(t3) <= b["lam"] * b["T"]
+    assert abs(Eq - Eex) <= b["bound"]
+    print("int8 |dE_K| %.3e, bound %.3e" % (abs(Eq - Eex), b["bound"]))
