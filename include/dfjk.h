@@ -312,6 +312,30 @@ int dfjk_build_checked(dfjk_plan *plan, const double *d_C, int32_t nocc, double 
  * and reporting; no device work. */
 int dfjk_build_shape(const dfjk_plan *plan, int32_t nocc, int32_t precision, int32_t *shape);
 
+/* Setup straight into host memory, for molecules whose B should not or
+ * cannot be held in HBM even once (paper, Section 2.1 "Dataset and
+ * Performance": integrals in host memory for large systems).  After the
+ * metric, its Cholesky factor and L^-1 (as dfjk_setup), B = U L^-T is formed
+ * one block of function-pair rows at a time: the three-centre integrals of
+ * the block's shell pairs, then the whitening GEMM, then the block's rows of
+ * every aux slab copied into h_pinned (slab-major [slab][f][plen], the layout
+ * dfjk_offload writes; page-locked host memory the caller allocates and keeps
+ * until dfjk_plan_destroy) on a copy stream of the plan, two row buffers so
+ * the copies of one block overlap the next.  U and B are never whole in
+ * device memory.  dfjk_setup_host_bytes: host_bytes for B and device_bytes
+ * for the workspace with the widest row blocks whose workspace stays within
+ * max_device_bytes (0: one block of every row); DFJK_E_OOM if not even one
+ * shell pair's rows fit.  The workspace holds the plan's tables afterwards
+ * and stays borrowed until dfjk_plan_destroy.  Later builds (C route, any
+ * precision) stream B back slab by slab as after dfjk_offload.  Synchronises
+ * `stream`.  Errors: DFJK_E_STATE unless the plan is screened and not yet
+ * host-resident; DFJK_E_NOT_POSDEF as dfjk_setup; DFJK_E_OOM for buffers
+ * below the size query. */
+int dfjk_setup_host_bytes(const dfjk_plan *plan, size_t max_device_bytes, size_t *host_bytes,
+                          size_t *device_bytes);
+int dfjk_setup_host(dfjk_plan *plan, void *h_pinned, size_t host_bytes, void *d_workspace, size_t device_bytes,
+                    void *stream);
+
 /* Host-resident B, the paper's large-system storage (paper, Section 2.1
  * "Dataset and Performance": integrals held in host memory and moved to the
  * GPU asynchronously).  After dfjk_setup, dfjk_offload copies the whitened

@@ -51,6 +51,8 @@ SIGNATURES = {
     "dfjk_autotune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_sz, c_vp, P_i32, P_i32, P_i32, P_dbl]),
     "dfjk_build_shape": (c_i32, [c_vp, c_i32, c_i32, P_i32]),
     "dfjk_build_checked_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_sz)]),
+    "dfjk_setup_host_bytes": (c_i32, [c_vp, c_sz, ctypes.POINTER(c_sz), ctypes.POINTER(c_sz)]),
+    "dfjk_setup_host": (c_i32, [c_vp, c_vp, c_sz, c_vp, c_sz, c_vp]),
     "dfjk_build_checked": (c_i32, [c_vp, c_vp, c_i32, c_dbl, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp, P_i32, P_dbl]),
     "dfjk_offload_bytes": (c_i32, [c_vp, ctypes.POINTER(c_sz), ctypes.POINTER(c_sz)]),
     "dfjk_offload": (c_i32, [c_vp, c_vp, c_sz, c_vp, c_sz, c_vp]),

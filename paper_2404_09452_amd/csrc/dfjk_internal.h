@@ -18,6 +18,7 @@ constexpr int kMaxLAO = 2;     // highest AO angular momentum
 constexpr int kMaxLAux = 3;    // highest aux angular momentum
 constexpr int kPadAux = 128;   // aux dimension stored as a multiple of this (half-transform tile)
 constexpr int kPadF = 64;      // function-pair dimension stored as a multiple of this
+constexpr int kMaxPairRows = (2 * kMaxLAO + 1) * (2 * kMaxLAO + 1);   // function pairs of one shell pair
 
 // Int8 slices of the half-transformed tensor (DFJK_MIXED_INT8).  Row mu of X
 // is cut into blocks of kI8Block contraction elements; each block has a
@@ -272,6 +273,7 @@ void launch_boys_eval(int mmax, int64_t n, const double *T, double *F, const dou
 void launch_schwarz_pairs(int64_t npair, const ShellsDev &ao, double *q, hipStream_t s);
 void launch_schwarz_aux(int32_t nsh, const ShellsDev &ax, double *q, hipStream_t s);
 void launch_int3c(const Plan &p, hipStream_t s);
+void launch_int3c_rows(const Plan &p, double *U, int64_t f_base, int32_t i0, int32_t i1, hipStream_t s);
 void launch_int2c(const Plan &p, hipStream_t s);
 void upload_constants(const double coef[kMaxLAux + 1][7][10], hipStream_t s);
 // Pair tables of the direct path: for each class, px..p, Eb and Ek from the

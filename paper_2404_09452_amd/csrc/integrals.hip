@@ -271,8 +271,9 @@ struct Int3cArgs {
     ShellsDev ao, ax;
     const double *boys;
     double tau;
-    double *U;
+    double *U;                // rows f - f_base (a block of function-pair rows)
     int64_t ld;
+    int64_t f_base;
 };
 
 template <int LA, int LB, int LC>
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(128) void k_int3c(Int3cArgs g)
     const int ip = g.p_begin + (int)(tid / npc);
     const int ic = g.c_begin + (int)(tid % npc);
     const int a = g.pa[ip], b = g.pb[ip];
-    double *out = g.U + (int64_t)g.pf0[ip] * g.ld + g.ax.off[ic];
+    double *out = g.U + ((int64_t)g.pf0[ip] - g.f_base) * g.ld + g.ax.off[ic];
 
     if (g.pq[ip] * g.ax.q[ic] < g.tau) {
 #pragma unroll
@@ -405,13 +406,19 @@ static ShellsDev ax_view(const Plan &p)
 
 void launch_int3c(const Plan &p, hipStream_t s)
 {
+    launch_int3c_rows(p, p.d.U, 0, 0, (int32_t)p.sp_a.size(), s);
+}
+
+// U rows of the kept pairs i0 <= i < i1, written at row f - f_base of U.
+void launch_int3c_rows(const Plan &p, double *U, int64_t f_base, int32_t i0, int32_t i1, hipStream_t s)
+{
     Int3cArgs g{};
     g.pa = p.d.sp_a; g.pb = p.d.sp_b; g.pf0 = p.d.sp_f0; g.pq = p.d.sp_q;
     g.ao = ao_view(p); g.ax = ax_view(p);
-    g.boys = p.d.boys; g.tau = p.thresh; g.U = p.d.U; g.ld = p.naux_pad;
+    g.boys = p.d.boys; g.tau = p.thresh; g.U = U; g.ld = p.naux_pad; g.f_base = f_base;
     static const int cls_la[6] = {0, 1, 1, 2, 2, 2}, cls_lb[6] = {0, 0, 1, 0, 1, 2};
     for (int pc = 0; pc < 6; ++pc) {
-        g.p_begin = p.sp_class[pc].begin; g.p_end = p.sp_class[pc].end;
+        g.p_begin = std::max(p.sp_class[pc].begin, i0); g.p_end = std::min(p.sp_class[pc].end, i1);
         if (g.p_end <= g.p_begin) continue;
         for (int lc = 0; lc <= kMaxLAux; ++lc) {
             g.c_begin = p.ax_class[lc].begin; g.c_end = p.ax_class[lc].end;

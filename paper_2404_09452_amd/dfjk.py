@@ -131,6 +131,22 @@ class Plan:
         _check(N.lib().dfjk_setup(self._h, _ptr(self._ws), self._ws.numel(), _stream_handle(stream)))
         return self
 
+    @_on_stream
+    def setup_host(self, max_device_bytes=0, stream=None):
+        """Set up with B formed block by block straight into page-locked host
+        memory (dfjk_setup_host): the device workspace stays within
+        max_device_bytes (0: no limit).  Returns self; self.setup_host_info
+        holds the host and device byte counts."""
+        hb, db = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(N.lib().dfjk_setup_host_bytes(self._h, int(max_device_bytes), ctypes.byref(hb), ctypes.byref(db)))
+        self._host_B = torch.empty(hb.value, dtype=torch.uint8, pin_memory=True)
+        self._ws = torch.empty(db.value, dtype=torch.uint8, device="cuda")
+        _check(N.lib().dfjk_setup_host(self._h, ctypes.c_void_p(self._host_B.data_ptr()), hb.value, _ptr(self._ws),
+                                       self._ws.numel(), _stream_handle(stream)))
+        self._scratch = {}
+        self.setup_host_info = {"host_bytes": hb.value, "device_bytes": db.value}
+        return self
+
     def build_bytes(self, nocc, precision="fp64", with_density=False):
         n = ctypes.c_size_t()
         _check(N.lib().dfjk_build_bytes(self._h, int(nocc), PRECISION[precision], int(with_density),

@@ -101,6 +101,10 @@ def test_call_order_is_enforced_without_device():
     assert lib.dfjk_build_shape(plan._h, 5, 0, shape) == 7                 # not screened
     assert lib.dfjk_build_shape(plan._h, 5, 0, None) == 1
     assert lib.dfjk_build_checked_bytes(plan._h, 5, ctypes.byref(n)) == 7         # not screened
+    n2 = ctypes.c_size_t()
+    assert lib.dfjk_setup_host_bytes(plan._h, 0, ctypes.byref(n), ctypes.byref(n2)) == 7
+    assert lib.dfjk_setup_host(plan._h, ctypes.c_void_p(8), 1 << 20, ctypes.c_void_p(8), 1 << 20, None) == 7
+    assert lib.dfjk_setup_host_bytes(plan._h, 0, None, ctypes.byref(n2)) == 1
     chosen, bound = ctypes.c_int32(), ctypes.c_double()
     assert lib.dfjk_build_checked(plan._h, ctypes.c_void_p(8), 5, 1e-6, ctypes.c_void_p(8), ctypes.c_void_p(8),
                                   ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 20, None, ctypes.byref(chosen),

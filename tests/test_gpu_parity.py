@@ -4,6 +4,8 @@ Tolerances: the plain FP64 path must agree with the oracle to 1e-10 relative
 (max |diff| / max |oracle|) on J and K and on E_J, E_K; per-kernel checks use
 tighter bounds where the arithmetic allows (integrals 1e-12 relative plus the
 screening threshold, Boys 1e-14 relative)."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -16,6 +18,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
+from paper_2404_09452_amd import _native as N  # noqa: E402
 from paper_2404_09452_amd import dfjk as G  # noqa: E402
 
 TAU = 1e-14
@@ -427,6 +430,52 @@ def test_host_resident_B_matches_device_B(cluster5, slab):
     assert e.value.status == "UNSUPPORTED"
     host.close()
     dev.close()
+
+
+@pytest.mark.parametrize("slab", [0, 128])
+def test_setup_straight_into_host_memory(cluster5, slab):
+    """dfjk_setup_host under a device budget far below B: U and B formed in
+    row blocks, each block's rows copied into the host slabs.  The host B
+    equals the one dfjk_offload copies from a whole setup (every row of B is
+    the same GEMM row), so builds in every precision are bitwise those of the
+    offloaded plan, and FP64 matches the oracle."""
+    d = cluster5
+    ref_plan = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU, aux_slab=slab).screen().setup().offload()
+    plan = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU, aux_slab=slab).screen()
+    info = plan.info()
+    nf_pad, npad = -(-info["nf"] // 64) * 64, info["naux_pad"]
+    b_bytes = nf_pad * npad * 8
+    hb, db = ctypes.c_size_t(), ctypes.c_size_t()
+    assert N.lib().dfjk_setup_host_bytes(plan._h, 0, ctypes.byref(hb), ctypes.byref(db)) == 0
+    fixed = db.value - 3 * b_bytes                        # all but the U and two B row buffers
+    rows = max(nf_pad // 16, 32)
+    budget = fixed + 3 * rows * npad * 8 + 8192           # about nf/16 rows per block
+    plan.setup_host(max_device_bytes=budget)
+    dev_bytes = plan.setup_host_info["device_bytes"]
+    print("nf %d, B %.2f MB, device workspace %.2f MB (budget %.2f MB)"
+          % (info["nf"], b_bytes / 1e6, dev_bytes / 1e6, budget / 1e6))
+    assert dev_bytes <= budget and dev_bytes < b_bytes
+    C1 = W.perturbed_orbitals(d["C"], d["S"], 2, eps=1e-2, seed=1000)
+    for C in (d["C"], C1):
+        for prec in ("fp64", "int8", "fp32"):
+            J1, K1, E1 = (t.cpu().numpy() for t in ref_plan.build(C=C, precision=prec))
+            J2, K2, E2 = (t.cpu().numpy() for t in plan.build(C=C, precision=prec))
+            assert np.array_equal(J1, J2) and np.array_equal(K1, K2) and np.array_equal(E1, E2), prec
+    J, K, E = (t.cpu().numpy() for t in plan.build(C=d["C"]))
+    assert rel(K, d["ref"]["K"]) <= 1e-10 and rel(J, d["ref"]["J"]) <= 1e-10
+    with pytest.raises(G.DFJKError) as e:
+        plan.setup_host()
+    assert e.value.status == "STATE"
+    plan.close()
+    ref_plan.close()
+
+
+def test_setup_host_refuses_a_budget_below_one_pair(cluster5):
+    plan = G.Plan.from_molecule(cluster5["mol"], schwarz_thresh=TAU).screen()
+    with pytest.raises(G.DFJKError) as e:
+        plan.setup_host(max_device_bytes=1 << 20)
+    assert e.value.status == "OOM"
+    plan.close()
 
 
 @pytest.mark.parametrize("n,tile", [(3, 64), (5, 64), (3, 128), (5, 128)])
