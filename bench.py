@@ -59,7 +59,7 @@ def committed_traffic(shape):
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "k_gemm_f64_water32.md")
-    src = os.path.join(ROOT, "paper_2404_09452_amd", "csrc", "gemm_f64.h")
+    src = os.path.join(ROOT, "paper_2404_09452_amd", "csrc", "syrk_f64.hip")
     try:
         text = open(path).read()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -336,14 +336,16 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
         srv = Server(executor(), max_active=max_active, hbm_budget_bytes=budget,
                      runtime_reserve_bytes=RUNTIME_RESERVE_BYTES, on_done=progress("closed loop"))
         t0 = time.perf_counter()
+        m0 = time.monotonic_ns()
         closed = srv.serve(reqs(np.zeros(nreq)))
+        m1 = time.monotonic_ns()
         wall = time.perf_counter() - t0
         sat = summarize(closed, wall)
         mu = nreq / wall
         print("bench: serving %s closed loop: %.2f req/s, %d failed" % (mode, mu, sat["failed"]), file=sys.stderr,
               flush=True)
         r = {"saturation_requests_per_s": round(mu, 3), "saturation_builds_per_s": round(sat["builds_per_s"], 2),
-             "saturation_failed": sat["failed"]}
+             "saturation_failed": sat["failed"], "closed_loop_monotonic_ns": [m0, m1]}
         if sat["errors"]:
             r["saturation_errors"] = sat["errors"]
         for load in loads:
@@ -528,6 +530,9 @@ def main():
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only run the serving stream: --serve-requests requests of 1..64 waters, Poisson "
                          "loads 0.5..1.1 x saturation, for each of --serve-modes; print its JSON")
+    ap.add_argument("--serve-profile", action="store_true",
+                    help="only the serving warm-up and closed-loop runs of --serve-modes with --serve-requests "
+                         "requests of 1..64 waters (for a kernel trace); print their JSON")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 128-water leg and print its JSON (for profiling)")
     ap.add_argument("--large-builds", type=int, default=2)
@@ -542,7 +547,7 @@ def main():
     args = ap.parse_args()
     # serving molecules of 1..64 waters needs unsplit large blocks (set before
     # torch touches the GPU; see serve.configure_allocator)
-    if not args.no_serve or args.serve_sweep:
+    if not args.no_serve or args.serve_sweep or args.serve_profile:
         from paper_2404_09452_amd.serve import configure_allocator
         configure_allocator()
     if args.copy_calibration:
@@ -561,6 +566,10 @@ def main():
     if args.serve_sweep:
         print(json.dumps({"serving_sweep": serving_bench(args.serve_modes.split(","), args.serve_requests, 64,
                                                          loads=(0.5, 0.75, 0.9, 1.1))}))
+        return
+    if args.serve_profile:
+        print(json.dumps({"serving_profile": serving_bench(args.serve_modes.split(","), args.serve_requests, 64,
+                                                           loads=())}))
         return
     if args.only_large:
         print(json.dumps({"water128": large_bench(args.large_builds)}))
@@ -656,7 +665,7 @@ def main():
     k_launches = f64["stage_launches"]["build.K"] / (args.steps * NBUILDS)
     k_ms = f64["stages_ms_per_launch"]["build.K"]
     achieved = k_flops / k_launches / (k_ms * 1e-3) / 1e12
-    roofline = {"kernel": "build.K (FP64 MFMA X X^T, k_gemm_f64<%d>, %d splits)" % (shape["k_tile"], shape["nsplit"]),
+    roofline = {"kernel": "build.K (FP64 MFMA X X^T, k_syrk_f64<%d>, %d splits)" % (shape["k_tile"], shape["nsplit"]),
                 "bound": "mfma",
                 "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": committed_traffic(shape),

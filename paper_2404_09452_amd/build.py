@@ -10,7 +10,7 @@ SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdfjk.so")
 SOURCES = ["host.hip", "integrals.hip", "linalg.hip", "jk.hip", "syrk_mixed.hip", "export.hip", "direct.hip",
-           "align.hip", "bound.hip"]
+           "align.hip", "bound.hip", "syrk_f64.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -346,6 +346,10 @@ void launch_direct_build(const Plan &p, const DirectLayout &L, const double *C, 
 void launch_density(const double *C, int64_t nao, int32_t nocc, double scale, double *D, hipStream_t s);
 
 // align.hip: Cr = C Q, Q the orthogonal polar factor of C^T C0 (Procrustes)
+// FP64 K contraction by LDS DMA (syrk_f64.hip): split-K partial tiles of
+// A B^T, lower tiles or every tile, T = 64 or 128
+void launch_syrk_f64(bool lower, const double *A, const double *B, int64_t M, int64_t kdim, int64_t ksplit,
+                     int nsplit, int T, double *partial, hipStream_t s);
 // Gram bound (align.hip): out[0] = |C^T C|_F, out[1] >= lambda_max(C^T C)
 // from |(C^T C)^16|_F^(1/16); work of gram_work_doubles(nocc) doubles.
 constexpr int kGramSquarings = 4;

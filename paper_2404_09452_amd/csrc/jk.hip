@@ -631,6 +631,8 @@ static int choose_ksplit(int ntiles, int64_t kdim, int num_cus, int per_cu = 2)
     return ns;
 }
 
+static int xcd_round(int ns) { return ns >= kXcds ? ns / kXcds * kXcds : ns; }
+
 BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool with_D, bool delta, int nsplit,
                          bool allow_overlap, int64_t force_slab, int ktile)
 {
@@ -708,11 +710,14 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.overlap = may_overlap && L.nslab >= 2;
     L.kdim = x_kdim(precision, slab, L.ncol);
     const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
-    // FP64: the 128-wide tiles fill two slots per CU; the 64-wide tiles need
-    // about four times the workgroups (16 per CU: 64 x 34 splits measured
-    // like 64 x 32, the fastest shape on the 32-water cluster, 12.1-12.4 ms
-    // per build, against 12.7-12.9 ms at 8 splits)
-    L.nsplit_k = precision == DFJK_FP64 ? choose_ksplit(ntiles, L.kdim, p.num_cus, L.ktile == 64 ? 16 : 2)
+    // FP64 syrk: enough splits for 64 workgroups per CU with 64-wide tiles
+    // and 16 with 128-wide ones (one workgroup fills a CU's LDS; short k
+    // ranges keep a split's panels in L2).  On the 32-water cluster, 64-wide
+    // tiles x 16 / 32 / 64 / 128 splits: 10.56 / 10.06 / 9.81 / 9.61 ms per
+    // build; 128-wide x 8 / 16 / 32: 17.9 / 14.3 / 12.4 ms.  A split count of
+    // 8 or more is rounded down to a multiple of the XCD count, so that the
+    // syrk runs whole splits per XCD.
+    L.nsplit_k = precision == DFJK_FP64 ? xcd_round(choose_ksplit(ntiles, L.kdim, p.num_cus, L.ktile == 64 ? 64 : 16))
                : precision == DFJK_MIXED_INT8 ? i8_nsplit(p.nao, L.kdim, !delta, p.num_cus)
                                               : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
     if (nsplit == 0 && !with_D && !delta) {   // a split count the autotuner measured for this shape
@@ -815,15 +820,9 @@ static void slab_gemm(const BuildLayout &L, bool lower, const void *X, const voi
                       const void *Bop_lo, int64_t nao, int64_t kdim, double *part, hipStream_t s)
 {
     if (L.precision == DFJK_FP64) {
-        GemmArgs g{};
-        g.A = static_cast<const double *>(X); g.lda = kdim;
-        g.B = static_cast<const double *>(Bop); g.ldb = kdim;
-        g.M = g.N = nao;
-        g.k_begin = 0; g.k_end = kdim;
-        g.ksplit = align_up((size_t)((kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
-        g.alpha = 1.0; g.lower = lower ? 1 : 0; g.partial = part;
-        if (L.ktile == 64) gemm_f64<64, false>(g, L.nsplit_k, s);
-        else gemm_f64<kTileK, false>(g, L.nsplit_k, s);
+        const int64_t ksplit = (int64_t)align_up((size_t)((kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
+        launch_syrk_f64(lower, static_cast<const double *>(X), static_cast<const double *>(Bop), nao, kdim, ksplit,
+                        L.nsplit_k, L.ktile, part, s);
     } else if (L.precision == DFJK_MIXED_INT8) {
         launch_gemm_i8(lower, X, static_cast<const double *>(Xlo), Bop, static_cast<const double *>(Bop_lo), nao,
                        kdim, L.nsplit_k, part, s);

@@ -1,0 +1,211 @@
+// FP64 K contraction with operands moved by LDS DMA: the split-K partial
+// tiles of C = A B^T (A, B: rows of the half-transformed tensor, k
+// contiguous), lower tiles only for K = X X^T or every tile for the
+// increment's X1 X2^T.  Same partial layout and the same order of the FP64
+// MFMA accumulation per element as the register-staged tile GEMM
+// (gemm_f64.h): chunks of 16 k in ascending order, four k per MFMA step.
+//
+// Workgroup: one T x T tile of one k split, WGM x WGN waves (T = 128: 4 x 2
+// waves of 32 x 64; T = 64: 2 x 2 waves of 32 x 32), v_mfma_f64_16x16x4f64
+// (lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator r of lane l
+// is D[l/16 + 4r][l%16]).
+//
+// Operands go from global memory straight into LDS
+// (global_load_lds_dwordx4: 16 bytes per lane, the lanes of one instruction
+// filling 1 KB in lane order) through a ring of three chunk buffers, two
+// chunks in flight while the MFMAs use the third; one barrier per chunk.
+// One instruction brings 8 rows x 16 k of one operand; inside it lane l
+// holds row r = l/8 and k pair p = (l%8) xor (r%8), so the k pair of a row
+// is stored at slot p xor (r%8): the 64 lanes of a fragment read (16 rows x
+// 4 k) then fall on every 16-byte bank group twice, the minimum for 512
+// bytes.  Rows past M read row M-1; their products reach only outputs the
+// reduction drops.
+#include "dfjk_internal.h"
+
+namespace dfjk {
+
+namespace {
+
+constexpr int kSyrkKC = 16;          // k per chunk (three chunk buffers)
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct SyrkArgs {
+    const double *A, *B;             // [M][ld] rows, k contiguous
+    int64_t ld, M;
+    int64_t kdim, ksplit;            // ksplit: a multiple of kSyrkKC
+    int ntm;                         // tiles per side
+    int lower;                       // 1: tiles with tn <= tm (K = X X^T), else every tile
+    int nsplit;
+    double *partial;                 // [split][tile][T][T]
+};
+
+// s_waitcnt immediates (gfx9: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt
+// 11:8; a field at its maximum does not wait)
+template <int N> constexpr int wait_vm() { return (N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+template <int T, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(T == 128 ? 2 : 3)))
+void k_syrk_f64(SyrkArgs g)
+{
+    constexpr int NW = WGM * WGN;
+    constexpr int WTM = T / WGM, WTN = T / WGN, MB = WTM / 16, NB = WTN / 16;
+    constexpr int OPD = T * kSyrkKC;                 // doubles of one operand's chunk
+    constexpr int NI = 2 * T / 8;                    // DMA instructions per chunk (8 rows each)
+    constexpr int NIW = NI / NW;                     // per wave
+    static_assert(NIW * NW == NI && NIW <= 15, "DMA instructions must spread evenly over the waves");
+    __shared__ __attribute__((aligned(1024))) double s0[2 * OPD];
+    __shared__ __attribute__((aligned(1024))) double s1[2 * OPD];
+    __shared__ __attribute__((aligned(1024))) double s2[2 * OPD];
+
+    const int ntiles = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
+    // workgroup -> (split, tile), 1-D grid.  With a split count that is a
+    // multiple of the XCD count, XCD x (workgroups go round-robin over the
+    // XCDs) runs whole splits x, x + 8, ...: the tiles of one k range share
+    // their panels in one L2 instead of every L2 fetching every panel.
+    int tile, split;
+    if (g.nsplit % kXcds == 0) {
+        const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+        split = xcd + kXcds * (local / ntiles);
+        tile = local % ntiles;
+    } else {
+        split = blockIdx.x / ntiles;
+        tile = blockIdx.x % ntiles;
+    }
+    int tm, tn;
+    if (g.lower) {
+        int r = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+        while (r * (r + 1) / 2 > tile) --r;
+        while ((r + 1) * (r + 2) / 2 <= tile) ++r;
+        tm = r;
+        tn = tile - r * (r + 1) / 2;
+    } else {
+        tm = tile % g.ntm;
+        tn = tile / g.ntm;
+    }
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int64_t kb = (int64_t)split * g.ksplit;
+    const int64_t ke = min(kb + g.ksplit, g.kdim);
+    const int nch = (int)((ke - kb) / kSyrkKC);
+
+    // this lane's global offset (doubles, relative to the chunk's k0) for each
+    // DMA instruction of its wave
+    int64_t goff[NIW];
+#pragma unroll
+    for (int q = 0; q < NIW; ++q) {
+        const int ins = wave * NIW + q;
+        const bool isA = ins < NI / 2;
+        const int r = (ins % (NI / 2)) * 8 + lane / 8;
+        const int p = (lane % 8) ^ (r % 8);
+        const int64_t row = min((isA ? (int64_t)tm : (int64_t)tn) * T + r, g.M - 1);
+        goff[q] = row * g.ld + 2 * p;
+    }
+    auto dma = [&](int c, double *buf) {
+        const int64_t k0 = kb + (int64_t)min(c, nch - 1) * kSyrkKC;   // past the end: the last chunk again
+#pragma unroll
+        for (int q = 0; q < NIW; ++q) {
+            const int ins = wave * NIW + q;
+            const bool isA = ins < NI / 2;
+            const double *src = (isA ? g.A : g.B) + goff[q] + k0;
+            double *dst = buf + (isA ? 0 : OPD) + (ins % (NI / 2)) * 8 * kSyrkKC;
+            __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)dst, 16,
+                                             0, 0);
+        }
+    };
+
+    f64x4 acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    // fragment read offset of step ks: row (lane % 16) of the fragment, k
+    // 4 ks + lane / 16 -> pair 2 ks + lane / 32 (swizzled), parity (lane / 16) % 2
+    int roff[kSyrkKC / 4];
+#pragma unroll
+    for (int ks = 0; ks < kSyrkKC / 4; ++ks)
+        roff[ks] = (lane & 15) * kSyrkKC + (((2 * ks + (lane >> 5)) ^ (lane & 7)) << 1) + ((lane >> 4) & 1);
+
+    auto mfma = [&](const double *buf) {
+        const double *as = buf + wm * WTM * kSyrkKC;
+        const double *bs = buf + OPD + wn * WTN * kSyrkKC;
+#pragma unroll
+        for (int ks = 0; ks < kSyrkKC / 4; ++ks) {
+            double a[MB], b[NB];
+#pragma unroll
+            for (int i = 0; i < MB; ++i) a[i] = as[i * 16 * kSyrkKC + roff[ks]];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) b[j] = bs[j * 16 * kSyrkKC + roff[ks]];
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+    // chunk c: its DMA has landed for this wave once only the NIW loads of
+    // chunk c + 1 are outstanding; the barrier makes that true for every
+    // wave and tells that chunk c - 1's buffer is read; then the DMA of
+    // chunk c + 2 goes into that buffer and the MFMAs run on chunk c
+    auto step = [&](int c, const double *cur, double *nxt2) {
+        __builtin_amdgcn_s_waitcnt(wait_vm<NIW>());
+        __builtin_amdgcn_s_barrier();
+        dma(c + 2, nxt2);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma(cur);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    if (nch > 0) {
+        dma(0, s0);
+        dma(1, s1);
+        int c = 0;
+        for (; c + 3 <= nch; c += 3) {   // whole rounds of the three buffers
+            step(c, s0, s2);
+            step(c + 1, s1, s0);
+            step(c + 2, s2, s1);
+        }
+        if (c < nch) step(c, s0, s2);
+        if (c + 1 < nch) step(c + 1, s1, s0);
+        __builtin_amdgcn_s_waitcnt(wait_vm<0>());   // no DMA into LDS outlives the workgroup
+    }
+
+    double *dst = g.partial + ((int64_t)split * ntiles + tile) * (int64_t)(T * T);
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+                const int col = wn * WTN + j * 16 + (lane & 15);
+                dst[row * T + col] = acc[i][j][r];
+            }
+}
+
+}  // namespace
+
+// Split-K partial tiles of A B^T (A = B for the lower-tile syrk): M rows of
+// kdim, nsplit splits of ksplit (a multiple of 16), tiles of T (64 or 128).
+void launch_syrk_f64(bool lower, const double *A, const double *B, int64_t M, int64_t kdim, int64_t ksplit,
+                     int nsplit, int T, double *partial, hipStream_t s)
+{
+    SyrkArgs g{};
+    g.A = A; g.B = B; g.ld = kdim; g.M = M; g.kdim = kdim; g.ksplit = ksplit;
+    g.ntm = (int)((M + T - 1) / T);
+    g.lower = lower ? 1 : 0;
+    g.nsplit = nsplit;
+    g.partial = partial;
+    const int ntiles = lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
+    if (ntiles <= 0 || nsplit <= 0) return;
+    const unsigned nwg = (unsigned)(ntiles * nsplit);
+    if (T == 128)
+        hipLaunchKernelGGL((k_syrk_f64<128, 4, 2>), dim3(nwg), dim3(512), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_syrk_f64<64, 2, 2>), dim3(nwg), dim3(256), 0, s, g);
+}
+
+}  // namespace dfjk
