@@ -58,7 +58,7 @@ def committed_traffic(shape):
     launch shape (tile, split count) changed since those counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_gemm_f64_water32.md")
+    path = os.path.join(ROOT, "profiles", "k_syrk_f64_water32.md")
     src = os.path.join(ROOT, "paper_2404_09452_amd", "csrc", "syrk_f64.hip")
     try:
         text = open(path).read()
@@ -669,7 +669,7 @@ def main():
                 "bound": "mfma",
                 "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": committed_traffic(shape),
-                "traffic_source": "profiles/k_gemm_f64_water32.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, per launch)",
+                "traffic_source": "profiles/k_syrk_f64_water32.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, per launch)",
                 "flops_per_launch": k_flops / k_launches, "ms_per_launch": k_ms, "launches_per_build": k_launches}
     # the other steps of an FP64 build against their bounds (HIP-event stage times;
     # algorithmic bytes: J reads B twice, the half transform reads B twice and
