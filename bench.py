@@ -522,7 +522,7 @@ def main():
                     help="comma-separated water32 modes after fp64 (default: every mixed mode)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=16,
+    ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests per serving run (each load point and the closed loop)")
     ap.add_argument("--serve-max-waters", type=int, default=64)
     ap.add_argument("--no-large", action="store_true", help="skip the 128-water leg")
