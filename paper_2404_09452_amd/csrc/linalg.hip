@@ -159,27 +159,26 @@ __global__ void k_identity(double *A, int64_t npad)
     A[i] = (i % npad == i / npad) ? 1.0 : 0.0;
 }
 
-// X[i0 + r][c] <- (L_ii^{-1} X_i)[r][c] for c < ncols; one thread per column,
-// the column in registers.  Forward substitution in right-looking order: x_l
-// is final once divided by L_ll, and its column of L updates every later row
-// with independent FMAs.  L_ii sits transposed in LDS (row l holds column l,
-// 16-byte aligned rows), so each update reads two entries per broadcast read.
-__global__ __launch_bounds__(64) void k_trtri_diag(const double *L, double *X, int64_t ld, int64_t i0,
-                                                    int64_t ncols)
+// D_k = L_kk^{-1} for every 64x64 diagonal block k (one workgroup each, all
+// at once; they are independent): column c of D_k by forward substitution
+// of e_c, one thread per column, the column in registers.  Right-looking:
+// x_l is final once divided by L_ll, and its column of L updates every later
+// row with independent FMAs.  L_kk sits transposed in LDS (row l holds column
+// l, 16-byte aligned rows), so each update reads two entries per broadcast.
+__global__ __launch_bounds__(64) void k_trinv_blocks(const double *L, int64_t ld, double *D)
 {
     constexpr int LDT = NBK + 2;
     __shared__ __align__(16) double LT[NBK * LDT];
     const int tid = threadIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.x * NBK;
     for (int e = tid; e < NBK * NBK; e += NBK) {
         const int r = e / NBK, l = e % NBK;
-        LT[l * LDT + r] = L[(i0 + r) * ld + i0 + l];
+        LT[l * LDT + r] = L[(k0 + r) * ld + k0 + l];
     }
     __syncthreads();
-    const int64_t c = blockIdx.x * (int64_t)NBK + tid;
-    if (c >= ncols) return;
     double x[NBK];
 #pragma unroll
-    for (int r = 0; r < NBK; ++r) x[r] = X[(i0 + r) * ld + c];
+    for (int r = 0; r < NBK; ++r) x[r] = (r == tid) ? 1.0 : 0.0;
 #pragma unroll
     for (int l = 0; l < NBK; ++l) {
         const double *cl = LT + l * LDT;
@@ -196,21 +195,35 @@ __global__ __launch_bounds__(64) void k_trtri_diag(const double *L, double *X, i
             x[r + 1] = fma(-v.y, x[l], x[r + 1]);
         }
     }
+    double *Dk = D + (int64_t)blockIdx.x * NBK * NBK;
 #pragma unroll
-    for (int r = 0; r < NBK; ++r) X[(i0 + r) * ld + c] = x[r];
+    for (int r = 0; r < NBK; ++r) Dk[r * NBK + tid] = x[r];
 }
 
-void launch_trtri(const double *L, double *X, int64_t npad, hipStream_t s)
+// X = L^{-1} by blocked forward substitution on the identity: for block row
+// i, X_i[0:w] <- D_i X_i[0:w] (w = (i+1) 64; an MFMA GEMM with the diagonal
+// block's inverse, in place: each output tile reads only its own 64 x 64
+// block of X_i, wholly, before writing it), then X[rows below][0:w] -=
+// L[rows below][block i] X_i[0:w].  The inverses of all diagonal blocks come
+// first in one launch (Dinv: npad x 64 doubles).
+void launch_trtri(const double *L, double *X, double *Dinv, int64_t npad, hipStream_t s)
 {
     const int64_t tot = npad * npad;
     hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                        const_cast<double *>(L), npad);
     hipLaunchKernelGGL(k_identity, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, npad);
     const int64_t nb = npad / NBK;
+    hipLaunchKernelGGL(k_trinv_blocks, dim3((unsigned)nb), dim3(NBK), 0, s, L, npad, Dinv);
     for (int64_t i = 0; i < nb; ++i) {
         const int64_t i0 = i * NBK, w = i0 + NBK;
-        hipLaunchKernelGGL(k_trtri_diag, dim3((unsigned)((w + NBK - 1) / NBK)), dim3(NBK), 0, s, L, X, npad,
-                           i0, w);
+        GemmArgs d{};
+        d.A = Dinv + i * NBK * NBK; d.lda = NBK;
+        d.B = X + i0 * npad; d.ldb = npad;
+        d.C = X + i0 * npad; d.ldc = npad;
+        d.M = NBK; d.N = w;
+        d.k_begin = 0; d.k_end = NBK; d.ksplit = NBK;
+        d.alpha = 1.0; d.beta = 0.0;
+        gemm_f64<64, true>(d, 1, s);
         if (i + 1 == nb) break;
         // X[j rows > i][0:w] -= L[j rows][i cols] X[i rows][0:w]
         GemmArgs g{};
