@@ -283,7 +283,7 @@ void launch_direct_pairs(const DirectClassDev *cls, const ShellsDev &ao, hipStre
 
 // linalg.hip
 void launch_metric_pad(double *V, int64_t n, int64_t npad, hipStream_t s);
-void launch_cholesky(double *A, int64_t npad, int32_t *status, hipStream_t s);
+void launch_cholesky(double *A, int64_t npad, int32_t *status, double *Dinv, hipStream_t s);
 void launch_trtri(const double *L, double *Linv, double *Dinv, int64_t npad, hipStream_t s);
 void launch_whiten(const double *U, const double *Linv, double *B, int64_t nf_pad, int64_t npad,
                    hipStream_t s);

@@ -1,7 +1,8 @@
 // Dense FP64 linear algebra on the auxiliary metric, gfx950:
 //   - blocked right-looking Cholesky V = L L^T (64-wide panels; the diagonal
-//     block is factored in registers by one wave, the panel below it is
-//     solved row by row, the trailing matrix is updated on FP64 MFMA),
+//     block is factored in registers by one wave, which also inverts it; the
+//     panel below is multiplied by that inverse and the trailing matrix
+//     updated, both on FP64 MFMA),
 //   - L^{-1} by blocked forward substitution on the identity,
 //   - the whitening B = U L^{-T}-transposed product, i.e. B[f][P] =
 //     sum_{Q<=P} U[f][Q] Linv[P][Q], as one MFMA GEMM that stops each output
@@ -51,9 +52,11 @@ __device__ __forceinline__ double readlane_f64(double v, int src)
 // stored as zero.  A pivot <= 0 is recorded (smallest index wins) and
 // replaced by 1 so the remaining steps stay finite; the host reports the
 // recorded index.
-__global__ __launch_bounds__(64) void k_potrf_diag(double *A, int64_t ld, int64_t k0, int32_t *status)
+__global__ __launch_bounds__(64) void k_potrf_diag(double *A, int64_t ld, int64_t k0, int32_t *status, double *Dk)
 {
     __shared__ __align__(16) double col[2][NBK];
+    constexpr int LDT = NBK + 2;
+    __shared__ __align__(16) double LT[NBK * LDT];
     const int i = threadIdx.x;
     double *row = A + (k0 + i) * ld + k0;
     double r[NBK];
@@ -87,51 +90,56 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double *A, int64_t ld, int64_
     }
     if (i == 0 && bad != INT_MAX) atomicMin(status, bad);
 #pragma unroll
-    for (int c = 0; c < NBK; ++c) row[c] = (c <= i) ? r[c] : 0.0;
-}
-
-// Panel: rows i0.. of block column k0 get L_ik = A_ik L_kk^{-T}; one
-// workgroup per 64-row block, one thread per row (x L_kk^T = a, forward),
-// the row in registers and L_kk broadcast from LDS; four partial sums per
-// entry shorten the dependent chain.
-__global__ __launch_bounds__(64) void k_trsm_panel(double *A, int64_t ld, int64_t k0)
-{
-    __shared__ double Lk[NBK][NBK + 1];
-    const int tid = threadIdx.x;
-    const int64_t r0 = k0 + NBK * (1 + (int64_t)blockIdx.x);
-    for (int e = tid; e < NBK * NBK; e += NBK) Lk[e / NBK][e % NBK] = A[(k0 + e / NBK) * ld + k0 + e % NBK];
-    double *row = A + (r0 + tid) * ld + k0;
+    for (int c = 0; c < NBK; ++c) {
+        const double v = (c <= i) ? r[c] : 0.0;
+        row[c] = v;
+        LT[c * LDT + i] = v;          // L_kk transposed: row l holds column l
+    }
+    __syncthreads();
+    // Dk = L_kk^{-1}: column t by forward substitution of e_t (as k_trinv_blocks)
+    const int t = i;
     double x[NBK];
 #pragma unroll
-    for (int c = 0; c < NBK; ++c) x[c] = row[c];
-    __syncthreads();
+    for (int q = 0; q < NBK; ++q) x[q] = (q == t) ? 1.0 : 0.0;
 #pragma unroll
-    for (int j = 0; j < NBK; ++j) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-        for (int l = 0; l + 3 < j; l += 4) {
-            s0 += x[l] * Lk[j][l];
-            s1 += x[l + 1] * Lk[j][l + 1];
-            s2 += x[l + 2] * Lk[j][l + 2];
-            s3 += x[l + 3] * Lk[j][l + 3];
+    for (int l = 0; l < NBK; ++l) {
+        const double *cl = LT + l * LDT;
+        x[l] = x[l] / cl[l];
+        int q0 = l + 1;
+        if ((q0 & 1) && q0 < NBK) {
+            x[q0] = fma(-cl[q0], x[l], x[q0]);
+            ++q0;
         }
 #pragma unroll
-        for (int l = j & ~3; l < j; ++l) s0 += x[l] * Lk[j][l];
-        x[j] = (x[j] - ((s0 + s1) + (s2 + s3))) / Lk[j][j];
+        for (int q = q0; q < NBK; q += 2) {
+            const double2 v = *reinterpret_cast<const double2 *>(cl + q);
+            x[q] = fma(-v.x, x[l], x[q]);
+            x[q + 1] = fma(-v.y, x[l], x[q + 1]);
+        }
     }
 #pragma unroll
-    for (int c = 0; c < NBK; ++c) row[c] = x[c];
+    for (int q = 0; q < NBK; ++q) Dk[q * NBK + t] = x[q];
 }
 
-void launch_cholesky(double *A, int64_t npad, int32_t *status, hipStream_t s)
+void launch_cholesky(double *A, int64_t npad, int32_t *status, double *Dinv, hipStream_t s)
 {
     const int64_t nb = npad / NBK;
     for (int64_t k = 0; k < nb; ++k) {
         const int64_t k0 = k * NBK;
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NBK), 0, s, A, npad, k0, status);
+        double *Dk = Dinv + k * NBK * NBK;
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NBK), 0, s, A, npad, k0, status, Dk);
         const int64_t rest = nb - k - 1;
         if (rest == 0) break;
-        hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)rest), dim3(NBK), 0, s, A, npad, k0);
+        // panel: L21 = A21 L_kk^{-T} = A21 Dk^T on MFMA, in place (each output
+        // tile reads only its own 64 rows, wholly, before writing them)
+        GemmArgs pg{};
+        pg.A = A + (k0 + NBK) * npad + k0; pg.lda = npad;
+        pg.B = Dk; pg.ldb = NBK;
+        pg.C = A + (k0 + NBK) * npad + k0; pg.ldc = npad;
+        pg.M = rest * NBK; pg.N = NBK;
+        pg.k_begin = 0; pg.k_end = NBK; pg.ksplit = NBK;
+        pg.alpha = 1.0; pg.beta = 0.0;
+        gemm_f64<64, false>(pg, 1, s);
         // A22 -= L21 L21^T on the lower tiles of the trailing matrix
         GemmArgs g{};
         const int64_t t0 = k0 + NBK;
