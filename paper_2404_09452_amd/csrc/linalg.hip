@@ -247,15 +247,7 @@ void launch_trtri(const double *L, double *X, double *Dinv, int64_t npad, hipStr
 
 void launch_whiten(const double *U, const double *Linv, double *B, int64_t nf_pad, int64_t npad, hipStream_t s)
 {
-    GemmArgs g{};
-    g.A = U; g.lda = npad;
-    g.B = Linv; g.ldb = npad;
-    g.C = B; g.ldc = npad;
-    g.M = nf_pad; g.N = npad;
-    g.k_begin = 0; g.k_end = npad; g.ksplit = npad;
-    g.alpha = 1.0; g.beta = 0.0;
-    g.tri_k = 1;
-    gemm_f64<128, false>(g, 1, s);
+    launch_gemm_nt_tri(U, Linv, B, nf_pad, npad, npad, s);
 }
 
 }  // namespace dfjk

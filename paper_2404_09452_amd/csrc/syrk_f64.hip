@@ -31,13 +31,16 @@ constexpr int kSyrkKC = 16;          // k per chunk (three chunk buffers)
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct SyrkArgs {
-    const double *A, *B;             // [M][ld] rows, k contiguous
-    int64_t ld, M;
+    const double *A, *B;             // [M][ld], [N][ld] rows, k contiguous
+    int64_t ld, M, N;
     int64_t kdim, ksplit;            // ksplit: a multiple of kSyrkKC
-    int ntm;                         // tiles per side
+    int ntm, ntn;                    // tiles along M and N
     int lower;                       // 1: tiles with tn <= tm (K = X X^T), else every tile
+    int tri_k;                       // 1: B(n, k) = 0 for k > n, so a tile stops at its last column
     int nsplit;
-    double *partial;                 // [split][tile][T][T]
+    double *partial;                 // [split][tile][T][T], or
+    double *C;                       // C[m][n] (ldc) when partial is null
+    int64_t ldc;
 };
 
 // s_waitcnt immediates (gfx9: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt
@@ -59,7 +62,7 @@ void k_syrk_f64(SyrkArgs g)
     __shared__ __attribute__((aligned(1024))) double s1[2 * OPD];
     __shared__ __attribute__((aligned(1024))) double s2[2 * OPD];
 
-    const int ntiles = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
+    const int ntiles = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntn;
     // workgroup -> (split, tile), 1-D grid.  With a split count that is a
     // multiple of the XCD count, XCD x (workgroups go round-robin over the
     // XCDs) runs whole splits x, x + 8, ...: the tiles of one k range share
@@ -83,12 +86,14 @@ void k_syrk_f64(SyrkArgs g)
     } else {
         tm = tile % g.ntm;
         tn = tile / g.ntm;
+        if (g.tri_k) tn = g.ntn - 1 - tn;   // the longest k ranges first
     }
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WGN, wn = wave % WGN;
     const int64_t kb = (int64_t)split * g.ksplit;
-    const int64_t ke = min(kb + g.ksplit, g.kdim);
+    int64_t ke = min(kb + g.ksplit, g.kdim);
+    if (g.tri_k) ke = min(ke, (int64_t)(tn + 1) * T);
     const int nch = (int)((ke - kb) / kSyrkKC);
 
     // this lane's global offset (doubles, relative to the chunk's k0) for each
@@ -100,7 +105,7 @@ void k_syrk_f64(SyrkArgs g)
         const bool isA = ins < NI / 2;
         const int r = (ins % (NI / 2)) * 8 + lane / 8;
         const int p = (lane % 8) ^ (r % 8);
-        const int64_t row = min((isA ? (int64_t)tm : (int64_t)tn) * T + r, g.M - 1);
+        const int64_t row = isA ? min((int64_t)tm * T + r, g.M - 1) : min((int64_t)tn * T + r, g.N - 1);
         goff[q] = row * g.ld + 2 * p;
     }
     auto dma = [&](int c, double *buf) {
@@ -173,16 +178,29 @@ void k_syrk_f64(SyrkArgs g)
         __builtin_amdgcn_s_waitcnt(wait_vm<0>());   // no DMA into LDS outlives the workgroup
     }
 
-    double *dst = g.partial + ((int64_t)split * ntiles + tile) * (int64_t)(T * T);
+    if (g.partial) {
+        double *dst = g.partial + ((int64_t)split * ntiles + tile) * (int64_t)(T * T);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+                    const int col = wn * WTN + j * 16 + (lane & 15);
+                    dst[row * T + col] = acc[i][j][r];
+                }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = wm * WTM + i * 16 + (lane >> 4) + 4 * r;
-                const int col = wn * WTN + j * 16 + (lane & 15);
-                dst[row * T + col] = acc[i][j][r];
+                const int64_t m = (int64_t)tm * T + wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+                const int64_t n = (int64_t)tn * T + wn * WTN + j * 16 + (lane & 15);
+                if (m < g.M && n < g.N) g.C[m * g.ldc + n] = acc[i][j][r];
             }
 }
 
@@ -194,18 +212,35 @@ void launch_syrk_f64(bool lower, const double *A, const double *B, int64_t M, in
                      int nsplit, int T, double *partial, hipStream_t s)
 {
     SyrkArgs g{};
-    g.A = A; g.B = B; g.ld = kdim; g.M = M; g.kdim = kdim; g.ksplit = ksplit;
-    g.ntm = (int)((M + T - 1) / T);
+    g.A = A; g.B = B; g.ld = kdim; g.M = M; g.N = M; g.kdim = kdim; g.ksplit = ksplit;
+    g.ntm = g.ntn = (int)((M + T - 1) / T);
     g.lower = lower ? 1 : 0;
     g.nsplit = nsplit;
     g.partial = partial;
-    const int ntiles = lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
+    const int ntiles = lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntn;
     if (ntiles <= 0 || nsplit <= 0) return;
     const unsigned nwg = (unsigned)(ntiles * nsplit);
     if (T == 128)
         hipLaunchKernelGGL((k_syrk_f64<128, 4, 2>), dim3(nwg), dim3(512), 0, s, g);
     else
         hipLaunchKernelGGL((k_syrk_f64<64, 2, 2>), dim3(nwg), dim3(256), 0, s, g);
+}
+
+// C = A B^T with B lower triangular in (n, k) (B(n, k) = 0 for k > n), both
+// row-major over ld = k: the whitening B_fP = sum_{Q <= P} U_fQ Linv_PQ.  M
+// rows of A, N rows of B (a multiple of 128), 128-wide tiles, no split.
+void launch_gemm_nt_tri(const double *A, const double *B, double *C, int64_t M, int64_t N, int64_t ld,
+                        hipStream_t s)
+{
+    SyrkArgs g{};
+    g.A = A; g.B = B; g.ld = ld; g.M = M; g.N = N; g.kdim = ld; g.ksplit = ld;
+    g.ntm = (int)((M + 127) / 128);
+    g.ntn = (int)((N + 127) / 128);
+    g.lower = 0; g.tri_k = 1; g.nsplit = 1;
+    g.C = C; g.ldc = ld;
+    const int ntiles = g.ntm * g.ntn;
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL((k_syrk_f64<128, 4, 2>), dim3((unsigned)ntiles), dim3(512), 0, s, g);
 }
 
 }  // namespace dfjk
