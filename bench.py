@@ -370,6 +370,32 @@ def serving_bench(modes, nreq, nmax, seed=3, max_active=4, budget_frac=0.6, load
     return out
 
 
+def large_setup_bench(nsetup):
+    """`nsetup` setups of the 128-water cluster (the workload of large_bench):
+    wall time and stage times of each."""
+    import torch
+    import workload as W
+    from paper_2404_09452_amd.dfjk import Plan
+
+    z, x = W.water_cluster(128, 16.0, 4)
+    mol = W.make_molecule(z, x)
+    runs = []
+    for _ in range(nsetup):
+        plan = Plan.from_molecule(mol, schwarz_thresh=1e-10).profile(True)
+        plan.screen()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.setup()
+        torch.cuda.synchronize()
+        runs.append({"setup_s": round(time.perf_counter() - t0, 4),
+                     "setup_stage_ms": {k: round(v[0], 3) for k, v in plan.profile_read().items()
+                                        if k.startswith("setup.")}})
+        print("bench: water128 setup %.4f s" % runs[-1]["setup_s"], file=sys.stderr, flush=True)
+        del plan
+        torch.cuda.empty_cache()
+    return {"workload": "water128: 128-water cluster, 16 A box, 3840 AO / 11136 aux, Schwarz 1e-10", "runs": runs}
+
+
 def large_bench(nbuild=2):
     """The 128-water cluster (3,840 AO, 11,136 aux, nocc 640, 16 A box, geometry
     seed 4, Schwarz 1e-10): one setup, then `nbuild` builds per precision with
@@ -536,6 +562,9 @@ def main():
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 128-water leg and print its JSON (for profiling)")
     ap.add_argument("--large-builds", type=int, default=2)
+    ap.add_argument("--only-large-setup", type=int, default=0, metavar="N",
+                    help="run only N setups of the 128-water cluster and print their stage times (for profiling "
+                         "the integral kernels)")
     ap.add_argument("--no-direct", action="store_true", help="skip the four-centre direct J/K leg")
     ap.add_argument("--only-direct", action="store_true",
                     help="run only the four-centre direct J/K leg on the 32-water cluster and print its JSON")
@@ -570,6 +599,9 @@ def main():
     if args.serve_profile:
         print(json.dumps({"serving_profile": serving_bench(args.serve_modes.split(","), args.serve_requests, 64,
                                                            loads=())}))
+        return
+    if args.only_large_setup:
+        print(json.dumps({"water128_setup": large_setup_bench(args.only_large_setup)}))
         return
     if args.only_large:
         print(json.dumps({"water128": large_bench(args.large_builds)}))

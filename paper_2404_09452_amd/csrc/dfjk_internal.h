@@ -233,6 +233,7 @@ struct Plan {
         const double *boys;
         double *U, *B, *V, *L, *Linv;
         double *Dinv;                   // inverses of the 64x64 diagonal blocks of L (setup)
+        double *pair_rec;               // per shell pair: P, p and the spherical Hermite bra (setup)
         int32_t *status;
     } d{};
 };
@@ -273,6 +274,17 @@ void launch_boys_eval(int mmax, int64_t n, const double *T, double *F, const dou
                       hipStream_t s);
 void launch_schwarz_pairs(int64_t npair, const ShellsDev &ao, double *q, hipStream_t s);
 void launch_schwarz_aux(int32_t nsh, const ShellsDev &ax, double *q, hipStream_t s);
+// Doubles of one shell pair's record for the three-centre kernel: a header of
+// 8 (p, P, Schwarz factor) and the bra coefficients [nherm(la+lb)][(2la+1)(2lb+1)],
+// rounded up to whole 64-byte lines.
+constexpr int pair_rec_doubles(int la, int lb)
+{
+    return (8 + (la + lb + 1) * (la + lb + 2) * (la + lb + 3) / 6 * (2 * la + 1) * (2 * lb + 1) + 7) / 8 * 8;
+}
+constexpr int kPairClassLa[6] = {0, 1, 1, 2, 2, 2}, kPairClassLb[6] = {0, 0, 1, 0, 1, 2};
+// offset (doubles) of each pair class's records, and the total
+void pair_rec_offsets(const Plan &p, int64_t off[7]);
+void launch_pair_records(const Plan &p, hipStream_t s);
 void launch_int3c(const Plan &p, hipStream_t s);
 void launch_int3c_rows(const Plan &p, double *U, int64_t f_base, int32_t i0, int32_t i1, hipStream_t s);
 void launch_int2c(const Plan &p, hipStream_t s);
@@ -369,6 +381,7 @@ void launch_align(const double *C, const double *C0, int64_t nao, int32_t nocc, 
 
 // export.hip
 void launch_zero(double *p, int64_t n, hipStream_t s);
+void launch_zero_rect(double *p, int64_t ld, int64_t r0, int64_t r1, int64_t c0, int64_t c1, hipStream_t s);
 void launch_fmap(const Plan &p, hipStream_t s);   // the sampling diagnostic's pair map, from the stored rows
 void launch_export(const Plan &p, int kind, double *out, hipStream_t s);
 void launch_sample(const Plan &p, int kind, int64_t n, const int32_t *idx, double *out,

@@ -14,6 +14,20 @@ void launch_zero(double *p, int64_t n, hipStream_t s)
     if (n > 0) hipLaunchKernelGGL(k_fill_export, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
 }
 
+__global__ void k_zero_rect(double *p, int64_t ld, int64_t r0, int64_t c0, int64_t nc, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[(r0 + i / nc) * ld + c0 + i % nc] = 0.0;
+}
+
+// zero rows r0..r1, columns c0..c1 of a row-major matrix with leading dimension ld
+void launch_zero_rect(double *p, int64_t ld, int64_t r0, int64_t r1, int64_t c0, int64_t c1, hipStream_t s)
+{
+    const int64_t n = (r1 - r0) * (c1 - c0);
+    if (r1 > r0 && c1 > c0)
+        hipLaunchKernelGGL(k_zero_rect, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, ld, r0, c0, c1 - c0, n);
+}
+
 // out[Pc][mu][nu] = T[f][P] (and [Pc][nu][mu] for off-diagonal blocks)
 __global__ void k_export_3c(const double *__restrict__ T, int64_t ld, const int32_t *__restrict__ fmu,
                             const int32_t *__restrict__ fnu, const double *__restrict__ fw,

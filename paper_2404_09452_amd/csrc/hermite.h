@@ -72,16 +72,19 @@ __device__ __forceinline__ void boys(double T, double (&F)[M + 1], const double 
 // R^n_{000} = (-2 alpha)^n F_n, and R^n_{tuv} from R^{n+1} by
 // R_{t+1,u,v} = t R_{t-1,u,v} + X R_{t,u,v} (same in u with Y, v with Z).
 // Orders are overwritten from the highest down, so the lower orders still
-// hold level n+1 when they are read.
-template <int L>
+// hold level n+1 when they are read.  With S > 0 the table starts from level
+// S instead of 0 and is divided by (-2 alpha)^S: the derivatives of
+// F_S(alpha r^2) rather than of F_0 (F holds at least S + L + 1 values).
+template <int L, int S = 0, int NF>
 __device__ __forceinline__ void hermite_R(double alpha, double X, double Y, double Z,
-                                          const double (&F)[L + 1], double (&R)[nherm(L)])
+                                          const double (&F)[NF], double (&R)[nherm(L)])
 {
+    static_assert(NF >= S + L + 1, "Boys values missing");
     double H[L + 1];
     double pw = 1.0;
     const double m2a = -2.0 * alpha;
 #pragma unroll
-    for (int n = 0; n <= L; ++n) { H[n] = pw * F[n]; pw *= m2a; }
+    for (int n = 0; n <= L; ++n) { H[n] = pw * F[S + n]; pw *= m2a; }
     R[0] = H[L];
 #pragma unroll
     for (int n = L - 1; n >= 0; --n) {

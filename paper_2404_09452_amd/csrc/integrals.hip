@@ -263,6 +263,26 @@ void launch_schwarz_aux(int32_t nsh, const ShellsDev &ax, double *q, hipStream_t
 
 // --------------------------------------------------------------------------
 // Three-centre integrals.
+//
+// Work split.  Everything that depends only on the shell pair (a, b) is formed
+// once per pair by k_pair_rec: the Gaussian product p, P and the spherical bra
+// Hermite coefficients
+//   Eh[tuv][ab] = 2 pi^{5/2} N_a N_b / p * t! u! v! * sum_{ca,cb} s_a s_b E^x E^y E^z.
+// k_int3c then gives each lane one output column, an (aux shell c, m_c)
+// combination: floor(64 / (2 lc + 1)) aux shells per wave, all m_c of a shell in
+// adjacent lanes, so a row (a function pair) is stored as one contiguous run.
+// The pair record is the same for the whole wave and is read through scalar
+// loads, so the bra contraction takes its coefficient as a scalar operand.
+//
+// Ket by Hobson's theorem applied a second time.  With G = F_lc(alpha r^2),
+//   sum_k s_m(k) R_{tuv+k} = d^{tuv}[S_m(X, Y, Z) (-2 alpha)^lc G],
+// the derivative of a harmonic polynomial times a radial function (S_m(grad)
+// of a function of r^2 is S_m(r) (2 d/dr^2)^lc of it).  By Leibniz, with
+// Taylor-scaled factors D[d] = d^d S_m / d! and G'[tuv] = d^{tuv} G / tuv!,
+//   W'[tuv] = sum_{d <= tuv, |d| <= lc} D[d] G'[tuv - d]   (= W[tuv] / tuv!),
+// so a lane holds the Hermite table only up to the bra order la + lb instead of
+// la + lb + lc, and (ab|c m) = N_c (alpha/g)^lc / (g sqrt(p+g)) sum_tuv Eh[tuv][ab] W'[tuv]
+// (the ket factor (-1/(2g))^lc times (-2 alpha)^lc).
 
 struct Int3cArgs {
     const int32_t *pa, *pb, *pf0;
@@ -271,37 +291,61 @@ struct Int3cArgs {
     ShellsDev ao, ax;
     const double *boys;
     double tau;
+    const double *rec;        // record of pair rec_first of this class
+    int32_t rec_first;
     double *U;                // rows f - f_base (a block of function-pair rows)
     int64_t ld;
     int64_t f_base;
 };
 
-template <int LA, int LB, int LC>
-__global__ __launch_bounds__(128) void k_int3c(Int3cArgs g)
-{
-    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1;
-    constexpr int CA = ncart(LA), CB = ncart(LB), CC = ncart(LC);
-    constexpr int LAB = LA + LB, L = LAB + LC;
-    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int npc = g.c_end - g.c_begin;
-    const int64_t total = (int64_t)(g.p_end - g.p_begin) * npc;
-    if (tid >= total) return;
-    const int ip = g.p_begin + (int)(tid / npc);
-    const int ic = g.c_begin + (int)(tid % npc);
-    const int a = g.pa[ip], b = g.pb[ip];
-    double *out = g.U + ((int64_t)g.pf0[ip] - g.f_base) * g.ld + g.ax.off[ic];
+constexpr double kFact[5] = {1.0, 1.0, 2.0, 6.0, 24.0};
+constexpr double kInvFact[5] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0};
 
-    if (g.pq[ip] * g.ax.q[ic] < g.tau) {
-#pragma unroll
-        for (int i = 0; i < NA * NB; ++i)
-#pragma unroll
-            for (int m = 0; m < NC; ++m) out[i * g.ld + m] = 0.0;
-        return;
-    }
-    const double ea = g.ao.exp[a], eb = g.ao.exp[b], gc = g.ax.exp[ic];
+// Terms of D[d] = sum_{|k| = l, k >= d} s(k) C(kx,dx) C(ky,dy) C(kz,dz) X^{kx-dx} Y^{ky-dy} Z^{kz-dz}:
+// Hermite index of d, Cartesian index of k, monomial index of k - d, binomial factor.
+template <int LC>
+struct KetTerms {
+    int n;
+    int d[64], k[64], m[64];
+    double c[64];
+};
+template <int LC>
+constexpr KetTerms<LC> ket_terms()
+{
+    KetTerms<LC> t{};
+    constexpr double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+    int k = 0;
+    for (int kx = LC; kx >= 0; --kx)
+        for (int ky = LC - kx; ky >= 0; --ky, ++k) {
+            const int kz = LC - kx - ky;
+            for (int dx = 0; dx <= kx; ++dx)
+                for (int dy = 0; dy <= ky; ++dy)
+                    for (int dz = 0; dz <= kz; ++dz) {
+                        t.d[t.n] = hidx(dx, dy, dz);
+                        t.k[t.n] = k;
+                        t.m[t.n] = hidx(kx - dx, ky - dy, kz - dz);
+                        t.c[t.n] = binom[kx][dx] * binom[ky][dy] * binom[kz][dz];
+                        ++t.n;
+                    }
+        }
+    return t;
+}
+
+// One thread per (pair, ma, mb) of the class's pairs p_begin..p_end (records
+// from rec, in pair order).
+template <int LA, int LB>
+__global__ __launch_bounds__(256) void k_pair_rec(Int3cArgs g, double *__restrict__ rec)
+{
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NAB = NA * NB, LAB = LA + LB;
+    constexpr int RS = pair_rec_doubles(LA, LB);
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)(g.p_end - g.p_begin) * NAB) return;
+    const int pl = (int)(tid / NAB), ab = (int)(tid % NAB);
+    const int ip = g.p_begin + pl;
+    const int a = g.pa[ip], b = g.pb[ip];
+    const double ea = g.ao.exp[a], eb = g.ao.exp[b];
     const double Ax = g.ao.x[a], Ay = g.ao.y[a], Az = g.ao.z[a];
     const double Bx = g.ao.x[b], By = g.ao.y[b], Bz = g.ao.z[b];
-    const double Cx = g.ax.x[ic], Cy = g.ax.y[ic], Cz = g.ax.z[ic];
     const double p = ea + eb, ipp = 1.0 / p;
     const double Px = (ea * Ax + eb * Bx) * ipp, Py = (ea * Ay + eb * By) * ipp, Pz = (ea * Az + eb * Bz) * ipp;
     const double mu = ea * eb * ipp;
@@ -309,24 +353,85 @@ __global__ __launch_bounds__(128) void k_int3c(Int3cArgs g)
     hermite_E<LA, LB>(Px - Ax, Px - Bx, 0.5 * ipp, exp(-mu * (Ax - Bx) * (Ax - Bx)), Ex);
     hermite_E<LA, LB>(Py - Ay, Py - By, 0.5 * ipp, exp(-mu * (Ay - By) * (Ay - By)), Ey);
     hermite_E<LA, LB>(Pz - Az, Pz - Bz, 0.5 * ipp, exp(-mu * (Az - Bz) * (Az - Bz)), Ez);
-
-    const double pg = p + gc;
-    const double alpha = p * gc / pg;
-    const double X = Px - Cx, Y = Py - Cy, Z = Pz - Cz;
-    double F[L + 1];
-    boys<L>(alpha * (X * X + Y * Y + Z * Z), F, g.boys);
-    double R[nherm(L)];
-    hermite_R<L>(alpha, X, Y, Z, F, R);
-
-    double ket = 1.0;
+    double Es[nherm(LAB)];
+    bra_sph<LA, LB>(ab / NB, ab % NB, Ex, Ey, Ez, Es);
+    double *r = rec + (int64_t)pl * RS;
+    if (ab == 0) {
+        r[0] = p; r[1] = Px; r[2] = Py; r[3] = Pz; r[4] = g.pq[ip]; r[5] = 0.0; r[6] = 0.0; r[7] = 0.0;
+    }
+    const double pref = kTwoPi52 * ipp * g.ao.norm[a] * g.ao.norm[b];
 #pragma unroll
-    for (int k = 0; k < LC; ++k) ket *= -0.5 / gc;    // (-1)^l (2g)^{-l}
-    const double pref = kTwoPi52 / (p * gc * sqrt(pg)) * ket * g.ao.norm[a] * g.ao.norm[b] * g.ax.norm[ic];
-
+    for (int t = 0; t <= LAB; ++t)
 #pragma unroll
-    for (int mc = 0; mc < NC; ++mc) {
-        // ket-contracted Hermite integrals W[tuv] = sum_k s_lm(k) R[tuv + k]
-        double W[nherm(LAB)];
+        for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+            for (int v = 0; v + u + t <= LAB; ++v)
+                r[8 + hidx(t, u, v) * NAB + ab] = pref * (kFact[t] * kFact[u] * kFact[v]) * Es[hidx(t, u, v)];
+}
+
+template <int LA, int LB, int LC>
+__global__ __launch_bounds__(256) void k_int3c(Int3cArgs g)
+{
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1, NAB = NA * NB;
+    constexpr int CC = ncart(LC), LAB = LA + LB, L = LAB + LC;
+    constexpr int SPW = 64 / NC, SPB = 4 * SPW;   // aux shells per wave, per workgroup
+    constexpr int RS = pair_rec_doubles(LA, LB);
+    const int nsc = g.c_end - g.c_begin;
+    const int ngrp = (nsc + SPB - 1) / SPB;
+    const int pl = (int)(blockIdx.x / ngrp), grp = (int)(blockIdx.x % ngrp);
+    const int ip = g.p_begin + pl;
+    const double *__restrict__ rec = g.rec + (int64_t)(ip - g.rec_first) * RS;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sl = lane / NC, mc = lane - sl * NC;
+    const int cl = grp * SPB + wave * SPW + sl;
+    if (sl >= SPW || cl >= nsc) return;
+    const int ic = g.c_begin + cl;
+    double acc[NAB];
+#pragma unroll
+    for (int i = 0; i < NAB; ++i) acc[i] = 0.0;
+
+    const double p = rec[0];
+    if (rec[4] * g.ax.q[ic] >= g.tau) {
+        const double gc = g.ax.exp[ic];
+        const double X = rec[1] - g.ax.x[ic], Y = rec[2] - g.ax.y[ic], Z = rec[3] - g.ax.z[ic];
+        const double pg = p + gc, ipg = 1.0 / pg;
+        const double alpha = p * gc * ipg;
+        double F[L + 1];
+        boys<L>(alpha * (X * X + Y * Y + Z * Z), F, g.boys);
+        // G'[tuv] = d^{tuv} F_lc(alpha r^2) / (t! u! v!)
+        double G[nherm(LAB)];
+        hermite_R<LAB, LC>(alpha, X, Y, Z, F, G);
+#pragma unroll
+        for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+            for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+                for (int v = 0; v + u + t <= LAB; ++v)
+                    G[hidx(t, u, v)] *= kInvFact[t] * kInvFact[u] * kInvFact[v];
+        // D[d] = d^d S_mc(X, Y, Z) / d!  for |d| <= lc, from the monomials X^i Y^j Z^k
+        double D[nherm(LC)];
+        {
+            double px[LC + 1], py[LC + 1], pz[LC + 1];
+            px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+            for (int i = 1; i <= LC; ++i) { px[i] = px[i - 1] * X; py[i] = py[i - 1] * Y; pz[i] = pz[i - 1] * Z; }
+            double M[nherm(LC)];
+#pragma unroll
+            for (int i = 0; i <= LC; ++i)
+#pragma unroll
+                for (int j = 0; i + j <= LC; ++j)
+#pragma unroll
+                    for (int k = 0; i + j + k <= LC; ++k) M[hidx(i, j, k)] = px[i] * py[j] * pz[k];
+            double sv[CC];
+#pragma unroll
+            for (int k = 0; k < CC; ++k) sv[k] = c_sph[LC][mc][k];
+#pragma unroll
+            for (int i = 0; i < nherm(LC); ++i) D[i] = 0.0;
+            constexpr KetTerms<LC> kt = ket_terms<LC>();
+#pragma unroll
+            for (int i = 0; i < kt.n; ++i) D[kt.d[i]] += (kt.c[i] * sv[kt.k[i]]) * M[kt.m[i]];
+        }
+        // W'[tuv] and the bra contraction, one Hermite index at a time
 #pragma unroll
         for (int t = 0; t <= LAB; ++t)
 #pragma unroll
@@ -335,64 +440,44 @@ __global__ __launch_bounds__(128) void k_int3c(Int3cArgs g)
                 for (int v = 0; v + u + t <= LAB; ++v) {
                     double w = 0.0;
 #pragma unroll
-                    for (int k = 0; k < CC; ++k)
-                        w += c_sph[LC][mc][k] *
-                             R[hidx(t + cart_pow(LC, k, 0), u + cart_pow(LC, k, 1), v + cart_pow(LC, k, 2))];
-                    W[hidx(t, u, v)] = w;
+                    for (int dx = 0; dx <= t && dx <= LC; ++dx)
+#pragma unroll
+                        for (int dy = 0; dy <= u && dx + dy <= LC; ++dy)
+#pragma unroll
+                            for (int dz = 0; dz <= v && dx + dy + dz <= LC; ++dz)
+                                w += D[hidx(dx, dy, dz)] * G[hidx(t - dx, u - dy, v - dz)];
+                    const double *e = rec + 8 + hidx(t, u, v) * NAB;
+#pragma unroll
+                    for (int i = 0; i < NAB; ++i) acc[i] += e[i] * w;
                 }
-        // Cartesian bra
-        double cart[CA][CB];
+        double sc = g.ax.norm[ic] * sqrt(ipg) / gc;
 #pragma unroll
-        for (int ca = 0; ca < CA; ++ca)
+        for (int k = 0; k < LC; ++k) sc *= p * ipg;
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const int ax = cart_pow(LA, ca, 0), ay = cart_pow(LA, ca, 1), az = cart_pow(LA, ca, 2);
-                const int bx = cart_pow(LB, cb, 0), by = cart_pow(LB, cb, 1), bz = cart_pow(LB, cb, 2);
-                double s = 0.0;
-#pragma unroll
-                for (int t = 0; t <= ax + bx; ++t) {
-                    double su = 0.0;
-#pragma unroll
-                    for (int u = 0; u <= ay + by; ++u) {
-                        double sv = 0.0;
-#pragma unroll
-                        for (int v = 0; v <= az + bz; ++v) sv += Ez[az][bz][v] * W[hidx(t, u, v)];
-                        su += Ey[ay][by][u] * sv;
-                    }
-                    s += Ex[ax][bx][t] * su;
-                }
-                cart[ca][cb] = s;
-            }
-        // spherical bra, two one-index transforms
-        double half[NA][CB];
-#pragma unroll
-        for (int ma = 0; ma < NA; ++ma)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                double s = 0.0;
-#pragma unroll
-                for (int ca = 0; ca < CA; ++ca) s += c_sph[LA][ma][ca] * cart[ca][cb];
-                half[ma][cb] = s;
-            }
-#pragma unroll
-        for (int ma = 0; ma < NA; ++ma)
-#pragma unroll
-            for (int mb = 0; mb < NB; ++mb) {
-                double s = 0.0;
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) s += c_sph[LB][mb][cb] * half[ma][cb];
-                out[(ma * NB + mb) * g.ld + mc] = pref * s;
-            }
+        for (int i = 0; i < NAB; ++i) acc[i] *= sc;
     }
+    double *out = g.U + ((int64_t)g.pf0[ip] - g.f_base) * g.ld + g.ax.off[ic] + mc;
+#pragma unroll
+    for (int i = 0; i < NAB; ++i) out[i * g.ld] = acc[i];
+}
+
+template <int LA, int LB>
+static void launch_pair_class(Int3cArgs g, double *rec, hipStream_t s)
+{
+    constexpr int NAB = (2 * LA + 1) * (2 * LB + 1);
+    const int64_t n = (int64_t)(g.p_end - g.p_begin) * NAB;
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_pair_rec<LA, LB>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, rec);
 }
 
 template <int LA, int LB, int LC>
 static void launch_class(Int3cArgs g, hipStream_t s)
 {
-    const int64_t total = (int64_t)(g.p_end - g.p_begin) * (g.c_end - g.c_begin);
-    if (total <= 0) return;
-    const int bs = 128;
-    hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, g);
+    constexpr int SPB = 4 * (64 / (2 * LC + 1));
+    const int64_t npl = g.p_end - g.p_begin, nsc = g.c_end - g.c_begin;
+    if (npl <= 0 || nsc <= 0) return;
+    const int64_t nblk = npl * ((nsc + SPB - 1) / SPB);
+    hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)nblk), dim3(256), 0, s, g);
 }
 
 static ShellsDev ao_view(const Plan &p)
@@ -404,26 +489,65 @@ static ShellsDev ax_view(const Plan &p)
     return ShellsDev{p.d.ax_exp, p.d.ax_x, p.d.ax_y, p.d.ax_z, p.d.ax_norm, p.d.ax_q, p.d.ax_l, p.d.ax_off};
 }
 
+void pair_rec_offsets(const Plan &p, int64_t off[7])
+{
+    off[0] = 0;
+    for (int pc = 0; pc < 6; ++pc)
+        off[pc + 1] = off[pc] + (int64_t)(p.sp_class[pc].end - p.sp_class[pc].begin) *
+                                    pair_rec_doubles(kPairClassLa[pc], kPairClassLb[pc]);
+}
+
+static Int3cArgs int3c_args(const Plan &p)
+{
+    Int3cArgs g{};
+    g.pa = p.d.sp_a; g.pb = p.d.sp_b; g.pf0 = p.d.sp_f0; g.pq = p.d.sp_q;
+    g.ao = ao_view(p); g.ax = ax_view(p);
+    g.boys = p.d.boys; g.tau = p.thresh; g.ld = p.naux_pad;
+    return g;
+}
+
+// Records of every kept pair into p.d.pair_rec (before any int3c launch).
+void launch_pair_records(const Plan &p, hipStream_t s)
+{
+    int64_t off[7];
+    pair_rec_offsets(p, off);
+    Int3cArgs g = int3c_args(p);
+    for (int pc = 0; pc < 6; ++pc) {
+        g.p_begin = p.sp_class[pc].begin; g.p_end = p.sp_class[pc].end;
+        double *rec = p.d.pair_rec + off[pc];
+        switch (pc) {
+        case 0: launch_pair_class<0, 0>(g, rec, s); break;
+        case 1: launch_pair_class<1, 0>(g, rec, s); break;
+        case 2: launch_pair_class<1, 1>(g, rec, s); break;
+        case 3: launch_pair_class<2, 0>(g, rec, s); break;
+        case 4: launch_pair_class<2, 1>(g, rec, s); break;
+        default: launch_pair_class<2, 2>(g, rec, s); break;
+        }
+    }
+}
+
 void launch_int3c(const Plan &p, hipStream_t s)
 {
     launch_int3c_rows(p, p.d.U, 0, 0, (int32_t)p.sp_a.size(), s);
 }
 
-// U rows of the kept pairs i0 <= i < i1, written at row f - f_base of U.
+// U rows of the kept pairs i0 <= i < i1, written at row f - f_base of U
+// (their pair records already formed by launch_pair_records).
 void launch_int3c_rows(const Plan &p, double *U, int64_t f_base, int32_t i0, int32_t i1, hipStream_t s)
 {
-    Int3cArgs g{};
-    g.pa = p.d.sp_a; g.pb = p.d.sp_b; g.pf0 = p.d.sp_f0; g.pq = p.d.sp_q;
-    g.ao = ao_view(p); g.ax = ax_view(p);
-    g.boys = p.d.boys; g.tau = p.thresh; g.U = U; g.ld = p.naux_pad; g.f_base = f_base;
-    static const int cls_la[6] = {0, 1, 1, 2, 2, 2}, cls_lb[6] = {0, 0, 1, 0, 1, 2};
+    int64_t off[7];
+    pair_rec_offsets(p, off);
+    Int3cArgs g = int3c_args(p);
+    g.U = U; g.f_base = f_base;
     for (int pc = 0; pc < 6; ++pc) {
         g.p_begin = std::max(p.sp_class[pc].begin, i0); g.p_end = std::min(p.sp_class[pc].end, i1);
         if (g.p_end <= g.p_begin) continue;
+        g.rec = p.d.pair_rec + off[pc];
+        g.rec_first = p.sp_class[pc].begin;
         for (int lc = 0; lc <= kMaxLAux; ++lc) {
             g.c_begin = p.ax_class[lc].begin; g.c_end = p.ax_class[lc].end;
             if (g.c_end <= g.c_begin) continue;
-            const int key = cls_la[pc] * 100 + cls_lb[pc] * 10 + lc;
+            const int key = kPairClassLa[pc] * 100 + kPairClassLb[pc] * 10 + lc;
 #define CLS(A, B, C) case A * 100 + B * 10 + C: launch_class<A, B, C>(g, s); break;
             switch (key) {
                 CLS(0, 0, 0) CLS(0, 0, 1) CLS(0, 0, 2) CLS(0, 0, 3)
