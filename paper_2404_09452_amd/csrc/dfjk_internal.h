@@ -272,7 +272,8 @@ void upload_boys_table(const double *host, size_t n, const double **dev_addr, hi
 // integrals.hip
 void launch_boys_eval(int mmax, int64_t n, const double *T, double *F, const double *tab,
                       hipStream_t s);
-void launch_schwarz_pairs(int64_t npair, const ShellsDev &ao, double *q, hipStream_t s);
+void launch_schwarz_pairs(int64_t npair, const ShellsDev &ao, const int32_t *dsh, int32_t nd, double *q,
+                          hipStream_t s);
 void launch_schwarz_aux(int32_t nsh, const ShellsDev &ax, double *q, hipStream_t s);
 // Doubles of one shell pair's record for the three-centre kernel: a header of
 // 8 (p, P, Schwarz factor) and the bra coefficients [nherm(la+lb)][(2la+1)(2lb+1)],

@@ -139,11 +139,56 @@ __device__ __forceinline__ void bra_sph(int ma, int mb, const double (&Ex)[LA + 
     }
 }
 
-template <int LA, int LB>
-__device__ double schwarz_pair(double ea, double eb, double ax_, double ay_, double az_, double bx_,
-                               double by_, double bz_, double na, double nb)
+// R_{tuv}(alpha, 0) / (-2 alpha)^{(t+u+v)/2} for even t, u, v (zero otherwise):
+// (t-1)!! (u-1)!! (v-1)!! / (t+u+v+1), a compile-time constant.
+constexpr double kDfactM1[9] = {1.0, 0.0, 1.0, 0.0, 3.0, 0.0, 15.0, 0.0, 105.0};   // (n-1)!!, even n
+constexpr double r_origin_coef(int t, int u, int v)
 {
-    constexpr int LAB = LA + LB, L = 2 * LAB;
+    return ((t | u | v) & 1) ? 0.0 : kDfactM1[t] * kDfactM1[u] * kDfactM1[v] / (t + u + v + 1);
+}
+
+// sqrt(|(ab|ab)|) of one function pair from its spherical bra Es: the bra
+// twice, the ket's Hermite signs (-1)^{t'+u'+v'} and R at coincident centres
+// (alpha = p/2).
+template <int LAB>
+__device__ __forceinline__ double schwarz_form(const double (&Es)[nherm(LAB)], double p, double na, double nb)
+{
+    double pw[LAB + 1];   // (-2 alpha)^s
+    pw[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= LAB; ++k) pw[k] = pw[k - 1] * (-p);
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+        for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+            for (int v = 0; v + u + t <= LAB; ++v) {
+                double inner = 0.0;
+#pragma unroll
+                for (int t2 = 0; t2 <= LAB; ++t2)
+#pragma unroll
+                    for (int u2 = 0; u2 + t2 <= LAB; ++u2)
+#pragma unroll
+                        for (int v2 = 0; v2 + u2 + t2 <= LAB; ++v2) {
+                            if (((t + t2) | (u + u2) | (v + v2)) & 1) continue;
+                            const double c = (((t2 + u2 + v2) & 1) ? -1.0 : 1.0) *
+                                             r_origin_coef(t + t2, u + u2, v + v2);
+                            inner += (c * pw[(t + t2 + u + u2 + v + v2) / 2]) * Es[hidx(t2, u2, v2)];
+                        }
+                s += Es[hidx(t, u, v)] * inner;
+            }
+    const double pref = kTwoPi52 / (p * p * sqrt(2.0 * p)) * (na * nb) * (na * nb);
+    return sqrt(fabs(s) * pref);
+}
+
+// Largest sqrt|(ab|ab)| over the function pairs of one shell pair (classes
+// below (d d)): the Hermite tables once, then each function pair's bra.
+template <int LA, int LB>
+__device__ double schwarz_pair_max(double ea, double eb, double ax_, double ay_, double az_, double bx_, double by_,
+                                   double bz_, double na, double nb)
+{
+    constexpr int LAB = LA + LB, NB = 2 * LB + 1;
     const double p = ea + eb, ip = 1.0 / p;
     const double Px = (ea * ax_ + eb * bx_) * ip, Py = (ea * ay_ + eb * by_) * ip,
                  Pz = (ea * az_ + eb * bz_) * ip;
@@ -152,40 +197,20 @@ __device__ double schwarz_pair(double ea, double eb, double ax_, double ay_, dou
     hermite_E<LA, LB>(Px - ax_, Px - bx_, 0.5 * ip, exp(-mu * (ax_ - bx_) * (ax_ - bx_)), Ex);
     hermite_E<LA, LB>(Py - ay_, Py - by_, 0.5 * ip, exp(-mu * (ay_ - by_) * (ay_ - by_)), Ey);
     hermite_E<LA, LB>(Pz - az_, Pz - bz_, 0.5 * ip, exp(-mu * (az_ - bz_) * (az_ - bz_)), Ez);
-    double R[nherm(L)];
-    hermite_R_origin<L>(0.5 * p, R);
-    const double pref = kTwoPi52 / (p * p * sqrt(2.0 * p)) * (na * nb) * (na * nb);
     double best = 0.0;
-    for (int ma = 0; ma < 2 * LA + 1; ++ma)
-        for (int mb = 0; mb < 2 * LB + 1; ++mb) {
-            double Es[nherm(LAB)];
-            bra_sph<LA, LB>(ma, mb, Ex, Ey, Ez, Es);
-            double s = 0.0;
-#pragma unroll
-            for (int t = 0; t <= LAB; ++t)
-#pragma unroll
-                for (int u = 0; u + t <= LAB; ++u)
-#pragma unroll
-                    for (int v = 0; v + u + t <= LAB; ++v) {
-                        double inner = 0.0;
-#pragma unroll
-                        for (int t2 = 0; t2 <= LAB; ++t2)
-#pragma unroll
-                            for (int u2 = 0; u2 + t2 <= LAB; ++u2)
-#pragma unroll
-                                for (int v2 = 0; v2 + u2 + t2 <= LAB; ++v2) {
-                                    if (((t + t2) | (u + u2) | (v + v2)) & 1) continue;
-                                    const double sg = ((t2 + u2 + v2) & 1) ? -1.0 : 1.0;
-                                    inner += sg * Es[hidx(t2, u2, v2)] * R[hidx(t + t2, u + u2, v + v2)];
-                                }
-                        s += Es[hidx(t, u, v)] * inner;
-                    }
-            best = fmax(best, fabs(s));
-        }
-    return sqrt(best * pref);
+#pragma unroll 1
+    for (int k = 0; k < (2 * LA + 1) * NB; ++k) {
+        double Es[nherm(LAB)];
+        bra_sph<LA, LB>(k / NB, k % NB, Ex, Ey, Ez, Es);
+        best = fmax(best, schwarz_form<LAB>(Es, p, na, nb));
+    }
+    return best;
 }
 
-__global__ void k_schwarz_pairs(int64_t npair, ShellsDev ao, double *__restrict__ q)
+// Schwarz factor of every shell pair a >= b other than (d d): the largest
+// (ab|ab) over its function pairs, one thread per pair; (d d) pairs get 0
+// here and their value from k_schwarz_dd.
+__global__ __launch_bounds__(256) void k_schwarz_pairs(int64_t npair, ShellsDev ao, double *__restrict__ q)
 {
     const int64_t ab = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (ab >= npair) return;
@@ -196,20 +221,92 @@ __global__ void k_schwarz_pairs(int64_t npair, ShellsDev ao, double *__restrict_
     if (ao.l[a] < ao.l[b]) { const int t = a; a = b; b = t; }
     const int la = ao.l[a], lb = ao.l[b];
     double r = 0.0;
-#define SCH(LA, LB)                                                                                  \
-    r = schwarz_pair<LA, LB>(ao.exp[a], ao.exp[b], ao.x[a], ao.y[a], ao.z[a], ao.x[b], ao.y[b], ao.z[b], \
-                             ao.norm[a], ao.norm[b]);
+#define SCH(LA, LB)                                                                                   \
+    r = schwarz_pair_max<LA, LB>(ao.exp[a], ao.exp[b], ao.x[a], ao.y[a], ao.z[a], ao.x[b], ao.y[b], \
+                                 ao.z[b], ao.norm[a], ao.norm[b]);
     if (la == 0) { SCH(0, 0) }
     else if (la == 1) { if (lb == 0) { SCH(1, 0) } else { SCH(1, 1) } }
-    else { if (lb == 0) { SCH(2, 0) } else if (lb == 1) { SCH(2, 1) } else { SCH(2, 2) } }
+    else if (lb == 0) { SCH(2, 0) }
+    else if (lb == 1) { SCH(2, 1) }
 #undef SCH
     q[ab] = r;
 }
 
-void launch_schwarz_pairs(int64_t npair, const ShellsDev &ao, double *q, hipStream_t s)
+// (d d) pairs: pair (i >= j) of the ascending d-shell list dsh, 32 lanes per
+// pair, lane k < 25 taking function pair k.  Lane 0 forms the three Hermite
+// tables into LDS, each lane builds its bra from them, and the largest value
+// is kept with an integer maximum on the bits (non-negative values order as
+// their bit patterns do) in q, which k_schwarz_pairs has set to 0.
+__global__ __launch_bounds__(256) void k_schwarz_dd(int64_t ndd, const int32_t *__restrict__ dsh, ShellsDev ao,
+                                                    double *__restrict__ q)
 {
-    const int bs = 128;
-    hipLaunchKernelGGL(k_schwarz_pairs, dim3((unsigned)((npair + bs - 1) / bs)), dim3(bs), 0, s, npair, ao, q);
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t ij = gid >> 5;
+    const int k = (int)(gid & 31);
+    if (ij >= ndd || k >= 25) return;
+    int i = (int)((sqrt(8.0 * (double)ij + 1.0) - 1.0) * 0.5);
+    while ((int64_t)i * (i + 1) / 2 > ij) --i;
+    while ((int64_t)(i + 1) * (i + 2) / 2 <= ij) ++i;
+    const int j = (int)(ij - (int64_t)i * (i + 1) / 2);
+    const int a = dsh[i], b = dsh[j];
+    __shared__ double tab[8][3][3][3][5];
+    double (&T)[3][3][3][5] = tab[threadIdx.x >> 5];
+    const double ea = ao.exp[a], eb = ao.exp[b];
+    const double p = ea + eb, ip = 1.0 / p;
+    if (k == 0) {
+        const double A[3] = {ao.x[a], ao.y[a], ao.z[a]}, B[3] = {ao.x[b], ao.y[b], ao.z[b]};
+        const double mu = ea * eb * ip;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double P = (ea * A[d] + eb * B[d]) * ip;
+            double E[3][3][5];
+            hermite_E<2, 2>(P - A[d], P - B[d], 0.5 * ip, exp(-mu * (A[d] - B[d]) * (A[d] - B[d])), E);
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                for (int y = 0; y < 3; ++y)
+#pragma unroll
+                    for (int t = 0; t <= x + y; ++t) T[d][x][y][t] = E[x][y][t];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int ma = k / 5, mb = k % 5;
+    double Es[nherm(4)];
+#pragma unroll
+    for (int h = 0; h < nherm(4); ++h) Es[h] = 0.0;
+#pragma unroll
+    for (int ca = 0; ca < 6; ++ca) {
+        const double sa = c_sph[2][ma][ca];
+#pragma unroll
+        for (int cb = 0; cb < 6; ++cb) {
+            const double sab = sa * c_sph[2][mb][cb];
+            const int ax = cart_pow(2, ca, 0), ay = cart_pow(2, ca, 1), az = cart_pow(2, ca, 2);
+            const int bx = cart_pow(2, cb, 0), by = cart_pow(2, cb, 1), bz = cart_pow(2, cb, 2);
+#pragma unroll
+            for (int t = 0; t <= ax + bx; ++t)
+#pragma unroll
+                for (int u = 0; u <= ay + by; ++u) {
+                    const double xy = sab * T[0][ax][bx][t] * T[1][ay][by][u];
+#pragma unroll
+                    for (int v = 0; v <= az + bz; ++v) Es[hidx(t, u, v)] += xy * T[2][az][bz][v];
+                }
+        }
+    }
+    const double r = schwarz_form<4>(Es, p, ao.norm[a], ao.norm[b]);
+    const int64_t ab = (int64_t)a * (a + 1) / 2 + b;
+    atomicMax(reinterpret_cast<unsigned long long *>(q) + ab, (unsigned long long)__double_as_longlong(r));
+}
+
+// dsh: the nd d shells in ascending order (device memory)
+void launch_schwarz_pairs(int64_t npair, const ShellsDev &ao, const int32_t *dsh, int32_t nd, double *q,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_schwarz_pairs, dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, s, npair, ao, q);
+    const int64_t ndd = (int64_t)nd * (nd + 1) / 2;
+    if (ndd > 0)
+        hipLaunchKernelGGL(k_schwarz_dd, dim3((unsigned)((ndd * 32 + 255) / 256)), dim3(256), 0, s, ndd, dsh, ao, q);
 }
 
 // (c|c) of one solid-harmonic Gaussian, largest over m (all equal in exact
@@ -369,11 +466,85 @@ __global__ __launch_bounds__(256) void k_pair_rec(Int3cArgs g, double *__restric
                 r[8 + hidx(t, u, v) * NAB + ab] = pref * (kFact[t] * kFact[u] * kFact[v]) * Es[hidx(t, u, v)];
 }
 
+// Shared pieces of both lane layouts: the Taylor-scaled Hermite table G' of
+// F_lc(alpha r^2) to the bra order, the monomials of (X, Y, Z) to order lc,
+// the ket factor D of one m_c, and the bra contraction.
+template <int LAB, int LC>
+__device__ __forceinline__ void ket_table(double p, double X, double Y, double Z, double gc, const double *boys_tab,
+                                          double (&G)[nherm(LAB)], double (&M)[nherm(LC)], double &scale)
+{
+    constexpr int L = LAB + LC;
+    const double pg = p + gc, ipg = 1.0 / pg;
+    const double alpha = p * gc * ipg;
+    double F[L + 1];
+    boys<L>(alpha * (X * X + Y * Y + Z * Z), F, boys_tab);
+    hermite_R<LAB, LC>(alpha, X, Y, Z, F, G);
+#pragma unroll
+    for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+        for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+            for (int v = 0; v + u + t <= LAB; ++v) G[hidx(t, u, v)] *= kInvFact[t] * kInvFact[u] * kInvFact[v];
+    double px[LC + 1], py[LC + 1], pz[LC + 1];
+    px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+    for (int i = 1; i <= LC; ++i) { px[i] = px[i - 1] * X; py[i] = py[i - 1] * Y; pz[i] = pz[i - 1] * Z; }
+#pragma unroll
+    for (int i = 0; i <= LC; ++i)
+#pragma unroll
+        for (int j = 0; i + j <= LC; ++j)
+#pragma unroll
+            for (int k = 0; i + j + k <= LC; ++k) M[hidx(i, j, k)] = px[i] * py[j] * pz[k];
+    // (alpha/g)^lc / (g sqrt(p+g)); the caller multiplies in N_c
+    scale = sqrt(ipg) / gc;
+#pragma unroll
+    for (int k = 0; k < LC; ++k) scale *= p * ipg;
+}
+
+template <int LC>
+__device__ __forceinline__ void ket_factor(const double (&sv)[ncart(LC)], const double (&M)[nherm(LC)],
+                                           double (&D)[nherm(LC)])
+{
+#pragma unroll
+    for (int i = 0; i < nherm(LC); ++i) D[i] = 0.0;
+    constexpr KetTerms<LC> kt = ket_terms<LC>();
+#pragma unroll
+    for (int i = 0; i < kt.n; ++i) D[kt.d[i]] += (kt.c[i] * sv[kt.k[i]]) * M[kt.m[i]];
+}
+
+// acc[ab] += sum_tuv e[tuv][ab] W'[tuv], W'[tuv] = sum_d D[d] G'[tuv - d]
+template <int LAB, int LC, int NAB>
+__device__ __forceinline__ void bra_contract(const double *__restrict__ e, const double (&D)[nherm(LC)],
+                                             const double (&G)[nherm(LAB)], double (&acc)[NAB])
+{
+#pragma unroll
+    for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+        for (int u = 0; u + t <= LAB; ++u)
+#pragma unroll
+            for (int v = 0; v + u + t <= LAB; ++v) {
+                double w = 0.0;
+#pragma unroll
+                for (int dx = 0; dx <= t && dx <= LC; ++dx)
+#pragma unroll
+                    for (int dy = 0; dy <= u && dx + dy <= LC; ++dy)
+#pragma unroll
+                        for (int dz = 0; dz <= v && dx + dy + dz <= LC; ++dz)
+                            w += D[hidx(dx, dy, dz)] * G[hidx(t - dx, u - dy, v - dz)];
+                const double *eh = e + hidx(t, u, v) * NAB;
+#pragma unroll
+                for (int i = 0; i < NAB; ++i) acc[i] += eh[i] * w;
+            }
+}
+
+// Lane per (aux shell, m_c): floor(64 / (2 lc + 1)) shells per wave, all m_c of
+// a shell in adjacent lanes, so every function-pair row is stored as one
+// contiguous run per wave.
 template <int LA, int LB, int LC>
 __global__ __launch_bounds__(256) void k_int3c(Int3cArgs g)
 {
     constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1, NAB = NA * NB;
-    constexpr int CC = ncart(LC), LAB = LA + LB, L = LAB + LC;
+    constexpr int CC = ncart(LC), LAB = LA + LB;
     constexpr int SPW = 64 / NC, SPB = 4 * SPW;   // aux shells per wave, per workgroup
     constexpr int RS = pair_rec_doubles(LA, LB);
     const int nsc = g.c_end - g.c_begin;
@@ -389,76 +560,81 @@ __global__ __launch_bounds__(256) void k_int3c(Int3cArgs g)
     double acc[NAB];
 #pragma unroll
     for (int i = 0; i < NAB; ++i) acc[i] = 0.0;
-
-    const double p = rec[0];
     if (rec[4] * g.ax.q[ic] >= g.tau) {
-        const double gc = g.ax.exp[ic];
-        const double X = rec[1] - g.ax.x[ic], Y = rec[2] - g.ax.y[ic], Z = rec[3] - g.ax.z[ic];
-        const double pg = p + gc, ipg = 1.0 / pg;
-        const double alpha = p * gc * ipg;
-        double F[L + 1];
-        boys<L>(alpha * (X * X + Y * Y + Z * Z), F, g.boys);
-        // G'[tuv] = d^{tuv} F_lc(alpha r^2) / (t! u! v!)
-        double G[nherm(LAB)];
-        hermite_R<LAB, LC>(alpha, X, Y, Z, F, G);
+        double G[nherm(LAB)], M[nherm(LC)], sc;
+        ket_table<LAB, LC>(rec[0], rec[1] - g.ax.x[ic], rec[2] - g.ax.y[ic], rec[3] - g.ax.z[ic], g.ax.exp[ic],
+                           g.boys, G, M, sc);
+        double sv[CC], D[nherm(LC)];
 #pragma unroll
-        for (int t = 0; t <= LAB; ++t)
-#pragma unroll
-            for (int u = 0; u + t <= LAB; ++u)
-#pragma unroll
-                for (int v = 0; v + u + t <= LAB; ++v)
-                    G[hidx(t, u, v)] *= kInvFact[t] * kInvFact[u] * kInvFact[v];
-        // D[d] = d^d S_mc(X, Y, Z) / d!  for |d| <= lc, from the monomials X^i Y^j Z^k
-        double D[nherm(LC)];
-        {
-            double px[LC + 1], py[LC + 1], pz[LC + 1];
-            px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-            for (int i = 1; i <= LC; ++i) { px[i] = px[i - 1] * X; py[i] = py[i - 1] * Y; pz[i] = pz[i - 1] * Z; }
-            double M[nherm(LC)];
-#pragma unroll
-            for (int i = 0; i <= LC; ++i)
-#pragma unroll
-                for (int j = 0; i + j <= LC; ++j)
-#pragma unroll
-                    for (int k = 0; i + j + k <= LC; ++k) M[hidx(i, j, k)] = px[i] * py[j] * pz[k];
-            double sv[CC];
-#pragma unroll
-            for (int k = 0; k < CC; ++k) sv[k] = c_sph[LC][mc][k];
-#pragma unroll
-            for (int i = 0; i < nherm(LC); ++i) D[i] = 0.0;
-            constexpr KetTerms<LC> kt = ket_terms<LC>();
-#pragma unroll
-            for (int i = 0; i < kt.n; ++i) D[kt.d[i]] += (kt.c[i] * sv[kt.k[i]]) * M[kt.m[i]];
-        }
-        // W'[tuv] and the bra contraction, one Hermite index at a time
-#pragma unroll
-        for (int t = 0; t <= LAB; ++t)
-#pragma unroll
-            for (int u = 0; u + t <= LAB; ++u)
-#pragma unroll
-                for (int v = 0; v + u + t <= LAB; ++v) {
-                    double w = 0.0;
-#pragma unroll
-                    for (int dx = 0; dx <= t && dx <= LC; ++dx)
-#pragma unroll
-                        for (int dy = 0; dy <= u && dx + dy <= LC; ++dy)
-#pragma unroll
-                            for (int dz = 0; dz <= v && dx + dy + dz <= LC; ++dz)
-                                w += D[hidx(dx, dy, dz)] * G[hidx(t - dx, u - dy, v - dz)];
-                    const double *e = rec + 8 + hidx(t, u, v) * NAB;
-#pragma unroll
-                    for (int i = 0; i < NAB; ++i) acc[i] += e[i] * w;
-                }
-        double sc = g.ax.norm[ic] * sqrt(ipg) / gc;
-#pragma unroll
-        for (int k = 0; k < LC; ++k) sc *= p * ipg;
+        for (int k = 0; k < CC; ++k) sv[k] = c_sph[LC][mc][k];
+        ket_factor<LC>(sv, M, D);
+        bra_contract<LAB, LC, NAB>(rec + 8, D, G, acc);
+        sc *= g.ax.norm[ic];
 #pragma unroll
         for (int i = 0; i < NAB; ++i) acc[i] *= sc;
     }
     double *out = g.U + ((int64_t)g.pf0[ip] - g.f_base) * g.ld + g.ax.off[ic] + mc;
 #pragma unroll
     for (int i = 0; i < NAB; ++i) out[i * g.ld] = acc[i];
+}
+
+// Lane per aux shell (classes with few outputs per triplet): the Boys
+// function, the Hermite table and the divisions are formed once per triplet
+// rather than once per m_c, every m_c is accumulated in registers, and each
+// function-pair row of the wave's 64 shells goes out through LDS as one
+// contiguous run of 64 (2 lc + 1) values.
+template <int LA, int LB, int LC>
+__global__ __launch_bounds__(256) void k_int3c_sh(Int3cArgs g)
+{
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1, NAB = NA * NB;
+    constexpr int CC = ncart(LC), LAB = LA + LB;
+    constexpr int RS = pair_rec_doubles(LA, LB);
+    __shared__ double buf[4][64 * NC];
+    const int nsc = g.c_end - g.c_begin;
+    const int ngrp = (nsc + 255) / 256;
+    const int pl = (int)(blockIdx.x / ngrp), grp = (int)(blockIdx.x % ngrp);
+    const int ip = g.p_begin + pl;
+    const double *__restrict__ rec = g.rec + (int64_t)(ip - g.rec_first) * RS;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c0 = grp * 256 + wave * 64;
+    if (c0 >= nsc) return;   // whole wave past the class
+    const int nv = min(64, nsc - c0);
+    const int ic = g.c_begin + c0 + min(lane, nv - 1);
+    double acc[NC][NAB];
+#pragma unroll
+    for (int m = 0; m < NC; ++m)
+#pragma unroll
+        for (int i = 0; i < NAB; ++i) acc[m][i] = 0.0;
+    if (lane < nv && rec[4] * g.ax.q[ic] >= g.tau) {
+        double G[nherm(LAB)], M[nherm(LC)], sc;
+        ket_table<LAB, LC>(rec[0], rec[1] - g.ax.x[ic], rec[2] - g.ax.y[ic], rec[3] - g.ax.z[ic], g.ax.exp[ic],
+                           g.boys, G, M, sc);
+        sc *= g.ax.norm[ic];
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            double sv[CC], D[nherm(LC)];
+#pragma unroll
+            for (int k = 0; k < CC; ++k) sv[k] = c_sph[LC][m][k];
+            ket_factor<LC>(sv, M, D);
+            bra_contract<LAB, LC, NAB>(rec + 8, D, G, acc[m]);
+#pragma unroll
+            for (int i = 0; i < NAB; ++i) acc[m][i] *= sc;
+        }
+    }
+    double *row = g.U + ((int64_t)g.pf0[ip] - g.f_base) * g.ld + g.ax.off[g.c_begin + c0];
+    double *b = buf[wave];
+#pragma unroll
+    for (int i = 0; i < NAB; ++i) {
+#pragma unroll
+        for (int m = 0; m < NC; ++m) b[lane * NC + m] = acc[m][i];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int e = j * 64 + lane;
+            if (e < nv * NC) row[i * g.ld + e] = b[e];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 template <int LA, int LB>
@@ -470,14 +646,29 @@ static void launch_pair_class(Int3cArgs g, double *rec, hipStream_t s)
     hipLaunchKernelGGL((k_pair_rec<LA, LB>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, rec);
 }
 
+// Lane per aux shell while the outputs of a triplet, (2la+1)(2lb+1)(2lc+1),
+// fit in registers beside the tables and the wave's pass over the pair record
+// per m_c stays short; lane per (aux shell, m_c) otherwise (chosen per class
+// from kernel times on the 128-water cluster).
+constexpr bool shell_lanes_for(int la, int lb, int lc)
+{
+    const int nout = (2 * la + 1) * (2 * lb + 1) * (2 * lc + 1);
+    const int nh = (la + lb + 1) * (la + lb + 2) * (la + lb + 3) / 6;
+    return nout <= 45 && nout * nh <= 500;
+}
+
 template <int LA, int LB, int LC>
 static void launch_class(Int3cArgs g, hipStream_t s)
 {
-    constexpr int SPB = 4 * (64 / (2 * LC + 1));
+    constexpr bool shell_lanes = shell_lanes_for(LA, LB, LC);
+    constexpr int SPB = shell_lanes ? 256 : 4 * (64 / (2 * LC + 1));
     const int64_t npl = g.p_end - g.p_begin, nsc = g.c_end - g.c_begin;
     if (npl <= 0 || nsc <= 0) return;
     const int64_t nblk = npl * ((nsc + SPB - 1) / SPB);
-    hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)nblk), dim3(256), 0, s, g);
+    if constexpr (shell_lanes)
+        hipLaunchKernelGGL((k_int3c_sh<LA, LB, LC>), dim3((unsigned)nblk), dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)nblk), dim3(256), 0, s, g);
 }
 
 static ShellsDev ao_view(const Plan &p)
@@ -631,6 +822,12 @@ void launch_direct_pairs(const DirectClassDev *cls, const ShellsDev &ao, hipStre
 // Two-centre metric (P|Q), both sides solid harmonic (Hobson on each):
 // (c|d) = N_c N_d 2 pi^{5/2}/(g d sqrt(g+d)) (2g)^{-lc} (-1)^{ld} (2d)^{-ld}
 //         sum_{k,k'} s_c(k) s_d(k') R_{k+k'}(alpha, C-D).
+// The sum over k' is S_md(grad) applied to R_000, which by Hobson's theorem is
+// d^k [S_md(X, Y, Z) (-2 alpha)^ld F_ld(alpha r^2)]; with the Taylor-scaled
+// tables of the three-centre kernel (G' to order lc, D of S_md) it is
+// k! W'[k], W'[k] = sum_d D[d] G'[k - d], needed only at |k| = lc.  So
+// (c|d) = N_c N_d 2 pi^{5/2}/(g d sqrt(g+d)) (2g)^{-lc} (g/(g+d))^ld
+//         sum_{|k| = lc} s_c(k) k! W'[k].
 
 struct Int2cArgs {
     ShellsDev ax;
@@ -643,40 +840,47 @@ struct Int2cArgs {
 template <int LC, int LD>
 __device__ void metric_block(const Int2cArgs &g, int c, int d)
 {
-    constexpr int L = LC + LD, CC = ncart(LC), CD = ncart(LD);
+    constexpr int CC = ncart(LC), CD = ncart(LD);
     const double gc = g.ax.exp[c], gd = g.ax.exp[d];
     const double X = g.ax.x[c] - g.ax.x[d], Y = g.ax.y[c] - g.ax.y[d], Z = g.ax.z[c] - g.ax.z[d];
-    const double sum = gc + gd, alpha = gc * gd / sum;
-    double F[L + 1];
-    boys<L>(alpha * (X * X + Y * Y + Z * Z), F, g.boys);
-    double R[nherm(L)];
-    hermite_R<L>(alpha, X, Y, Z, F, R);
-    double sc = 1.0;
+    double G[nherm(LC)], M[nherm(LD)], sc;
+    // ket_table with (p, g) = (gc, gd) gives G' = d^k F_ld(alpha r^2)/k! to order lc,
+    // the monomials to order ld, and (alpha/gd)^ld / (gd sqrt(gc+gd)), alpha/gd = gc/(gc+gd)
+    ket_table<LC, LD>(gc, X, Y, Z, gd, g.boys, G, M, sc);
 #pragma unroll
     for (int k = 0; k < LC; ++k) sc *= 0.5 / gc;
-#pragma unroll
-    for (int k = 0; k < LD; ++k) sc *= -0.5 / gd;
-    const double pref = kTwoPi52 / (gc * gd * sqrt(sum)) * sc * g.ax.norm[c] * g.ax.norm[d];
+    const double pref = kTwoPi52 / gc * sc * g.ax.norm[c] * g.ax.norm[d];
     const int oc = g.ax.off[c], od = g.ax.off[d];
 #pragma unroll
-    for (int mc = 0; mc < 2 * LC + 1; ++mc)
+    for (int md = 0; md < 2 * LD + 1; ++md) {
+        double sv[CD], D[nherm(LD)];
 #pragma unroll
-        for (int md = 0; md < 2 * LD + 1; ++md) {
+        for (int k = 0; k < CD; ++k) sv[k] = c_sph[LD][md][k];
+        ket_factor<LD>(sv, M, D);
+        double W[CC];
+#pragma unroll
+        for (int i = 0; i < CC; ++i) {
+            const int t = cart_pow(LC, i, 0), u = cart_pow(LC, i, 1), v = cart_pow(LC, i, 2);
+            double w = 0.0;
+#pragma unroll
+            for (int dx = 0; dx <= t && dx <= LD; ++dx)
+#pragma unroll
+                for (int dy = 0; dy <= u && dx + dy <= LD; ++dy)
+#pragma unroll
+                    for (int dz = 0; dz <= v && dx + dy + dz <= LD; ++dz)
+                        w += D[hidx(dx, dy, dz)] * G[hidx(t - dx, u - dy, v - dz)];
+            W[i] = w * (kFact[t] * kFact[u] * kFact[v]);
+        }
+#pragma unroll
+        for (int mc = 0; mc < 2 * LC + 1; ++mc) {
             double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < CC; ++i) {
-                double inner = 0.0;
-#pragma unroll
-                for (int j = 0; j < CD; ++j)
-                    inner += c_sph[LD][md][j] * R[hidx(cart_pow(LC, i, 0) + cart_pow(LD, j, 0),
-                                                       cart_pow(LC, i, 1) + cart_pow(LD, j, 1),
-                                                       cart_pow(LC, i, 2) + cart_pow(LD, j, 2))];
-                s += c_sph[LC][mc][i] * inner;
-            }
+            for (int i = 0; i < CC; ++i) s += c_sph[LC][mc][i] * W[i];
             s *= pref;
             g.V[(int64_t)(oc + mc) * g.ld + od + md] = s;
             g.V[(int64_t)(od + md) * g.ld + oc + mc] = s;
         }
+    }
 }
 
 __global__ __launch_bounds__(128) void k_int2c(Int2cArgs g)
