@@ -722,7 +722,7 @@ def main():
         "K": {"bound": "mfma", "frac": roofline["frac"]},
         "int3c": {"bound": "fp64 valu", "ms_per_setup": f64["stages_ms_per_launch"].get("setup.int3c"),
                   "shell_triplets": scr["triplets_kept"],
-                  "note": "FP64 VALU fraction from counters: profiles/water128_int3c_and_k.md"},
+                  "note": "FP64 VALU fraction from counters: profiles/int3c_water128.md"},
     }
     for prec, peak in (("int8", PEAK_INT8_TOPS / I8_PRODUCTS), ("fp32", PEAK_F32_TFLOPS),
                        ("bf16x3", PEAK_BF16_TFLOPS / 3.0)):
