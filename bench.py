@@ -35,6 +35,7 @@ PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_BYTES = 8.0e12
 PEAK_INT8_TOPS = 5000.0          # dense int8 MFMA
 I8_PRODUCTS = 15                 # int8 slice products per FP64-equivalent product (five slices, orders <= 4)
+I8F_PRODUCTS = 10                # the same for int8_fast (orders <= 3)
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "water32.json")
 
 
@@ -190,7 +191,7 @@ def make_inputs(n=32, box=10.0, geom_seed=1, cocc_seed=1):
 
 
 def run_job(Plan, mol, Cd, precision, bufs, profile):
-    """One job: setup + NBUILDS builds.  precision 'fp64' / 'int8' / 'fp32' /
+    """One job: setup + NBUILDS builds.  precision 'fp64' / 'int8' / 'int8_fast' / 'fp32' /
     'bf16x3' builds every K directly; '<p>_incr' builds K(C_0) in FP64 and
     each later K as K(C_0) + K(D - D_0) with the increment in precision <p>;
     'checked' runs dfjk_build_checked (int8 when its energy-error bound is
@@ -431,7 +432,8 @@ def large_bench(nbuild=2):
            "B_resident_GB": round(info["nf"] * info["naux_pad"] * 8 / 1e9, 2)}
     ref = None
     for prec, peak in (("fp64", PEAK_F64_TFLOPS), ("int8", PEAK_INT8_TOPS / I8_PRODUCTS),
-                       ("fp32", PEAK_F32_TFLOPS), ("bf16x3", PEAK_BF16_TFLOPS / 3.0), ("fp32_incr", PEAK_F32_TFLOPS)):
+                       ("int8_fast", PEAK_INT8_TOPS / I8F_PRODUCTS), ("fp32", PEAK_F32_TFLOPS),
+                       ("bf16x3", PEAK_BF16_TFLOPS / 3.0), ("fp32_incr", PEAK_F32_TFLOPS)):
         incr = prec.endswith("_incr")
         Es = []
         torch.cuda.synchronize()
@@ -455,8 +457,9 @@ def large_bench(nbuild=2):
         if not incr:
             r["K_tflops"] = round(k_flops / (kms * 1e-3) / 1e12, 2)
             r["K_frac_of_peak"] = round(k_flops / (kms * 1e-3) / 1e12 / peak, 4)
-            if prec == "int8":
-                r["K_int8_tops"] = round(I8_PRODUCTS * k_flops / (kms * 1e-3) / 1e12, 1)
+            if prec.startswith("int8"):
+                r["K_int8_tops"] = round((I8_PRODUCTS if prec == "int8" else I8F_PRODUCTS) * k_flops
+                                         / (kms * 1e-3) / 1e12, 1)
         if prec == "fp64":
             ref = E
         else:
@@ -629,8 +632,8 @@ def main():
     results = {}
     ref_E = None
     ref_K = None
-    modes = ["fp64"] + ([] if args.no_mixed else ["int8", "checked", "checked_1e-5", "fp32", "bf16x3", "fp32_incr",
-                                                      "bf16x3_incr"])
+    modes = ["fp64"] + ([] if args.no_mixed else ["int8", "int8_fast", "checked", "checked_1e-5", "fp32", "bf16x3",
+                                                      "fp32_incr", "bf16x3_incr"])
     if args.modes:
         modes = ["fp64"] + [m for m in args.modes.split(",") if m != "fp64"]
     for prec in modes:
@@ -724,15 +727,17 @@ def main():
                   "shell_triplets": scr["triplets_kept"],
                   "note": "FP64 VALU fraction from counters: profiles/int3c_water128.md"},
     }
-    for prec, peak in (("int8", PEAK_INT8_TOPS / I8_PRODUCTS), ("fp32", PEAK_F32_TFLOPS),
+    for prec, peak in (("int8", PEAK_INT8_TOPS / I8_PRODUCTS), ("int8_fast", PEAK_INT8_TOPS / I8F_PRODUCTS),
+                       ("fp32", PEAK_F32_TFLOPS),
                        ("bf16x3", PEAK_BF16_TFLOPS / 3.0)):
         if prec in results:
             n_l = results[prec]["stage_launches"]["build.K"] / (args.steps * NBUILDS)
             ms = results[prec]["stages_ms_per_launch"]["build.K"] * n_l        # per build
             results[prec]["K_tflops"] = round(k_flops / (ms * 1e-3) / 1e12, 2)
             results[prec]["K_frac_of_peak"] = round(k_flops / (ms * 1e-3) / 1e12 / peak, 4)
-            if prec == "int8":
-                results[prec]["K_int8_tops"] = round(I8_PRODUCTS * k_flops / (ms * 1e-3) / 1e12, 1)
+            if prec.startswith("int8"):
+                results[prec]["K_int8_tops"] = round((I8_PRODUCTS if prec == "int8" else I8F_PRODUCTS) * k_flops
+                                                     / (ms * 1e-3) / 1e12, 1)
 
     direct = None
     if not args.no_direct:

@@ -74,7 +74,13 @@ typedef enum {
                                 with exact int32 sums, folded into FP64 once
                                 per block.  Per product the dropped part is
                                 below 2^-33 of the product of the two block
-                                scales */
+                                scales */,
+    DFJK_MIXED_INT8_FAST = 4 /* the same slices, K from the 11 products with
+                                i + j <= 3 and a_2 b_2 (a_4 unused; a_2 b_2,
+                                a square on the diagonal, is kept so that the
+                                dropped part carries no systematic sign): per
+                                product the dropped part is below 2^-27 of the
+                                product of the two block scales */
 } dfjk_precision;
 
 /* One basis (AO or auxiliary): nshell uncontracted shells on atoms. */

@@ -91,6 +91,13 @@ def int8_product(A, B, block=256, nslices=5, keep=None):
     return out
 
 
+def int8_fast_keep(i, j):
+    """The products of the four-order variant: i + j <= 3, and a_2 b_2 (a
+    square on the diagonal of K, so the one order-4 product whose omission
+    would bias E_K)."""
+    return i + j <= 3 or (i, j) == (2, 2)
+
+
 def int8_scale_envelope(A, B, block=256, nslices=5):
     """S_{mu nu} = sum_k 2^{e_mu(k) + e_nu(k)}: times 2^-33 it bounds the
     truncation error of int8_product (each kept-set product is within

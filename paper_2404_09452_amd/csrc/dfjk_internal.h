@@ -59,9 +59,10 @@ inline int64_t ht_ldc(int64_t ncol) { return ht_passes(ncol) * ht_pass_frags(nco
 
 // Contraction length of one aux slab of plen rows with ncol columns as the
 // precision stores it, and the bytes of its X buffers (main and second plane).
+inline bool is_int8(int precision) { return precision == DFJK_MIXED_INT8 || precision == DFJK_MIXED_INT8_FAST; }
 inline int64_t x_kdim(int precision, int64_t plen, int64_t ncol)
 {
-    return plen * (precision == DFJK_MIXED_INT8 ? ncol + (ncol & 1) : ncol);
+    return plen * (is_int8(precision) ? ncol + (ncol & 1) : ncol);
 }
 inline size_t x_bytes(int precision, int64_t rows, int64_t kdim)
 {
@@ -76,10 +77,10 @@ inline size_t x_bytes(int precision, int64_t rows, int64_t kdim)
 inline size_t x_lo_bytes(int precision, int64_t rows, int64_t kdim)
 {
     if (precision == DFJK_MIXED_BF16X3) return (size_t)rows * (size_t)kdim * 2;
-    if (precision == DFJK_MIXED_INT8) return (size_t)rows * (size_t)(kdim / kI8Block) * 8;   // block scales
+    if (is_int8(precision)) return (size_t)rows * (size_t)(kdim / kI8Block) * 8;   // block scales
     return 0;
 }
-inline bool valid_precision(int precision) { return precision >= DFJK_FP64 && precision <= DFJK_MIXED_INT8; }
+inline bool valid_precision(int precision) { return precision >= DFJK_FP64 && precision <= DFJK_MIXED_INT8_FAST; }
 
 // Boys table: F_m(T_k) at T_k = k * h, 0 <= k < kBoysNT, 0 <= m < kBoysNM.
 constexpr double kBoysH = 0.05;

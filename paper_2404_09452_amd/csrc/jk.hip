@@ -619,7 +619,7 @@ __global__ __launch_bounds__(256) void k_energies_grouped(EnergyGroup grp, doubl
 int mixed_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus);
 int i8_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus);
 void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, const double *sB, int64_t nao,
-                    int64_t kdim, int nsplit, double *part, hipStream_t s);
+                    int64_t kdim, int nsplit, bool fast, double *part, hipStream_t s);
 
 static int choose_ksplit(int ntiles, int64_t kdim, int num_cus, int per_cu = 2)
 {
@@ -684,7 +684,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     // beside the half transform the 128-water build took 1.33 s, against
     // 1.21 s for the same build with sequential slabs.
     const bool may_overlap = allow_overlap && !with_D && !delta && !p.host_B && p.naux_pad >= 2 * kPadAux &&
-                             precision != DFJK_MIXED_INT8;
+                             !is_int8(precision);
     const double per_aux = (double)p.nao * L.ncol *
                            (esz + (with_D ? 8 : 0)) *
                            (delta ? 2 : 1) * (may_overlap ? 2 : 1);
@@ -692,7 +692,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
                  : force_slab > 0 ? force_slab
                  : p.aux_slab > 0 ? (int64_t)align_up((size_t)p.aux_slab, kPadAux)
                                   : (int64_t)(kAutoSlabBytes / per_aux) / kPadAux * kPadAux;
-    if (precision == DFJK_MIXED_INT8 && !p.host_B) {   // 128 rows of int8 slices below 4 GiB (32-bit offsets)
+    if (is_int8(precision) && !p.host_B) {   // 128 rows of int8 slices below 4 GiB (32-bit offsets)
         const int64_t ncol_e = L.ncol + (L.ncol & 1);
         const int64_t cap = ((int64_t)UINT32_MAX / (128 * kI8Slices) / ncol_e) / kPadAux * kPadAux;
         if (slab > cap) slab = cap;
@@ -718,7 +718,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     // 8 or more is rounded down to a multiple of the XCD count, so that the
     // syrk runs whole splits per XCD.
     L.nsplit_k = precision == DFJK_FP64 ? xcd_round(choose_ksplit(ntiles, L.kdim, p.num_cus, L.ktile == 64 ? 64 : 16))
-               : precision == DFJK_MIXED_INT8 ? i8_nsplit(p.nao, L.kdim, !delta, p.num_cus)
+               : is_int8(precision) ? i8_nsplit(p.nao, L.kdim, !delta, p.num_cus)
                                               : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
     if (nsplit == 0 && !with_D && !delta) {   // a split count the autotuner measured for this shape
         const auto it = p.tuned_nsplit.find((int64_t)nocc * 4 + precision);
@@ -823,9 +823,9 @@ static void slab_gemm(const BuildLayout &L, bool lower, const void *X, const voi
         const int64_t ksplit = (int64_t)align_up((size_t)((kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
         launch_syrk_f64(lower, static_cast<const double *>(X), static_cast<const double *>(Bop), nao, kdim, ksplit,
                         L.nsplit_k, L.ktile, part, s);
-    } else if (L.precision == DFJK_MIXED_INT8) {
+    } else if (is_int8(L.precision)) {
         launch_gemm_i8(lower, X, static_cast<const double *>(Xlo), Bop, static_cast<const double *>(Bop_lo), nao,
-                       kdim, L.nsplit_k, part, s);
+                       kdim, L.nsplit_k, L.precision == DFJK_MIXED_INT8_FAST, part, s);
     } else {
         launch_gemm_mixed(L.precision, lower, X, Xlo, Bop, Bop_lo, nao, kdim, L.nsplit_k, part, s);
     }

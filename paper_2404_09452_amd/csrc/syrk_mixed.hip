@@ -229,6 +229,12 @@ __global__ __launch_bounds__(256) void k_gemm_mixed(MixedArgs g)
 // FP64 and added with the block's scale 2^{e_x + e_y} into FP64
 // accumulators.  The only rounding is the truncation of the slices.
 //
+// DFJK_MIXED_INT8_FAST (FAST below) keeps the orders i + j <= 3 and the one
+// order-4 product a_2 b_2 (11 products; slice a_4 is neither loaded nor
+// used).  a_2 b_2 stays because on the diagonal it is a square: dropped, it
+// would shift every K_mu mu the same way and bias E_K (by 1e-6 Eh already on
+// three waters), whereas the other dropped order-4 products carry no sign.
+//
 // Workgroup: 128 rows x 64 columns of the output (half of a 128 x 128
 // partial tile, blockIdx.x = 2 tile + half), four waves of 64 x 32, each
 // 4 x 2 fragments of 16 x 16 with five int32 order accumulators (160
@@ -237,7 +243,8 @@ __global__ __launch_bounds__(256) void k_gemm_mixed(MixedArgs g)
 // registers): one wave instruction brings one MFMA operand fragment, 16 rows
 // x 64 k bytes of one slice, to 1 KB of LDS in lane order, so each later
 // fragment read is one contiguous 16-byte read per lane.  A chunk of 64 k is
-// 40 fragments of the 128 rows and 20 of the 64 columns (60 KB); two chunk
+// 8 NS fragments of the 128 rows and 4 NS of the 64 columns for the NS slices
+// used (60 KB at NS = 5); two chunk
 // buffers, the next chunk in flight while the current one feeds the MFMAs,
 // one barrier per chunk.
 // 16x16x64 i8 layout: lane l supplies row l%16 and 16 consecutive k bytes of
@@ -266,7 +273,7 @@ struct I8Args {
 // is always 128 x 64).  Fragments of a chunk are spread over the waves,
 // NFW per wave, padded with loads into a spare LDS slot so that every wave
 // issues the same count (the vmcnt immediate below).
-template <int WGM, int WGN, int RB, int CB>
+template <int WGM, int WGN, int RB, int CB, bool FAST>
 __global__ __launch_bounds__(64 * WGM * WGN)
 __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4)))
 void k_gemm_i8(I8Args g)
@@ -275,7 +282,8 @@ void k_gemm_i8(I8Args g)
     constexpr int AR = WGM * RB * 16, BR = WGN * CB * 16;                 // rows of the two operands
     static_assert(AR == T && BR == T / 2, "the workgroup tile is half of a 128 x 128 partial tile");
     constexpr int RBA = AR / 16, RBB = BR / 16;
-    constexpr int FA = RBA * kI8Slices, FB = RBB * kI8Slices, NF = FA + FB;   // fragments per chunk
+    constexpr int NS = FAST ? kI8Slices - 1 : kI8Slices;                 // slices loaded
+    constexpr int FA = RBA * NS, FB = RBB * NS, NF = FA + FB;           // fragments per chunk
     constexpr int NFW = (NF + NW - 1) / NW, NFS = NFW * NW;              // per wave; slots incl. spares
     constexpr int CH = kI8Slices * kI8Chunk;                             // bytes of one row per chunk
     static_assert(NFW <= 15, "vmcnt immediate holds 4 bits here");
@@ -385,16 +393,16 @@ void k_gemm_i8(I8Args g)
             const int64_t blk = k0 / kI8Block;
             if (tid < AR + BR) ssc[blk & 1][tid] = snext;
             scale_fetch(blk + 1);
-            i32x4 lev[5][RB][CB];
+            i32x4 lev[kI8Slices][RB][CB];   // order sums t = 0..4
 #pragma unroll
             for (int c = 0; c < kI8Block / kI8Chunk; ++c) {
                 const int64_t ci = (k0 - kb) / kI8Chunk + c;     // chunk index in this split (ci % 2 == c % 2)
                 unsigned char *cur = (c & 1) ? sm1 : sm0;
                 const unsigned char *Fa = cur + (wm * RB) * 1024 + lane * 16;
                 const unsigned char *Fb = cur + (FA + wn * CB) * 1024 + lane * 16;
-                i32x4 bf[kI8Slices][CB], af[kI8Slices][RB];
+                i32x4 bf[NS][CB], af[NS][RB];
 #pragma unroll
-                for (int sl = 0; sl < kI8Slices; ++sl) {
+                for (int sl = 0; sl < NS; ++sl) {
 #pragma unroll
                     for (int j = 0; j < CB; ++j)
                         bf[sl][j] = *reinterpret_cast<const i32x4 *>(Fb + (sl * RBB + j) * 1024);
@@ -407,14 +415,18 @@ void k_gemm_i8(I8Args g)
                 load(chunk_k(ci + 2), cur);
                 __builtin_amdgcn_sched_barrier(0);   // the DMA goes out before the MFMAs
 #pragma unroll
-                for (int si = 0; si < kI8Slices; ++si)
+                for (int si = 0; si < NS; ++si)
 #pragma unroll
-                    for (int sj = 0; sj + si < kI8Slices; ++sj)
+                    for (int sj = 0; sj < NS; ++sj)
 #pragma unroll
                         for (int i = 0; i < RB; ++i)
 #pragma unroll
                             for (int j = 0; j < CB; ++j) {
-                                const i32x4 cin = (c == 0 && si == 0) ? i32x4{0, 0, 0, 0} : lev[si + sj][i][j];
+                                const bool kept = FAST ? si + sj <= 3 || (si == 2 && sj == 2) : si + sj <= 4;
+                                if (!kept) continue;
+                                // the first product of each order sum in a block starts it from zero
+                                const bool first = c == 0 && si == (FAST && si + sj == 4 ? 2 : 0);
+                                const i32x4 cin = first ? i32x4{0, 0, 0, 0} : lev[si + sj][i][j];
                                 lev[si + sj][i][j] =
                                     __builtin_amdgcn_mfma_i32_16x16x64_i8(af[si][i], bf[sj][j], cin, 0, 0, 0);
                             }
@@ -437,10 +449,8 @@ void k_gemm_i8(I8Args g)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         double v = (double)lev[4][i][j][r];
-                        v = fma(v, 0x1p-7, (double)lev[3][i][j][r]);
-                        v = fma(v, 0x1p-7, (double)lev[2][i][j][r]);
-                        v = fma(v, 0x1p-7, (double)lev[1][i][j][r]);
-                        v = fma(v, 0x1p-7, (double)lev[0][i][j][r]);
+#pragma unroll
+                        for (int t = 3; t >= 0; --t) v = fma(v, 0x1p-7, (double)lev[t][i][j][r]);
                         acc[i][j][r] = fma(v, sa[r] * sb[j], acc[i][j][r]);
                     }
             }
@@ -501,7 +511,7 @@ int i8_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus)
 }
 
 void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, const double *sB, int64_t nao,
-                    int64_t kdim, int nsplit, double *part, hipStream_t s)
+                    int64_t kdim, int nsplit, bool fast, double *part, hipStream_t s)
 {
     I8Args g{};
     g.A = static_cast<const unsigned char *>(A);
@@ -514,8 +524,11 @@ void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, 
     g.partial = part;
     g.nsplit = nsplit;
     const int ntiles = lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm;
-    hipLaunchKernelGGL((k_gemm_i8<kI8WavesM, 2, 8 / kI8WavesM, 2>), dim3(2 * ntiles * nsplit), dim3(64 * 2 * kI8WavesM),
-                       0, s, g);
+    const dim3 grid(2 * ntiles * nsplit), block(64 * 2 * kI8WavesM);
+    if (fast)
+        hipLaunchKernelGGL((k_gemm_i8<kI8WavesM, 2, 8 / kI8WavesM, 2, true>), grid, block, 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm_i8<kI8WavesM, 2, 8 / kI8WavesM, 2, false>), grid, block, 0, s, g);
 }
 
 // Split count: one round of workgroups (two per CU), each split a multiple

@@ -14,8 +14,9 @@ import torch
 
 from . import _native as N
 
-FP64, MIXED_FP32, MIXED_BF16X3, MIXED_INT8 = 0, 1, 2, 3
-PRECISION = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3, "int8": MIXED_INT8}
+FP64, MIXED_FP32, MIXED_BF16X3, MIXED_INT8, MIXED_INT8_FAST = 0, 1, 2, 3, 4
+PRECISION = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3, "int8": MIXED_INT8,
+             "int8_fast": MIXED_INT8_FAST}
 EXPORT_INT3C, EXPORT_B, EXPORT_METRIC, EXPORT_CHOL = 0, 1, 2, 3
 
 STATUS = {0: "OK", 1: "INVALID", 2: "UNSUPPORTED", 3: "NOT_POSDEF", 4: "OOM", 5: "DEVICE",

@@ -170,7 +170,7 @@ class BatchedGpuExecutor(GpuExecutor):
     along from its first build.  Larger molecules, whose kernels fill the
     device by themselves, keep building on their own streams, free of the
     steps, overlapping with the batches.  Direct precisions only (fp64, int8,
-    fp32, bf16x3)."""
+    int8_fast, fp32, bf16x3)."""
 
     def __init__(self, keep_results=True, schwarz_thresh=1e-14, allocator_fraction=ALLOCATOR_FRACTION,
                  batch_below_nao=300):
@@ -188,7 +188,7 @@ class BatchedGpuExecutor(GpuExecutor):
 
     def run(self, req):
         torch = self.torch
-        if req.precision not in ("fp64", "int8", "fp32", "bf16x3"):
+        if req.precision not in ("fp64", "int8", "int8_fast", "fp32", "bf16x3"):
             raise ValueError("the batched executor runs direct builds only")
         plan, stream = self._plans[req.rid]
         if plan.nao >= self.batch_below_nao:

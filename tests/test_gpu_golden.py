@@ -58,7 +58,7 @@ def test_water32_fp64_against_golden(water32):
         assert relK <= 1e-10 and relJ <= 1e-10
 
 
-@pytest.mark.parametrize("prec", ["int8", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["int8", "int8_fast", "fp32", "bf16x3"])
 def test_water32_mixed_against_golden(water32, prec):
     g, plan, Cs = water32
     for k, C in Cs.items():
@@ -66,7 +66,7 @@ def test_water32_mixed_against_golden(water32, prec):
         dEJ, dEK, dK, relK, relJ, b = _errors(g, k, J, K, E)
         print("build %d %s: |dE_J| %.2e |dE_K| %.2e Eh  max|dK| (rows) %.2e" % (k, prec, dEJ, dEK, dK))
         assert relJ <= 1e-10 and dEJ <= 1e-10 * abs(b["E_J"])     # J stays FP64
-        if prec == "int8":
+        if prec.startswith("int8"):
             assert dEK <= 1e-6
 
 

@@ -13,11 +13,16 @@ Each format is checked twice:
       rounding boundary: |K - K_emul| <= 2^-39 S + 1e-13 max|K|, S the
       scale envelope 2 sum_k 2^{e_mu(k) + e_nu(k)} (one flip moves an
       element by at most 2^-34 2^{e_mu + e_nu});
+    INT8_FAST (orders i + j <= 3 and a_2 b_2): the same, but a flip of the
+      last slice it uses, a_3, moves an element by up to 2^-27 2^{e_mu + e_nu}
+      <= 2^-35 S: |K - K_emul| <= 2^-35 S + 1e-13 max|K|;
 * against the FP64 oracle K with the format's total error bound:
     FP32 (2^-15 + 2^-23), BF16x3 (2^-15 + 2^-14) times 2 sum_k |x||x|
     (binary32 rounding 2^-24 per factor; bf16 hi + lo of a binary32 value
     within 2^-17, the dropped lo.lo below 2^-16); INT8 2^-33 S (per product
-    the dropped orders and remainders stay below 2^-33 2^{e_x + e_y}).
+    the dropped orders and remainders stay below 2^-33 2^{e_x + e_y}),
+    INT8_FAST 2^-27 S (the dropped order-4 products sum to 1.5 2^-28, the
+    higher orders and remainders stay below 2^-33).
 A CPU test (tests/test_oracle_pins.py) shows that dropping any one kept
 product (int8) or the hi.lo cross term (BF16x3) breaks the first check.
 J and E_J stay FP64 in every mode; for INT8 the energies must also be
@@ -102,6 +107,11 @@ def check_format(prec, K, Kref, A_rows):
         S = 2 * sum(M.int8_scale_envelope(A, A) for A in A_rows)
         tight = 2.0 ** -39 * S + 1e-13 * Kmax
         total = 2.0 ** -33 * S + 1e-12 * Kmax
+    elif prec == "int8_fast":
+        Kf = 2 * sum(M.int8_product(A, A, keep=M.int8_fast_keep) for A in A_rows)
+        S = 2 * sum(M.int8_scale_envelope(A, A) for A in A_rows)
+        tight = 2.0 ** -35 * S + 1e-13 * Kmax
+        total = 2.0 ** -27 * S + 1e-12 * Kmax
     else:
         if prec == "fp32":
             ops = [(M.round_fp32(A), None) for A in A_rows]
@@ -135,20 +145,20 @@ def water3():
     return dict(mol=mol, S=S, C=C, U=U, V=V, B=B, ref=ref, plan=plan, Xp=Xp)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "int8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "int8", "int8_fast"])
 def test_mixed_k_elementwise_against_oracle(water3, prec):
     d = water3
     J, K, E = (t.cpu().numpy() for t in d["plan"].build(C=d["C"], precision=prec))
     J64, _, E64 = (t.cpu().numpy() for t in d["plan"].build(C=d["C"]))
     assert np.array_equal(J, J64) and E[0] == E64[0]         # J and E_J stay FP64
-    if prec == "int8":
+    if prec.startswith("int8"):
         rows = int8_rows(d["Xp"], d["Xp"].shape[0])
     else:
         rows = [d["Xp"].transpose(1, 0, 2).reshape(d["Xp"].shape[1], -1)]
     check_format(prec, K, d["ref"]["K"], rows)
     dEK = abs(E[1] - d["ref"]["EK"])
     print("%s: |dE_J| %.3e |dE_K| %.3e Eh" % (prec, abs(E[0] - d["ref"]["EJ"]), dEK))
-    if prec == "int8":
+    if prec.startswith("int8"):
         assert dEK <= 1e-6 and abs(E[0] - d["ref"]["EJ"]) <= 1e-10 * abs(d["ref"]["EJ"])
     assert np.abs(K - K.T).max() == 0.0
 

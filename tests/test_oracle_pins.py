@@ -610,7 +610,8 @@ def test_mixed_mutations_break_the_device_checks():
     tests allow between the device result and the format's exact value
     (tests/test_gpu_mixed.py) by a wide margin, so a kernel that made them
     would fail: dropping any one of the 15 kept int8 products (tolerance
-    2^-39 S + 1e-13 max|K|) and dropping the hi.lo cross term of BF16x3
+    2^-39 S + 1e-13 max|K|), any one of the 11 products of the fast variant
+    (2^-35 S + 1e-13 max|K|), and the hi.lo cross term of BF16x3
     (tolerance 2^-15 2 sum |x||x|, the FP32 summation bound)."""
     from oracle import mixed as M
     A = _x_rows_water3()
@@ -622,6 +623,16 @@ def test_mixed_mutations_break_the_device_checks():
         for j in range(5 - i):
             Km = 2 * M.int8_product(A, A, keep=lambda a, b, i=i, j=j: a + b <= 4 and (a, b) != (i, j))
             assert (np.abs(Km - Ke) / tight).max() > 4.0, (i, j)
+    # the fast variant: dropping any of its 11 products breaks its tolerance
+    # 2^-35 S + 1e-13 max|K|; its own error is within 2^-27 S
+    Kf4 = 2 * M.int8_product(A, A, keep=M.int8_fast_keep)
+    tight4 = 2.0 ** -35 * 2 * M.int8_scale_envelope(A, A) + 1e-13 * np.abs(K).max()
+    assert (np.abs(Kf4 - K) / (2.0 ** -27 * 2 * M.int8_scale_envelope(A, A))).max() <= 1.0
+    kept = [(i, j) for i in range(5) for j in range(5) if M.int8_fast_keep(i, j)]
+    assert len(kept) == 11
+    for i, j in kept:
+        Km = 2 * M.int8_product(A, A, keep=lambda a, b, i=i, j=j: M.int8_fast_keep(a, b) and (a, b) != (i, j))
+        assert (np.abs(Km - Kf4) / tight4).max() > 4.0, (i, j)
     hi, lo = M.split_bf16(A)
     Kf = 2 * (hi @ hi.T + hi @ lo.T + lo @ hi.T)
     ab = np.abs(hi) + np.abs(lo)
@@ -679,3 +690,21 @@ def test_int8_energy_error_decomposition_and_bound():
     assert abs(t3) <= b["lam"] * b["T"]
     assert abs(Eq - Eex) <= b["bound"]
     print("int8 |dE_K| %.3e, bound %.3e" % (abs(Eq - Eex), b["bound"]))
+
+
+def test_int8_fast_keeps_the_diagonal_square():
+    """Why the fast int8 variant keeps a_2 b_2: on 3 waters, orders i + j <= 3
+    alone shift E_K by about 1e-6 Eh (the dropped a_2^2 is positive on every
+    diagonal element of K), while adding a_2 b_2 back leaves an unbiased
+    error 40 times below 1e-6 Eh."""
+    from oracle import mixed as M
+    z, x = W.water_cluster(3, W.cluster_box(3), 103)
+    mol = W.make_molecule(z, x)
+    S = W.overlap_by_quadrature(mol)
+    C = W.occupied_orbitals(S, mol.nelec // 2, 10)
+    D = 2 * C @ C.T
+    A = _x_rows_water3()
+    EK = -0.25 * np.sum(D * (2 * A @ A.T))
+    e3 = -0.25 * np.sum(D * 2 * M.int8_product(A, A, keep=lambda i, j: i + j <= 3)) - EK
+    ef = -0.25 * np.sum(D * 2 * M.int8_product(A, A, keep=M.int8_fast_keep)) - EK
+    assert e3 > 5e-7 and abs(ef) < 2.5e-8
