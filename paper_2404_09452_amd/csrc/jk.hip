@@ -204,14 +204,31 @@ __device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB
     __syncthreads();   // the k loop's LDS reads are done
     if (tid < 128) bmax[tid] = 0ull;
     __syncthreads();
+    // Block maxima.  A lane's values of one r lie in one aux row, whose we <=
+    // 160 k span at most two blocks (lo, hi); the 16 lanes of that row (one
+    // DPP row, lane & 15) reduce both by butterfly, then one lane of each row
+    // updates the two blocks' maxima in LDS.
 #pragma unroll
-    for (int j = 0; j < NIB; ++j) {
-        const int c = j * 16 + (lane & 15);
-        if (c >= w) continue;
+    for (int r = 0; r < 4; ++r) {
+        const int row0 = (16 * wave + kl + 4 * r) * we;
+        const int blo = row0 / kI8Block;
+        double mlo = 0.0, mhi = 0.0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int kl_ = (16 * wave + kl + 4 * r) * we + c;
-            atomicMax(&bmax[kl_ / kI8Block], (unsigned long long)__double_as_longlong(fabs(acc[j][r])));
+        for (int j = 0; j < NIB; ++j) {
+            const int c = j * 16 + (lane & 15);
+            const double v = c < w ? fabs(acc[j][r]) : 0.0;
+            if ((row0 + c) / kI8Block == blo) mlo = fmax(mlo, v);
+            else mhi = fmax(mhi, v);
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            mlo = fmax(mlo, __shfl_xor(mlo, o, 16));
+            mhi = fmax(mhi, __shfl_xor(mhi, o, 16));
+        }
+        if ((lane & 15) == 0) {
+            atomicMax(&bmax[blo], (unsigned long long)__double_as_longlong(mlo));
+            if ((row0 + we - 1) / kI8Block != blo)
+                atomicMax(&bmax[blo + 1], (unsigned long long)__double_as_longlong(mhi));
         }
     }
     __syncthreads();
