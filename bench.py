@@ -555,7 +555,7 @@ def main():
                     help="requests per serving run (each load point and the closed loop)")
     ap.add_argument("--serve-max-waters", type=int, default=64)
     ap.add_argument("--no-large", action="store_true", help="skip the 128-water leg")
-    ap.add_argument("--serve-modes", default="fp64,int8+batched")
+    ap.add_argument("--serve-modes", default="fp64,int8+batched,int8_fast+batched")
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only run the serving stream: --serve-requests requests of 1..64 waters, Poisson "
                          "loads 0.5..1.1 x saturation, for each of --serve-modes; print its JSON")
