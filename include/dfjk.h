@@ -110,9 +110,9 @@ typedef struct {
                                     (syrk): 0 = dfjk_autotune's choice for the
                                     shape, else 64 where 128-wide tiles would
                                     execute over 14% more products (ragged
-                                    nao), else 128; 64 or 128 = that tile
-                                    for every FP64 syrk of the plan.  Other
-                                    values are DFJK_E_INVALID.                */
+                                    nao), else 128; 64, 96 or 128 = that
+                                    tile for every FP64 syrk of the plan.
+                                    Other values are DFJK_E_INVALID.          */
 } dfjk_options;
 
 typedef struct dfjk_plan dfjk_plan;

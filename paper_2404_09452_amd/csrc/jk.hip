@@ -679,7 +679,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
             auto executed = [&](int64_t t) { const int64_t n = (p.nao + t - 1) / t; return n * (n + 1) / 2 * t * t; };
             if ((double)executed(kTileK) > 1.14 * (double)executed(64)) kt = 64;
         }
-        if (kt == 64) L.ktile = 64;
+        if (kt == 64 || kt == 96) L.ktile = kt;
     }
     L.ntile = (int)((p.nao + L.ktile - 1) / L.ktile);
     L.delta = delta;
@@ -734,7 +734,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     // build; 128-wide x 8 / 16 / 32: 17.9 / 14.3 / 12.4 ms.  A split count of
     // 8 or more is rounded down to a multiple of the XCD count, so that the
     // syrk runs whole splits per XCD.
-    L.nsplit_k = precision == DFJK_FP64 ? xcd_round(choose_ksplit(ntiles, L.kdim, p.num_cus, L.ktile == 64 ? 64 : 16))
+    L.nsplit_k = precision == DFJK_FP64 ? xcd_round(choose_ksplit(ntiles, L.kdim, p.num_cus, L.ktile == 64 ? 64 : L.ktile == 96 ? 32 : 16))
                : is_int8(precision) ? i8_nsplit(p.nao, L.kdim, !delta, p.num_cus)
                                               : mixed_nsplit(p.nao, L.kdim, !delta, p.num_cus);
     if (nsplit == 0 && !with_D && !delta) {   // a split count the autotuner measured for this shape

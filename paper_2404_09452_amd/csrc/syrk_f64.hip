@@ -6,7 +6,8 @@
 // (gemm_f64.h): chunks of 16 k in ascending order, four k per MFMA step.
 //
 // Workgroup: one T x T tile of one k split, WGM x WGN waves (T = 128: 4 x 2
-// waves of 32 x 64; T = 64: 2 x 2 waves of 32 x 32), v_mfma_f64_16x16x4f64
+// waves of 32 x 64; T = 96: 2 x 2 waves of 48 x 48; T = 64: 2 x 2 waves of
+// 32 x 32), v_mfma_f64_16x16x4f64
 // (lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator r of lane l
 // is D[l/16 + 4r][l%16]).
 //
@@ -49,7 +50,7 @@ template <int N> constexpr int wait_vm() { return (N & 15) | ((N >> 4) << 14) | 
 
 template <int T, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN)
-__attribute__((amdgpu_waves_per_eu(T == 128 ? 2 : 3)))
+__attribute__((amdgpu_waves_per_eu(T == 64 ? 3 : 2)))
 void k_syrk_f64(SyrkArgs g)
 {
     constexpr int NW = WGM * WGN;
@@ -207,7 +208,7 @@ void k_syrk_f64(SyrkArgs g)
 }  // namespace
 
 // Split-K partial tiles of A B^T (A = B for the lower-tile syrk): M rows of
-// kdim, nsplit splits of ksplit (a multiple of 16), tiles of T (64 or 128).
+// kdim, nsplit splits of ksplit (a multiple of 16), tiles of T (64, 96 or 128).
 void launch_syrk_f64(bool lower, const double *A, const double *B, int64_t M, int64_t kdim, int64_t ksplit,
                      int nsplit, int T, double *partial, hipStream_t s)
 {
@@ -222,6 +223,8 @@ void launch_syrk_f64(bool lower, const double *A, const double *B, int64_t M, in
     const unsigned nwg = (unsigned)(ntiles * nsplit);
     if (T == 128)
         hipLaunchKernelGGL((k_syrk_f64<128, 4, 2>), dim3(nwg), dim3(512), 0, s, g);
+    else if (T == 96)
+        hipLaunchKernelGGL((k_syrk_f64<96, 2, 2>), dim3(nwg), dim3(256), 0, s, g);
     else
         hipLaunchKernelGGL((k_syrk_f64<64, 2, 2>), dim3(nwg), dim3(256), 0, s, g);
 }

@@ -63,7 +63,7 @@ def test_plan_create_and_info_on_host():
     (dict(ao_atom=[5]), "INVALID"),
     (dict(coords=[[0.0, float("inf"), 0.0]]), "INVALID"),
     (dict(schwarz_thresh=-1.0), "INVALID"),
-    (dict(k_tile=96), "INVALID"),
+    (dict(k_tile=80), "INVALID"),
 ])
 def test_plan_create_rejects_bad_input(bad, code):
     args = dict(coords=[[0.0, 0.0, 0.0]], ao_atom=[0], ao_l=[0], ao_exp=[1.0],

@@ -478,11 +478,11 @@ def test_setup_host_refuses_a_budget_below_one_pair(cluster5):
     plan.close()
 
 
-@pytest.mark.parametrize("n,tile", [(3, 64), (5, 64), (3, 128), (5, 128)])
+@pytest.mark.parametrize("n,tile", [(3, 64), (5, 64), (3, 96), (5, 96), (3, 128), (5, 128)])
 def test_k_tile_choices(n, tile):
-    """The FP64 syrk, its partials and reduction on 64- and 128-wide tiles
-    (ragged last tile row: nao 90 and 150), C and density routes, against
-    the oracle."""
+    """The FP64 syrk, its partials and reduction on 64-, 96- and 128-wide
+    tiles (ragged last tile row: nao 90 and 150), C and density routes,
+    against the oracle."""
     mol, S, C = case(n)
     plan = G.Plan.from_molecule(mol, schwarz_thresh=TAU, k_tile=tile).screen().setup()
     shape = plan.build_shape(C.shape[1])
