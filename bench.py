@@ -660,7 +660,11 @@ def main():
         E = np.array([o[2].cpu().numpy() for o in outs])
         K_last = outs[-1][1].cpu().numpy()
         setup_ms = sum(stage_ms[k] for k in stage_ms if k.startswith("setup.")) / args.steps
-        build_ms = sum(stage_ms[k] for k in stage_ms if k.startswith("build.")) / (args.steps * NBUILDS)
+        # a build's span on its stream (J overlaps the half transform and K on a
+        # side stream, so the stage times overlap); the stage sum where a mode
+        # records no span
+        build_ms = (stage_ms["span.build"] if stage_n.get("span.build") else
+                    sum(stage_ms[k] for k in stage_ms if k.startswith("build."))) / (args.steps * NBUILDS)
         r = {
             "builds_per_s": NBUILDS * args.steps / dt,
             "ms_per_step": 1000.0 * dt / args.steps,

@@ -484,8 +484,11 @@ int dfjk_boys(int32_t mmax, int64_t n, const double *d_T, double *d_F, void *str
  * synchronisation).  dfjk_profile_read waits for the recorded events, writes
  * the summed milliseconds and the number of timed launches of each of the
  * DFJK_NSTAGES stages (host arrays), and clears the record.
- * dfjk_stage_name(i) names stage i ("build.K", ...). */
-#define DFJK_NSTAGES 10
+ * dfjk_stage_name(i) names stage i ("build.K", ...).  "span.build" is a whole
+ * dfjk_build (C or D route) from its first to its last launch on the caller's
+ * stream: J runs on a side stream beside the half transform and K, so the
+ * "build.*" stages of one build overlap and their sum exceeds the span. */
+#define DFJK_NSTAGES 11
 int dfjk_profile(dfjk_plan *plan, int32_t on);
 int dfjk_profile_read(dfjk_plan *plan, double *ms, int32_t *count);
 const char *dfjk_stage_name(int32_t stage);

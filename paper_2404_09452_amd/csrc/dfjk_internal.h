@@ -114,6 +114,7 @@ struct ClassRange {
 enum Stage {
     ST_INT3C = 0, ST_METRIC, ST_CHOL, ST_TRTRI, ST_WHITEN,
     ST_DENSITY, ST_J, ST_HALFTRANS, ST_K, ST_KREDUCE,
+    ST_BUILD,                           // a whole build on its stream (stages on side streams overlap inside it)
     ST_COUNT
 };
 
@@ -154,7 +155,9 @@ struct Profiler {
     bool on = false;
     std::vector<hipEvent_t> pool;       // created on demand, destroyed with the plan
     std::vector<int> rec_stage;         // stage of event pair i (events 2i, 2i+1)
+    int open[ST_COUNT];                 // pair of the stage's unfinished begin, or -1
     hipStream_t stream = nullptr;
+    Profiler() { for (int &o : open) o = -1; }
     void mark(int stage, bool begin);   // records one event on `stream`
 };
 
@@ -187,6 +190,8 @@ struct Plan {
     // second stream of the overlapped half transform and its events
     hipStream_t ht_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_ht[2] = {nullptr, nullptr}, ev_kdone[2] = {nullptr, nullptr};
+    hipStream_t j_stream = nullptr;     // J beside the half transform and K of the same build
+    hipEvent_t ev_jfork = nullptr, ev_jdone = nullptr;
     // split counts chosen by dfjk_autotune for the closed-shell C-route build,
     // keyed by nocc * 4 + precision
     std::map<int64_t, int> tuned_nsplit;
@@ -326,6 +331,7 @@ struct BuildLayout {
     size_t o_norms;
     size_t o_stage[2];                  // staging of host-resident B slabs
     bool overlap;                       // half transform of the next slab beside the K GEMM
+    bool j_side;                        // J on a side stream beside the half transform and K
     size_t o_Xb, o_Xblo;                // the second X buffer of the overlapped schedule
 };
 // nsplit: 0 = the autotuned count when there is one, else the built-in

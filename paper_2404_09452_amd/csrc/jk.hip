@@ -725,6 +725,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
     L.slab = slab;
     L.nslab = (p.naux_pad + slab - 1) / slab;
     L.overlap = may_overlap && L.nslab >= 2;
+    L.j_side = allow_overlap && !p.host_B;
     L.kdim = x_kdim(precision, slab, L.ncol);
     const int ntiles = delta ? L.ntile * L.ntile : L.ntile * (L.ntile + 1) / 2;
     // FP64 syrk: enough splits for 64 workgroups per CU with 64-wide tiles
@@ -952,6 +953,26 @@ static void contract_slabs(Plan &p, const BuildLayout &L, const double *C1, cons
     }
 }
 
+// A side stream for J (created on first use; false if HIP refuses, and the
+// build then runs J in turn on its own stream).
+static bool j_stream(Plan &p)
+{
+    if (p.j_stream) return true;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t js = nullptr;
+    bool ok = hipEventCreateWithFlags(&a, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&js, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        if (js) (void)hipStreamDestroy(js);
+        return false;
+    }
+    p.ev_jfork = a; p.ev_jdone = b; p.j_stream = js;
+    return true;
+}
+
 void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *Din, double *J, double *K,
                   double *E, char *scratch, hipStream_t s)
 {
@@ -962,6 +983,7 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
     double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
     Profiler &pr = p.prof;
     pr.stream = s;
+    pr.mark(ST_BUILD, true);
 
     // 1. density
     pr.mark(ST_DENSITY, true);
@@ -979,17 +1001,32 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
                            reinterpret_cast<double *>(scratch + L.o_W));
     }
     pr.mark(ST_DENSITY, false);
-    // 2-4. J (always FP64)
+    // 2-4. J (always FP64).  J streams B through HBM (bound there) while the
+    // half transform and K are bound by the FP64 MFMA pipes, so J runs on a
+    // side stream beside them and is joined before the energies: it reads
+    // D and B and writes only J and its own scratch (d, c partials, c).
+    const bool jside = L.j_side && j_stream(p);
+    hipStream_t js = jside ? p.j_stream : s;
+    if (jside) {
+        (void)hipEventRecord(p.ev_jfork, s);
+        (void)hipStreamWaitEvent(js, p.ev_jfork, 0);
+        pr.stream = js;
+    }
     pr.mark(ST_J, true);
-    launch_j(p, L, D, J, scratch, s);
+    launch_j(p, L, D, J, scratch, js);
     pr.mark(ST_J, false);
+    if (jside) {
+        (void)hipEventRecord(p.ev_jdone, js);
+        pr.stream = s;
+    }
     // 5-6. per aux slab: half transform(s) and the slab's K contribution
     if (!L.delta)
         contract_slabs(p, L, L.with_D ? Din : C, nullptr, L.ncol, scratch, s);
     else
         contract_slabs(p, L, reinterpret_cast<double *>(scratch + L.o_U),
                        reinterpret_cast<double *>(scratch + L.o_W), L.ncol, scratch, s);
-    // 7. split-K sum, mirror, energies
+    // 7. split-K sum, mirror, energies (after J: the energies read c)
+    if (jside) (void)hipStreamWaitEvent(s, p.ev_jdone, 0);
     pr.mark(ST_KREDUCE, true);
     const int nlower = L.ntile * (L.ntile + 1) / 2;
     if (L.delta)
@@ -1002,6 +1039,7 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
     hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (L.ktile / 16), -0.25,
                        E);
     pr.mark(ST_KREDUCE, false);
+    pr.mark(ST_BUILD, false);
 }
 
 BuildLayout build_layout_uks(const Plan &p, int32_t nocc_a, int32_t nocc_b, int32_t precision)
@@ -1245,6 +1283,7 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
     hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (L.ktile / 16), -0.25,
                        E);
     pr.mark(ST_KREDUCE, false);
+    pr.mark(ST_BUILD, false);
 }
 
 }  // namespace dfjk

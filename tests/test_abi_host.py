@@ -135,12 +135,17 @@ def test_call_order_is_enforced_without_device():
     nocc = (ctypes.c_int32 * 1)(5)
     assert lib.dfjk_build_batch_bytes(1, hs, nocc, 0, ctypes.byref(n)) == 7     # not screened
     assert lib.dfjk_build_batch_bytes(0, hs, nocc, 0, ctypes.byref(n)) == 1     # empty batch
-    ms = np.zeros(10)
-    cnt = np.zeros(10, dtype=np.int32)
+    # the arrays hold DFJK_NSTAGES entries (the header's count, which the binding mirrors)
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "dfjk.h")).read()
+    nst = int(re.search(r"#define DFJK_NSTAGES (\d+)", hdr).group(1))
+    assert G.Plan.NSTAGES == nst
+    ms = np.zeros(nst)
+    cnt = np.zeros(nst, dtype=np.int32)
     assert lib.dfjk_profile(plan._h, 1) == 0
     assert lib.dfjk_profile_read(plan._h, ms.ctypes.data_as(N.P_dbl), cnt.ctypes.data_as(N.P_i32)) == 0
     assert cnt.sum() == 0
     assert lib.dfjk_stage_name(8) == b"build.K"
+    assert lib.dfjk_stage_name(nst - 1) == b"span.build"
 
 
 def test_boys_argument_checks_without_device():
