@@ -659,7 +659,8 @@ def main():
         dt = time.perf_counter() - t0
         E = np.array([o[2].cpu().numpy() for o in outs])
         K_last = outs[-1][1].cpu().numpy()
-        setup_ms = sum(stage_ms[k] for k in stage_ms if k.startswith("setup.")) / args.steps
+        setup_ms = (stage_ms["span.setup"] if stage_n.get("span.setup") else
+                    sum(stage_ms[k] for k in stage_ms if k.startswith("setup."))) / args.steps
         # a build's span on its stream (J overlaps the half transform and K on a
         # side stream, so the stage times overlap); the stage sum where a mode
         # records no span

@@ -487,8 +487,10 @@ int dfjk_boys(int32_t mmax, int64_t n, const double *d_T, double *d_F, void *str
  * dfjk_stage_name(i) names stage i ("build.K", ...).  "span.build" is a whole
  * dfjk_build (C or D route) from its first to its last launch on the caller's
  * stream: J runs on a side stream beside the half transform and K, so the
- * "build.*" stages of one build overlap and their sum exceeds the span. */
-#define DFJK_NSTAGES 11
+ * "build.*" stages of one build overlap and their sum exceeds the span.
+ * "span.setup" is a whole dfjk_setup alike (the integrals run beside the
+ * metric, its factor and inverse). */
+#define DFJK_NSTAGES 12
 int dfjk_profile(dfjk_plan *plan, int32_t on);
 int dfjk_profile_read(dfjk_plan *plan, double *ms, int32_t *count);
 const char *dfjk_stage_name(int32_t stage);

@@ -115,6 +115,7 @@ enum Stage {
     ST_INT3C = 0, ST_METRIC, ST_CHOL, ST_TRTRI, ST_WHITEN,
     ST_DENSITY, ST_J, ST_HALFTRANS, ST_K, ST_KREDUCE,
     ST_BUILD,                           // a whole build on its stream (stages on side streams overlap inside it)
+    ST_SETUP,                           // a whole setup on its stream, likewise
     ST_COUNT
 };
 
@@ -190,7 +191,7 @@ struct Plan {
     // second stream of the overlapped half transform and its events
     hipStream_t ht_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_ht[2] = {nullptr, nullptr}, ev_kdone[2] = {nullptr, nullptr};
-    hipStream_t j_stream = nullptr;     // J beside the half transform and K of the same build
+    hipStream_t j_stream = nullptr;     // side stream: J of a build, the integrals of a setup
     hipEvent_t ev_jfork = nullptr, ev_jdone = nullptr;
     // split counts chosen by dfjk_autotune for the closed-shell C-route build,
     // keyed by nocc * 4 + precision
@@ -293,6 +294,7 @@ constexpr int kPairClassLa[6] = {0, 1, 1, 2, 2, 2}, kPairClassLb[6] = {0, 0, 1, 
 void pair_rec_offsets(const Plan &p, int64_t off[7]);
 void launch_pair_records(const Plan &p, hipStream_t s);
 void launch_int3c(const Plan &p, hipStream_t s);
+bool side_stream(Plan &p);   // jk.hip: p.j_stream with p.ev_jfork / p.ev_jdone
 void launch_int3c_rows(const Plan &p, double *U, int64_t f_base, int32_t i0, int32_t i1, hipStream_t s);
 void launch_int2c(const Plan &p, hipStream_t s);
 void upload_constants(const double coef[kMaxLAux + 1][7][10], hipStream_t s);

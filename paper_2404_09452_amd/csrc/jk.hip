@@ -953,9 +953,10 @@ static void contract_slabs(Plan &p, const BuildLayout &L, const double *C1, cons
     }
 }
 
-// A side stream for J (created on first use; false if HIP refuses, and the
-// build then runs J in turn on its own stream).
-static bool j_stream(Plan &p)
+// The plan's side stream and its fork / join events (created on first use;
+// false if HIP refuses, and the caller then runs the work in turn on its
+// own stream).  A build runs J there; a setup runs the integrals there.
+bool side_stream(Plan &p)
 {
     if (p.j_stream) return true;
     hipEvent_t a = nullptr, b = nullptr;
@@ -1005,7 +1006,7 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
     // half transform and K are bound by the FP64 MFMA pipes, so J runs on a
     // side stream beside them and is joined before the energies: it reads
     // D and B and writes only J and its own scratch (d, c partials, c).
-    const bool jside = L.j_side && j_stream(p);
+    const bool jside = L.j_side && side_stream(p);
     hipStream_t js = jside ? p.j_stream : s;
     if (jside) {
         (void)hipEventRecord(p.ev_jfork, s);

@@ -350,7 +350,7 @@ class Plan:
         return self
 
     # -- diagnostics -------------------------------------------------------
-    NSTAGES = 11
+    NSTAGES = 12
 
     def profile(self, on=True):
         """Record HIP events around every stage of later setups and builds."""

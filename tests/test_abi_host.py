@@ -145,7 +145,7 @@ def test_call_order_is_enforced_without_device():
     assert lib.dfjk_profile_read(plan._h, ms.ctypes.data_as(N.P_dbl), cnt.ctypes.data_as(N.P_i32)) == 0
     assert cnt.sum() == 0
     assert lib.dfjk_stage_name(8) == b"build.K"
-    assert lib.dfjk_stage_name(nst - 1) == b"span.build"
+    assert lib.dfjk_stage_name(nst - 2) == b"span.build" and lib.dfjk_stage_name(nst - 1) == b"span.setup"
 
 
 def test_boys_argument_checks_without_device():
