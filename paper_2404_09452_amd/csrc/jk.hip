@@ -517,6 +517,12 @@ __global__ __launch_bounds__(256) void k_k_reduce_delta(const double *__restrict
 // Split-K reduction of the K tiles: K[m][n] = scale * sum_s partial[s][t][..]
 // in a fixed order, mirrored for off-diagonal tiles, plus per-block partial
 // sums of D[m][n] K[m][n] (weight 2 off the diagonal tiles) for E_K.
+// Rows of a tile per reduction workgroup: small enough that the grid has
+// many workgroups (each lane sums its splits in turn, so the loads of many
+// lanes in flight hide their latency).
+constexpr int kReduceRows = 4;
+constexpr int reduce_chunks(int T) { return T / kReduceRows; }
+
 __device__ __forceinline__ void reduce_tile(const double *__restrict__ part, int nsplit, int ntm, int T, int64_t nao,
                                             double scale, const double *__restrict__ D, double *__restrict__ K,
                                             double *__restrict__ Epart, const int t, const int chunk)
@@ -528,13 +534,14 @@ __device__ __forceinline__ void reduce_tile(const double *__restrict__ part, int
     while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
     const int tn = t - tm * (tm + 1) / 2;
     double e = 0.0;
-    for (int q = threadIdx.x; q < 16 * T; q += 256) {
-        const int row = chunk * 16 + q / T, col = q % T;
+    for (int q = threadIdx.x; q < kReduceRows * T; q += 256) {
+        const int row = chunk * kReduceRows + q / T, col = q % T;
         const int64_t m = (int64_t)tm * T + row, n = (int64_t)tn * T + col;
         // the upper half of a diagonal tile is mirrored from its lower half
         if (m >= nao || n >= nao || n > m) continue;
         const int64_t off = (int64_t)t * T * T + row * T + col;
         double s = 0.0;
+#pragma unroll 8
         for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t)sp * ntiles * T * T + off];
         s *= scale;
         K[m * nao + n] = s;
@@ -551,10 +558,10 @@ __device__ __forceinline__ void reduce_tile(const double *__restrict__ part, int
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) Epart[(int64_t)t * (T / 16) + chunk] = red[0];
+    if (threadIdx.x == 0) Epart[(int64_t)t * reduce_chunks(T) + chunk] = red[0];
 }
 
-// block (t, chunk): lower tile t (T wide), rows 16 chunk .. 16 chunk + 15
+// block (t, chunk): lower tile t (T wide), rows kReduceRows chunk onwards
 __global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ part, int nsplit, int ntm, int T,
                                                   int64_t nao, double scale, const double *__restrict__ D,
                                                   double *__restrict__ K, double *__restrict__ Epart)
@@ -563,7 +570,7 @@ __global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ par
 }
 
 // Grouped reduction for a batch: blocks blk_start[p] .. blk_start[p+1]-1 (times
-// kTileK / 16 chunks in y) reduce molecule p.  Descriptors by value.
+// reduce_chunks(kTileK) chunks in y) reduce molecule p.  Descriptors by value.
 constexpr int kReduceGroupMax = 16;
 struct ReduceGroup {
     int32_t n;
@@ -782,7 +789,7 @@ BuildLayout build_layout(const Plan &p, int32_t nocc, int32_t precision, bool wi
         L.o_stage[0] = take((size_t)p.nf_pad * L.slab * 8);
         L.o_stage[1] = take((size_t)p.nf_pad * L.slab * 8);
     }
-    L.o_Epart = take((size_t)L.ntile * (L.ntile + 1) / 2 * (L.ktile / 16) * 8);
+    L.o_Epart = take((size_t)L.ntile * (L.ntile + 1) / 2 * reduce_chunks(L.ktile) * 8);
     L.bytes = align_up(off, 256);
     return L;
 }
@@ -1030,15 +1037,15 @@ void launch_build(Plan &p, const BuildLayout &L, const double *C, const double *
     if (jside) (void)hipStreamWaitEvent(s, p.ev_jdone, 0);
     pr.mark(ST_KREDUCE, true);
     const int nlower = L.ntile * (L.ntile + 1) / 2;
+    const int64_t nep = (int64_t)nlower * (L.delta ? kTileK / 16 : reduce_chunks(L.ktile));   // energy partials
     if (L.delta)
         hipLaunchKernelGGL(k_k_reduce_delta, dim3(nlower, kTileK / 16), dim3(256), 0, s, Kpart,
                            (int)(L.nslab * L.nsplit_k),
                            L.ntile, nao, L.K0, D, K, Epart);
     else
-        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, L.ktile / 16), dim3(256), 0, s, Kpart,
+        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, reduce_chunks(L.ktile)), dim3(256), 0, s, Kpart,
                            (int)(L.nslab * L.nsplit_k), L.ntile, L.ktile, nao, L.with_D ? 1.0 : 2.0, D, K, Epart);
-    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (L.ktile / 16), -0.25,
-                       E);
+    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, nep, -0.25, E);
     pr.mark(ST_KREDUCE, false);
     pr.mark(ST_BUILD, false);
 }
@@ -1058,7 +1065,7 @@ BuildLayout build_layout_uks(const Plan &p, int32_t nocc_a, int32_t nocc_b, int3
     };
     L.o_Da = take((size_t)p.nao * p.nao * 8);
     L.o_Db = take((size_t)p.nao * p.nao * 8);
-    L.o_Epart = take((size_t)2 * L.ntile * (L.ntile + 1) / 2 * (L.ktile / 16) * 8);   // one block per spin
+    L.o_Epart = take((size_t)2 * L.ntile * (L.ntile + 1) / 2 * reduce_chunks(L.ktile) * 8);   // one block per spin
     L.bytes = align_up(off, 256);
     return L;
 }
@@ -1079,7 +1086,7 @@ void launch_build_uks(Plan &p, const BuildLayout &L, const double *Ca, const dou
     double *Kpart = reinterpret_cast<double *>(scratch + L.o_Kpart);
     double *Epart = reinterpret_cast<double *>(scratch + L.o_Epart);
     const int nlower = L.ntile * (L.ntile + 1) / 2;
-    const int64_t nep = (int64_t)nlower * (L.ktile / 16);
+    const int64_t nep = (int64_t)nlower * reduce_chunks(L.ktile);
     Profiler &pr = p.prof;
     pr.stream = s;
 
@@ -1102,7 +1109,7 @@ void launch_build_uks(Plan &p, const BuildLayout &L, const double *Ca, const dou
         }
         contract_slabs(p, L, Cs[sp], nullptr, nocc[sp], scratch, s);
         pr.mark(ST_KREDUCE, true);
-        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, L.ktile / 16), dim3(256), 0, s, Kpart,
+        hipLaunchKernelGGL(k_k_reduce, dim3(nlower, reduce_chunks(L.ktile)), dim3(256), 0, s, Kpart,
                            (int)(L.nslab * L.nsplit_k), L.ntile, L.ktile, nao, 1.0, Ds[sp], Ks[sp], Epart + sp * nep);
         pr.mark(ST_KREDUCE, false);
     }
@@ -1184,7 +1191,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
             total += L.ntile * (L.ntile + 1) / 2;
         }
         grp.blk_start[grp.n] = total;
-        hipLaunchKernelGGL(k_k_reduce_grouped, dim3(total, kTileK / 16), dim3(256), 0, s, grp, 2.0);
+        hipLaunchKernelGGL(k_k_reduce_grouped, dim3(total, reduce_chunks(kTileK)), dim3(256), 0, s, grp, 2.0);
     }
     for (int first = 0; first < n; first += kEnergyGroupMax) {
         EnergyGroup grp{};
@@ -1194,7 +1201,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
             grp.c[m] = reinterpret_cast<const double *>(scratch[i] + L.o_c);
             grp.naux[m] = L.naux_pad;
             grp.Epart[m] = reinterpret_cast<const double *>(scratch[i] + L.o_Epart);
-            grp.nEpart[m] = (int64_t)L.ntile * (L.ntile + 1) / 2 * (kTileK / 16);
+            grp.nEpart[m] = (int64_t)L.ntile * (L.ntile + 1) / 2 * reduce_chunks(kTileK);
             grp.E[m] = E[i];
         }
         hipLaunchKernelGGL(k_energies_grouped, dim3(m), dim3(256), 0, s, grp, -0.25);
@@ -1279,9 +1286,9 @@ void launch_build_hostB(Plan &p, const BuildLayout &L, const double *C, double *
     }
     pr.mark(ST_KREDUCE, true);
     const int nlower = L.ntile * (L.ntile + 1) / 2;
-    hipLaunchKernelGGL(k_k_reduce, dim3(nlower, L.ktile / 16), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
+    hipLaunchKernelGGL(k_k_reduce, dim3(nlower, reduce_chunks(L.ktile)), dim3(256), 0, s, Kpart, (int)(L.nslab * L.nsplit_k),
                        L.ntile, L.ktile, nao, 2.0, D, K, Epart);
-    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * (L.ktile / 16), -0.25,
+    hipLaunchKernelGGL(k_energies, dim3(1), dim3(256), 0, s, cvec, ld, Epart, (int64_t)nlower * reduce_chunks(L.ktile), -0.25,
                        E);
     pr.mark(ST_KREDUCE, false);
     pr.mark(ST_BUILD, false);
