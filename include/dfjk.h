@@ -488,8 +488,10 @@ int dfjk_boys(int32_t mmax, int64_t n, const double *d_T, double *d_F, void *str
  * dfjk_build (C or D route) from its first to its last launch on the caller's
  * stream: J runs on a side stream beside the half transform and K, so the
  * "build.*" stages of one build overlap and their sum exceeds the span.
- * "span.setup" is a whole dfjk_setup alike (the integrals run beside the
- * metric, its factor and inverse). */
+ * "span.setup" is a whole dfjk_setup alike: the integrals, then the block
+ * rows of L^-1, run on the side stream beside the metric and its factor, so
+ * "setup.inverse" is the span of the inverse's steps, most of it beside
+ * "setup.cholesky". */
 #define DFJK_NSTAGES 12
 int dfjk_profile(dfjk_plan *plan, int32_t on);
 int dfjk_profile_read(dfjk_plan *plan, double *ms, int32_t *count);

@@ -305,7 +305,11 @@ void launch_direct_pairs(const DirectClassDev *cls, const ShellsDev &ao, hipStre
 // linalg.hip
 void launch_metric_pad(double *V, int64_t n, int64_t npad, hipStream_t s);
 void launch_cholesky(double *A, int64_t npad, int32_t *status, double *Dinv, hipStream_t s);
-void launch_trtri(const double *L, double *Linv, double *Dinv, int64_t npad, hipStream_t s);
+void cholesky_step(double *A, int64_t npad, int64_t k, int32_t *status, double *Dinv, hipStream_t s);
+void launch_trtri(double *L, double *Linv, const double *Dinv, int64_t npad, hipStream_t s);
+void trtri_begin(double *X, int64_t npad, hipStream_t s);
+void trtri_step(const double *L, double *X, const double *Dinv, int64_t npad, int64_t i, hipStream_t s);
+void launch_zero_upper(double *L, int64_t npad, hipStream_t s);
 void launch_whiten(const double *U, const double *Linv, double *B, int64_t nf_pad, int64_t npad,
                    hipStream_t s);
 

@@ -121,36 +121,41 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double *A, int64_t ld, int64_
     for (int q = 0; q < NBK; ++q) Dk[q * NBK + t] = x[q];
 }
 
-void launch_cholesky(double *A, int64_t npad, int32_t *status, double *Dinv, hipStream_t s)
+// Step k of the blocked Cholesky: factor and invert the diagonal block,
+// form the panel below it, update the trailing matrix.
+void cholesky_step(double *A, int64_t npad, int64_t k, int32_t *status, double *Dinv, hipStream_t s)
 {
     const int64_t nb = npad / NBK;
-    for (int64_t k = 0; k < nb; ++k) {
-        const int64_t k0 = k * NBK;
-        double *Dk = Dinv + k * NBK * NBK;
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NBK), 0, s, A, npad, k0, status, Dk);
-        const int64_t rest = nb - k - 1;
-        if (rest == 0) break;
-        // panel: L21 = A21 L_kk^{-T} = A21 Dk^T on MFMA, in place (each output
-        // tile reads only its own 64 rows, wholly, before writing them)
-        GemmArgs pg{};
-        pg.A = A + (k0 + NBK) * npad + k0; pg.lda = npad;
-        pg.B = Dk; pg.ldb = NBK;
-        pg.C = A + (k0 + NBK) * npad + k0; pg.ldc = npad;
-        pg.M = rest * NBK; pg.N = NBK;
-        pg.k_begin = 0; pg.k_end = NBK; pg.ksplit = NBK;
-        pg.alpha = 1.0; pg.beta = 0.0;
-        gemm_f64<64, false>(pg, 1, s);
-        // A22 -= L21 L21^T on the lower tiles of the trailing matrix
-        GemmArgs g{};
-        const int64_t t0 = k0 + NBK;
-        g.A = A + t0 * npad + k0; g.lda = npad;
-        g.B = A + t0 * npad + k0; g.ldb = npad;
-        g.C = A + t0 * npad + t0; g.ldc = npad;
-        g.M = g.N = npad - t0;
-        g.k_begin = 0; g.k_end = NBK; g.ksplit = NBK;
-        g.alpha = -1.0; g.beta = 1.0; g.lower = 1;
-        gemm_f64<64, false>(g, 1, s);
-    }
+    const int64_t k0 = k * NBK;
+    double *Dk = Dinv + k * NBK * NBK;
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(NBK), 0, s, A, npad, k0, status, Dk);
+    const int64_t rest = nb - k - 1;
+    if (rest == 0) return;
+    // panel: L21 = A21 L_kk^{-T} = A21 Dk^T on MFMA, in place (each output
+    // tile reads only its own 64 rows, wholly, before writing them)
+    GemmArgs pg{};
+    pg.A = A + (k0 + NBK) * npad + k0; pg.lda = npad;
+    pg.B = Dk; pg.ldb = NBK;
+    pg.C = A + (k0 + NBK) * npad + k0; pg.ldc = npad;
+    pg.M = rest * NBK; pg.N = NBK;
+    pg.k_begin = 0; pg.k_end = NBK; pg.ksplit = NBK;
+    pg.alpha = 1.0; pg.beta = 0.0;
+    gemm_f64<64, false>(pg, 1, s);
+    // A22 -= L21 L21^T on the lower tiles of the trailing matrix
+    GemmArgs g{};
+    const int64_t t0 = k0 + NBK;
+    g.A = A + t0 * npad + k0; g.lda = npad;
+    g.B = A + t0 * npad + k0; g.ldb = npad;
+    g.C = A + t0 * npad + t0; g.ldc = npad;
+    g.M = g.N = npad - t0;
+    g.k_begin = 0; g.k_end = NBK; g.ksplit = NBK;
+    g.alpha = -1.0; g.beta = 1.0; g.lower = 1;
+    gemm_f64<64, false>(g, 1, s);
+}
+
+void launch_cholesky(double *A, int64_t npad, int32_t *status, double *Dinv, hipStream_t s)
+{
+    for (int64_t k = 0; k < npad / NBK; ++k) cholesky_step(A, npad, k, status, Dinv, s);
 }
 
 __global__ void k_zero_upper(double *A, int64_t npad)
@@ -167,82 +172,56 @@ __global__ void k_identity(double *A, int64_t npad)
     A[i] = (i % npad == i / npad) ? 1.0 : 0.0;
 }
 
-// D_k = L_kk^{-1} for every 64x64 diagonal block k (one workgroup each, all
-// at once; they are independent): column c of D_k by forward substitution
-// of e_c, one thread per column, the column in registers.  Right-looking:
-// x_l is final once divided by L_ll, and its column of L updates every later
-// row with independent FMAs.  L_kk sits transposed in LDS (row l holds column
-// l, 16-byte aligned rows), so each update reads two entries per broadcast.
-__global__ __launch_bounds__(64) void k_trinv_blocks(const double *L, int64_t ld, double *D)
-{
-    constexpr int LDT = NBK + 2;
-    __shared__ __align__(16) double LT[NBK * LDT];
-    const int tid = threadIdx.x;
-    const int64_t k0 = (int64_t)blockIdx.x * NBK;
-    for (int e = tid; e < NBK * NBK; e += NBK) {
-        const int r = e / NBK, l = e % NBK;
-        LT[l * LDT + r] = L[(k0 + r) * ld + k0 + l];
-    }
-    __syncthreads();
-    double x[NBK];
-#pragma unroll
-    for (int r = 0; r < NBK; ++r) x[r] = (r == tid) ? 1.0 : 0.0;
-#pragma unroll
-    for (int l = 0; l < NBK; ++l) {
-        const double *cl = LT + l * LDT;
-        x[l] = x[l] / cl[l];
-        int r0 = l + 1;
-        if ((r0 & 1) && r0 < NBK) {
-            x[r0] = fma(-cl[r0], x[l], x[r0]);
-            ++r0;
-        }
-#pragma unroll
-        for (int r = r0; r < NBK; r += 2) {
-            const double2 v = *reinterpret_cast<const double2 *>(cl + r);
-            x[r] = fma(-v.x, x[l], x[r]);
-            x[r + 1] = fma(-v.y, x[l], x[r + 1]);
-        }
-    }
-    double *Dk = D + (int64_t)blockIdx.x * NBK * NBK;
-#pragma unroll
-    for (int r = 0; r < NBK; ++r) Dk[r * NBK + tid] = x[r];
-}
-
-// X = L^{-1} by blocked forward substitution on the identity: for block row
-// i, X_i[0:w] <- D_i X_i[0:w] (w = (i+1) 64; an MFMA GEMM with the diagonal
-// block's inverse, in place: each output tile reads only its own 64 x 64
-// block of X_i, wholly, before writing it), then X[rows below][0:w] -=
-// L[rows below][block i] X_i[0:w].  The inverses of all diagonal blocks come
-// first in one launch (Dinv: npad x 64 doubles).
-void launch_trtri(const double *L, double *X, double *Dinv, int64_t npad, hipStream_t s)
+void launch_zero_upper(double *L, int64_t npad, hipStream_t s)
 {
     const int64_t tot = npad * npad;
-    hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                       const_cast<double *>(L), npad);
+    hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L, npad);
+}
+
+void trtri_begin(double *X, int64_t npad, hipStream_t s)
+{
+    const int64_t tot = npad * npad;
     hipLaunchKernelGGL(k_identity, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, npad);
+}
+
+// X = L^{-1} by blocked forward substitution on the identity, block row i at
+// a time: X_i[0:w] <- D_i X_i[0:w] (w = (i+1) 64, D_i = L_ii^{-1} from the
+// factor's diagonal step; an MFMA GEMM, in place: each output tile reads only
+// its own 64 x 64 block of X_i, wholly, before writing it), then
+// X[rows below][0:w] -= L[rows below][block i] X_i[0:w].  Step i reads only
+// what Cholesky steps 0..i have finished (D_i and the strictly lower column
+// block i of L), so it can follow step i on another stream.
+void trtri_step(const double *L, double *X, const double *Dinv, int64_t npad, int64_t i, hipStream_t s)
+{
     const int64_t nb = npad / NBK;
-    hipLaunchKernelGGL(k_trinv_blocks, dim3((unsigned)nb), dim3(NBK), 0, s, L, npad, Dinv);
-    for (int64_t i = 0; i < nb; ++i) {
-        const int64_t i0 = i * NBK, w = i0 + NBK;
-        GemmArgs d{};
-        d.A = Dinv + i * NBK * NBK; d.lda = NBK;
-        d.B = X + i0 * npad; d.ldb = npad;
-        d.C = X + i0 * npad; d.ldc = npad;
-        d.M = NBK; d.N = w;
-        d.k_begin = 0; d.k_end = NBK; d.ksplit = NBK;
-        d.alpha = 1.0; d.beta = 0.0;
-        gemm_f64<64, true>(d, 1, s);
-        if (i + 1 == nb) break;
-        // X[j rows > i][0:w] -= L[j rows][i cols] X[i rows][0:w]
-        GemmArgs g{};
-        g.A = L + w * npad + i0; g.lda = npad;
-        g.B = X + i0 * npad; g.ldb = npad;
-        g.C = X + w * npad; g.ldc = npad;
-        g.M = npad - w; g.N = w;
-        g.k_begin = 0; g.k_end = NBK; g.ksplit = NBK;
-        g.alpha = -1.0; g.beta = 1.0;
-        gemm_f64<64, true>(g, 1, s);
-    }
+    const int64_t i0 = i * NBK, w = i0 + NBK;
+    GemmArgs d{};
+    d.A = Dinv + i * NBK * NBK; d.lda = NBK;
+    d.B = X + i0 * npad; d.ldb = npad;
+    d.C = X + i0 * npad; d.ldc = npad;
+    d.M = NBK; d.N = w;
+    d.k_begin = 0; d.k_end = NBK; d.ksplit = NBK;
+    d.alpha = 1.0; d.beta = 0.0;
+    gemm_f64<64, true>(d, 1, s);
+    if (i + 1 == nb) return;
+    // X[j rows > i][0:w] -= L[j rows][i cols] X[i rows][0:w]
+    GemmArgs g{};
+    g.A = L + w * npad + i0; g.lda = npad;
+    g.B = X + i0 * npad; g.ldb = npad;
+    g.C = X + w * npad; g.ldc = npad;
+    g.M = npad - w; g.N = w;
+    g.k_begin = 0; g.k_end = NBK; g.ksplit = NBK;
+    g.alpha = -1.0; g.beta = 1.0;
+    gemm_f64<64, true>(g, 1, s);
+}
+
+// L^{-1} after the whole factor (Dinv as launch_cholesky left it); the upper
+// triangle of L is zeroed for the callers that read L itself.
+void launch_trtri(double *L, double *X, const double *Dinv, int64_t npad, hipStream_t s)
+{
+    launch_zero_upper(L, npad, s);
+    trtri_begin(X, npad, s);
+    for (int64_t i = 0; i < npad / NBK; ++i) trtri_step(L, X, Dinv, npad, i, s);
 }
 
 void launch_whiten(const double *U, const double *Linv, double *B, int64_t nf_pad, int64_t npad, hipStream_t s)
