@@ -102,6 +102,7 @@ __global__ void k_c_reduce(const double *__restrict__ cpart, int nsplit, int64_t
     const int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (P >= ld) return;
     double s = 0.0;
+#pragma unroll 8
     for (int k = 0; k < nsplit; ++k) s += cpart[k * ld + P];
     c[P] = s;
 }
@@ -491,6 +492,7 @@ __global__ __launch_bounds__(256) void k_k_reduce_delta(const double *__restrict
         const int64_t m = (int64_t)tm * kTileK + row, n = (int64_t)tn * kTileK + col;
         if (m >= nao || n >= nao || n > m) continue;
         double g1 = 0.0, g2 = 0.0;
+#pragma unroll 8
         for (int sp = 0; sp < nsplit; ++sp) {
             g1 += part[(sp * nt + tile_mn) * TT + row * kTileK + col];
             g2 += part[(sp * nt + tile_nm) * TT + col * kTileK + row];
