@@ -438,7 +438,10 @@ def test_setup_straight_into_host_memory(cluster5, slab):
     row blocks, each block's rows copied into the host slabs.  The host B
     equals the one dfjk_offload copies from a whole setup (every row of B is
     the same GEMM row), so builds in every precision are bitwise those of the
-    offloaded plan, and FP64 matches the oracle."""
+    offloaded plan, and FP64 matches the oracle.  The whole setup forms
+    L^-1 block row by block row on its side stream beside the factor, the
+    row-block setup after the whole factor: equal builds also show that
+    both orders give the same L^-1."""
     d = cluster5
     ref_plan = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU, aux_slab=slab).screen().setup().offload()
     plan = G.Plan.from_molecule(d["mol"], schwarz_thresh=TAU, aux_slab=slab).screen()
