@@ -3,7 +3,8 @@
 //     block is factored in registers by one wave, which also inverts it; the
 //     panel below is multiplied by that inverse and the trailing matrix
 //     updated, both on FP64 MFMA),
-//   - L^{-1} by blocked forward substitution on the identity,
+//   - L^{-1} by blocked forward substitution on the identity, block row by
+//     block row (row i needs only the factor steps up to i),
 //   - the whitening B = U L^{-T}-transposed product, i.e. B[f][P] =
 //     sum_{Q<=P} U[f][Q] Linv[P][Q], as one MFMA GEMM that stops each output
 //     tile's k loop at its last column (Linv is lower triangular).
@@ -96,7 +97,9 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double *A, int64_t ld, int64_
         LT[c * LDT + i] = v;          // L_kk transposed: row l holds column l
     }
     __syncthreads();
-    // Dk = L_kk^{-1}: column t by forward substitution of e_t (as k_trinv_blocks)
+    // Dk = L_kk^{-1}: column t by forward substitution of e_t, right-looking:
+    // x_l is final once divided by L_ll, and its column of L (a row of LT,
+    // 16-byte aligned) updates every later entry with independent FMAs
     const int t = i;
     double x[NBK];
 #pragma unroll
