@@ -179,6 +179,27 @@ int dfjk_screen(dfjk_plan *plan, void *d_scratch, size_t bytes, void *stream);
 int dfjk_setup_bytes(const dfjk_plan *plan, size_t *bytes);
 int dfjk_setup(dfjk_plan *plan, void *d_workspace, size_t bytes, void *stream);
 
+/* dfjk_setup of n screened plans (molecules of any sizes) in one call: the
+ * pair records and three-centre integrals of all of them run in shared
+ * launches, one per integral class (up to 16 molecules per launch, each
+ * workgroup finding its molecule by a prefix table passed by value), then
+ * each plan's metric, Cholesky factor, L^{-1} and whitening run on that
+ * plan's side stream, beside the other plans' (a chain of small launches
+ * each), joined back into `stream`.  Passage: as dfjk_setup; the packing of
+ * several molecules into one integral launch is this library's serving form,
+ * which the paper does not treat.  plans, d_workspaces, bytes: host arrays of
+ * n entries, workspace i as for dfjk_setup of plan i (dfjk_setup_bytes),
+ * borrowed alike.  Every plan ends bitwise as after its own dfjk_setup.  The
+ * stage profiler records nothing for this call.  Errors, before anything is
+ * enqueued: DFJK_E_INVALID (n < 1, a NULL array, pointer or workspace, or a
+ * plan given twice), DFJK_E_STATE (a plan not screened, offloaded, or
+ * screened on another device), DFJK_E_OOM (a workspace below its
+ * dfjk_setup_bytes); the message names the plan.  After the work:
+ * DFJK_E_NOT_POSDEF if a metric is not positive definite (the first such plan
+ * is named; the other plans are set up).  Synchronises `stream`. */
+int dfjk_setup_batch(int32_t n, dfjk_plan *const *plans, void *const *d_workspaces, const size_t *bytes,
+                     void *stream);
+
 /* One J/K build: J, K, E_J, E_K from the resident B and the current
  * orbitals or density, once per SCF iteration.  Passage: the tensor
  * contractions after the three-centre integrals, run on matrix units

@@ -39,6 +39,7 @@ SIGNATURES = {
     "dfjk_screen": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
     "dfjk_setup_bytes": (c_i32, [c_vp, ctypes.POINTER(c_sz)]),
     "dfjk_setup": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
+    "dfjk_setup_batch": (c_i32, [c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), ctypes.POINTER(c_sz), c_vp]),
     "dfjk_build_bytes": (c_i32, [c_vp, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "dfjk_build": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "dfjk_build_static": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),

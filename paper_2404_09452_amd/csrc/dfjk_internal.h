@@ -293,6 +293,8 @@ constexpr int kPairClassLa[6] = {0, 1, 1, 2, 2, 2}, kPairClassLb[6] = {0, 0, 1, 
 // offset (doubles) of each pair class's records, and the total
 void pair_rec_offsets(const Plan &p, int64_t off[7]);
 void launch_pair_records(const Plan &p, hipStream_t s);
+void launch_pair_records_plans(const Plan *const *plans, int n, hipStream_t s);
+void launch_int3c_plans(const Plan *const *plans, int n, hipStream_t s);
 void launch_int3c(const Plan &p, hipStream_t s);
 bool side_stream(Plan &p);   // jk.hip: p.j_stream with p.ev_jfork / p.ev_jdone
 void launch_int3c_rows(const Plan &p, double *U, int64_t f_base, int32_t i0, int32_t i1, hipStream_t s);

@@ -12,6 +12,9 @@
 // alpha = p g/(p+g).  The bra is taken to spherical form after the sums.
 // One thread evaluates one (shell pair, aux shell) triplet; a launch covers
 // one (la, lb, lc) class so every loop is unrolled at compile time.
+#include <array>
+#include <vector>
+
 #include "dfjk_internal.h"
 #include "hermite.h"
 
@@ -431,11 +434,10 @@ constexpr KetTerms<LC> ket_terms()
 // One thread per (pair, ma, mb) of the class's pairs p_begin..p_end (records
 // from rec, in pair order).
 template <int LA, int LB>
-__global__ __launch_bounds__(256) void k_pair_rec(Int3cArgs g, double *__restrict__ rec)
+__device__ __forceinline__ void pair_rec(const Int3cArgs &g, double *__restrict__ rec, int64_t tid)
 {
     constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NAB = NA * NB, LAB = LA + LB;
     constexpr int RS = pair_rec_doubles(LA, LB);
-    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (tid >= (int64_t)(g.p_end - g.p_begin) * NAB) return;
     const int pl = (int)(tid / NAB), ab = (int)(tid % NAB);
     const int ip = g.p_begin + pl;
@@ -464,6 +466,31 @@ __global__ __launch_bounds__(256) void k_pair_rec(Int3cArgs g, double *__restric
 #pragma unroll
             for (int v = 0; v + u + t <= LAB; ++v)
                 r[8 + hidx(t, u, v) * NAB + ab] = pref * (kFact[t] * kFact[u] * kFact[v]) * Es[hidx(t, u, v)];
+}
+
+template <int LA, int LB>
+__global__ __launch_bounds__(256) void k_pair_rec(Int3cArgs g, double *__restrict__ rec)
+{
+    pair_rec<LA, LB>(g, rec, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
+// The pair records of one class for several molecules in one launch
+// (workgroup b belongs to molecule m for blk_start[m] <= b < blk_start[m+1]).
+constexpr int kPairRecGroupMax = 14;
+struct PairRecGroup {
+    int32_t n;
+    uint32_t blk_start[kPairRecGroupMax + 1];
+    double *rec[kPairRecGroupMax];
+    Int3cArgs g[kPairRecGroupMax];
+};
+static_assert(sizeof(PairRecGroup) <= 4096, "kernel arguments are limited to 4 KB");
+
+template <int LA, int LB>
+__global__ __launch_bounds__(256) void k_pair_rec_group(PairRecGroup grp)
+{
+    int m = 0;
+    while (m + 1 < grp.n && blockIdx.x >= grp.blk_start[m + 1]) ++m;
+    pair_rec<LA, LB>(grp.g[m], grp.rec[m], (blockIdx.x - grp.blk_start[m]) * (int64_t)blockDim.x + threadIdx.x);
 }
 
 // Shared pieces of both lane layouts: the Taylor-scaled Hermite table G' of
@@ -541,7 +568,7 @@ __device__ __forceinline__ void bra_contract(const double *__restrict__ e, const
 // a shell in adjacent lanes, so every function-pair row is stored as one
 // contiguous run per wave.
 template <int LA, int LB, int LC>
-__global__ __launch_bounds__(256) void k_int3c(Int3cArgs g)
+__device__ __forceinline__ void int3c_cols(const Int3cArgs &g, unsigned blk)
 {
     constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1, NAB = NA * NB;
     constexpr int CC = ncart(LC), LAB = LA + LB;
@@ -549,7 +576,7 @@ __global__ __launch_bounds__(256) void k_int3c(Int3cArgs g)
     constexpr int RS = pair_rec_doubles(LA, LB);
     const int nsc = g.c_end - g.c_begin;
     const int ngrp = (nsc + SPB - 1) / SPB;
-    const int pl = (int)(blockIdx.x / ngrp), grp = (int)(blockIdx.x % ngrp);
+    const int pl = (int)(blk / ngrp), grp = (int)(blk % ngrp);
     const int ip = g.p_begin + pl;
     const double *__restrict__ rec = g.rec + (int64_t)(ip - g.rec_first) * RS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -578,21 +605,27 @@ __global__ __launch_bounds__(256) void k_int3c(Int3cArgs g)
     for (int i = 0; i < NAB; ++i) out[i * g.ld] = acc[i];
 }
 
+template <int LA, int LB, int LC>
+__global__ __launch_bounds__(256) void k_int3c(Int3cArgs g)
+{
+    int3c_cols<LA, LB, LC>(g, blockIdx.x);
+}
+
 // Lane per aux shell (classes with few outputs per triplet): the Boys
 // function, the Hermite table and the divisions are formed once per triplet
 // rather than once per m_c, every m_c is accumulated in registers, and each
 // function-pair row of the wave's 64 shells goes out through LDS as one
 // contiguous run of 64 (2 lc + 1) values.
+// buf: 4 x 64 (2 lc + 1) doubles of LDS, one run per wave.
 template <int LA, int LB, int LC>
-__global__ __launch_bounds__(256) void k_int3c_sh(Int3cArgs g)
+__device__ __forceinline__ void int3c_shells(const Int3cArgs &g, unsigned blk, double *buf)
 {
     constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NC = 2 * LC + 1, NAB = NA * NB;
     constexpr int CC = ncart(LC), LAB = LA + LB;
     constexpr int RS = pair_rec_doubles(LA, LB);
-    __shared__ double buf[4][64 * NC];
     const int nsc = g.c_end - g.c_begin;
     const int ngrp = (nsc + 255) / 256;
-    const int pl = (int)(blockIdx.x / ngrp), grp = (int)(blockIdx.x % ngrp);
+    const int pl = (int)(blk / ngrp), grp = (int)(blk % ngrp);
     const int ip = g.p_begin + pl;
     const double *__restrict__ rec = g.rec + (int64_t)(ip - g.rec_first) * RS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -622,7 +655,7 @@ __global__ __launch_bounds__(256) void k_int3c_sh(Int3cArgs g)
         }
     }
     double *row = g.U + ((int64_t)g.pf0[ip] - g.f_base) * g.ld + g.ax.off[g.c_begin + c0];
-    double *b = buf[wave];
+    double *b = buf + wave * 64 * NC;
 #pragma unroll
     for (int i = 0; i < NAB; ++i) {
 #pragma unroll
@@ -635,6 +668,13 @@ __global__ __launch_bounds__(256) void k_int3c_sh(Int3cArgs g)
         }
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+template <int LA, int LB, int LC>
+__global__ __launch_bounds__(256) void k_int3c_sh(Int3cArgs g)
+{
+    __shared__ double buf[4 * 64 * (2 * LC + 1)];
+    int3c_shells<LA, LB, LC>(g, blockIdx.x, buf);
 }
 
 template <int LA, int LB>
@@ -669,6 +709,67 @@ static void launch_class(Int3cArgs g, hipStream_t s)
         hipLaunchKernelGGL((k_int3c_sh<LA, LB, LC>), dim3((unsigned)nblk), dim3(256), 0, s, g);
     else
         hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)nblk), dim3(256), 0, s, g);
+}
+
+// Several molecules' triplets of one class in one launch: workgroup b runs
+// block b - blk_start[m] of molecule m (blk_start ascending), with that
+// molecule's arguments, so uneven molecules share the launch.  Descriptors
+// by value in the kernel arguments (no device table: the launch can be
+// captured).  Every element is the same computation as in a launch of its
+// own molecule, so the integrals are bitwise those of separate setups.
+constexpr int kInt3cGroupMax = 16;
+struct Int3cGroup {
+    int32_t n;
+    uint32_t blk_start[kInt3cGroupMax + 1];
+    Int3cArgs g[kInt3cGroupMax];
+};
+static_assert(sizeof(Int3cGroup) <= 4096, "kernel arguments are limited to 4 KB");
+
+template <int LA, int LB, int LC>
+__global__ __launch_bounds__(256) void k_int3c_group(Int3cGroup grp)
+{
+    int m = 0;
+    while (m + 1 < grp.n && blockIdx.x >= grp.blk_start[m + 1]) ++m;
+    const unsigned blk = blockIdx.x - grp.blk_start[m];
+    if constexpr (shell_lanes_for(LA, LB, LC)) {
+        __shared__ double buf[4 * 64 * (2 * LC + 1)];
+        int3c_shells<LA, LB, LC>(grp.g[m], blk, buf);
+    } else {
+        int3c_cols<LA, LB, LC>(grp.g[m], blk);
+    }
+}
+
+// Workgroups of one molecule's launch of the class (as launch_class).
+template <int LA, int LB, int LC>
+static int64_t class_blocks(const Int3cArgs &g)
+{
+    constexpr int SPB = shell_lanes_for(LA, LB, LC) ? 256 : 4 * (64 / (2 * LC + 1));
+    const int64_t npl = g.p_end - g.p_begin, nsc = g.c_end - g.c_begin;
+    if (npl <= 0 || nsc <= 0) return 0;
+    return npl * ((nsc + SPB - 1) / SPB);
+}
+
+template <int LA, int LB, int LC>
+static void launch_class_group(const Int3cArgs *args, int n, hipStream_t s)
+{
+    Int3cGroup grp{};
+    int64_t total = 0;
+    auto flush = [&]() {
+        if (grp.n == 0) return;
+        grp.blk_start[grp.n] = (uint32_t)total;
+        hipLaunchKernelGGL((k_int3c_group<LA, LB, LC>), dim3((unsigned)total), dim3(256), 0, s, grp);
+        grp = Int3cGroup{};
+        total = 0;
+    };
+    for (int i = 0; i < n; ++i) {
+        const int64_t nb = class_blocks<LA, LB, LC>(args[i]);
+        if (nb == 0) continue;
+        if (grp.n == kInt3cGroupMax || total + nb > (int64_t)UINT32_MAX / 2) flush();
+        grp.blk_start[grp.n] = (uint32_t)total;
+        grp.g[grp.n++] = args[i];
+        total += nb;
+    }
+    flush();
 }
 
 static ShellsDev ao_view(const Plan &p)
@@ -717,6 +818,60 @@ void launch_pair_records(const Plan &p, hipStream_t s)
     }
 }
 
+template <int LA, int LB>
+static void launch_pair_class_group(const Int3cArgs *args, double *const *recs, int n, hipStream_t s)
+{
+    constexpr int NAB = (2 * LA + 1) * (2 * LB + 1);
+    PairRecGroup grp{};
+    int64_t total = 0;
+    auto flush = [&]() {
+        if (grp.n == 0) return;
+        grp.blk_start[grp.n] = (uint32_t)total;
+        hipLaunchKernelGGL((k_pair_rec_group<LA, LB>), dim3((unsigned)total), dim3(256), 0, s, grp);
+        grp = PairRecGroup{};
+        total = 0;
+    };
+    for (int i = 0; i < n; ++i) {
+        const int64_t nb = ((int64_t)(args[i].p_end - args[i].p_begin) * NAB + 255) / 256;
+        if (nb <= 0) continue;
+        if (grp.n == kPairRecGroupMax) flush();
+        grp.blk_start[grp.n] = (uint32_t)total;
+        grp.rec[grp.n] = recs[i];
+        grp.g[grp.n++] = args[i];
+        total += nb;
+    }
+    flush();
+}
+
+// Pair records of several plans, each class of all plans in shared launches.
+void launch_pair_records_plans(const Plan *const *plans, int n, hipStream_t s)
+{
+    for (int pc = 0; pc < 6; ++pc) {
+        std::vector<Int3cArgs> args;
+        std::vector<double *> recs;
+        for (int i = 0; i < n; ++i) {
+            const Plan &p = *plans[i];
+            int64_t off[7];
+            pair_rec_offsets(p, off);
+            Int3cArgs g = int3c_args(p);
+            g.p_begin = p.sp_class[pc].begin; g.p_end = p.sp_class[pc].end;
+            if (g.p_end <= g.p_begin) continue;
+            args.push_back(g);
+            recs.push_back(p.d.pair_rec + off[pc]);
+        }
+        const int m = (int)args.size();
+        if (m == 0) continue;
+        switch (pc) {
+        case 0: launch_pair_class_group<0, 0>(args.data(), recs.data(), m, s); break;
+        case 1: launch_pair_class_group<1, 0>(args.data(), recs.data(), m, s); break;
+        case 2: launch_pair_class_group<1, 1>(args.data(), recs.data(), m, s); break;
+        case 3: launch_pair_class_group<2, 0>(args.data(), recs.data(), m, s); break;
+        case 4: launch_pair_class_group<2, 1>(args.data(), recs.data(), m, s); break;
+        default: launch_pair_class_group<2, 2>(args.data(), recs.data(), m, s); break;
+        }
+    }
+}
+
 void launch_int3c(const Plan &p, hipStream_t s)
 {
     launch_int3c_rows(p, p.d.U, 0, 0, (int32_t)p.sp_a.size(), s);
@@ -751,6 +906,48 @@ void launch_int3c_rows(const Plan &p, double *U, int64_t f_base, int32_t i0, int
 #undef CLS
         }
     }
+}
+
+// The three-centre integrals of several set-up-in-progress plans (their
+// pair records formed), every class's triplets of all plans in shared
+// launches (up to kInt3cGroupMax plans each).
+void launch_int3c_plans(const Plan *const *plans, int n, hipStream_t s)
+{
+    std::vector<Int3cArgs> args(n);
+    std::vector<std::array<int64_t, 7>> off(n);
+    for (int i = 0; i < n; ++i) {
+        pair_rec_offsets(*plans[i], off[i].data());
+        args[i] = int3c_args(*plans[i]);
+        args[i].U = plans[i]->d.U;
+        args[i].f_base = 0;
+    }
+    for (int pc = 0; pc < 6; ++pc)
+        for (int lc = 0; lc <= kMaxLAux; ++lc) {
+            std::vector<Int3cArgs> cls;
+            for (int i = 0; i < n; ++i) {
+                const Plan &p = *plans[i];
+                Int3cArgs g = args[i];
+                g.p_begin = p.sp_class[pc].begin; g.p_end = p.sp_class[pc].end;
+                g.c_begin = p.ax_class[lc].begin; g.c_end = p.ax_class[lc].end;
+                if (g.p_end <= g.p_begin || g.c_end <= g.c_begin) continue;
+                g.rec = p.d.pair_rec + off[i][pc];
+                g.rec_first = p.sp_class[pc].begin;
+                cls.push_back(g);
+            }
+            if (cls.empty()) continue;
+            const int key = kPairClassLa[pc] * 100 + kPairClassLb[pc] * 10 + lc;
+            const int m = (int)cls.size();
+#define CLS(A, B, C) case A * 100 + B * 10 + C: launch_class_group<A, B, C>(cls.data(), m, s); break;
+            switch (key) {
+                CLS(0, 0, 0) CLS(0, 0, 1) CLS(0, 0, 2) CLS(0, 0, 3)
+                CLS(1, 0, 0) CLS(1, 0, 1) CLS(1, 0, 2) CLS(1, 0, 3)
+                CLS(1, 1, 0) CLS(1, 1, 1) CLS(1, 1, 2) CLS(1, 1, 3)
+                CLS(2, 0, 0) CLS(2, 0, 1) CLS(2, 0, 2) CLS(2, 0, 3)
+                CLS(2, 1, 0) CLS(2, 1, 1) CLS(2, 1, 2) CLS(2, 1, 3)
+                CLS(2, 2, 0) CLS(2, 2, 1) CLS(2, 2, 2) CLS(2, 2, 3)
+            }
+#undef CLS
+        }
 }
 
 // --------------------------------------------------------------------------

@@ -473,6 +473,27 @@ class Plan:
             pass
 
 
+@_on_stream
+def setup_batch(plans, stream=None):
+    """dfjk_setup_batch: set up several screened plans in one call, the
+    integrals of all of them in shared launches per class and each plan's
+    factor chain beside the others'.  Each plan keeps its workspace as after
+    Plan.setup.  Returns the list of plans."""
+    plans = list(plans)
+    n = len(plans)
+    if n == 0:
+        return plans
+    for p in plans:
+        nbytes = p.setup_bytes()
+        if p._ws is None or p._ws.numel() < nbytes:
+            p._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    h = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+    w = (ctypes.c_void_p * n)(*[p._ws.data_ptr() for p in plans])
+    b = (ctypes.c_size_t * n)(*[p._ws.numel() for p in plans])
+    _check(N.lib().dfjk_setup_batch(n, h, w, b, _stream_handle(stream)))
+    return plans
+
+
 class Batch:
     """Closed-shell builds of several set-up plans in one dfjk_build_batch call:
     grouped K, reduction and energy launches across the molecules.  The scratch

@@ -86,6 +86,26 @@ def test_raw_abi_null_arguments():
     assert lib.dfjk_screen_bytes(None, ctypes.byref(n)) == 1
 
 
+def test_setup_batch_rejects_bad_input_without_device():
+    lib = N.lib()
+    plan = G.Plan.from_molecule(_water())
+    h = (ctypes.c_void_p * 2)(plan._h.value, plan._h.value)
+    w = (ctypes.c_void_p * 2)(8, 8)
+    b = (ctypes.c_size_t * 2)(1 << 20, 1 << 20)
+    assert lib.dfjk_setup_batch(0, h, w, b, None) == 1                    # INVALID: n < 1
+    assert lib.dfjk_setup_batch(1, None, w, b, None) == 1
+    assert lib.dfjk_setup_batch(1, h, None, b, None) == 1
+    assert lib.dfjk_setup_batch(1, h, w, None, None) == 1
+    nul = (ctypes.c_void_p * 1)(None)
+    assert lib.dfjk_setup_batch(1, nul, w, b, None) == 1
+    assert b"plan 0" in lib.dfjk_last_error()
+    assert lib.dfjk_setup_batch(2, h, w, b, None) == 7                    # STATE: not screened
+    assert b"plan 0" in lib.dfjk_last_error() and b"screened" in lib.dfjk_last_error()
+    with pytest.raises(G.DFJKError) as ei:
+        G.setup_batch([plan])
+    assert ei.value.status == "STATE"
+
+
 def test_call_order_is_enforced_without_device():
     plan = G.Plan.from_molecule(_water())
     lib = N.lib()

@@ -331,6 +331,41 @@ def test_batch_matches_single_builds(batch_set, prec):
         assert rel(outs[2][1].cpu().numpy(), ref["K"]) <= 1e-10
 
 
+def test_setup_batch_matches_single_setups(batch_set):
+    """dfjk_setup_batch on uneven molecules (1, 2, 3 and 5 waters) and on 18
+    plans (more than one grouped launch per integral class): the three-centre
+    integrals, the factor, B and the builds of every plan equal those of its
+    own dfjk_setup bitwise, and one molecule matches the oracle."""
+    cases, plans = batch_set
+    uniq, singles = cases[:4], plans[:4]
+    fresh = G.setup_batch([G.Plan.from_molecule(m, schwarz_thresh=TAU).screen() for m, _, _ in uniq])
+    for (mol, _, C), one, plan in zip(uniq, singles, fresh):
+        for kind in (G.EXPORT_INT3C, G.EXPORT_CHOL, G.EXPORT_B):
+            assert torch.equal(plan.export(kind), one.export(kind)), (mol.nao, kind)
+        for prec in ("fp64", "int8"):
+            J1, K1, E1 = (t.cpu().numpy() for t in one.build(C=C, precision=prec))
+            J2, K2, E2 = (t.cpu().numpy() for t in plan.build(C=C, precision=prec))
+            assert np.array_equal(J1, J2) and np.array_equal(K1, K2) and np.array_equal(E1, E2)
+    mol, _, C = uniq[2]
+    ref = oracle.dfjk(mol, C=C)
+    J, K, _ = (t.cpu().numpy() for t in fresh[2].build(C=C))
+    assert rel(K, ref["K"]) <= 1e-10 and rel(J, ref["J"]) <= 1e-10
+    many = G.setup_batch([G.Plan.from_molecule(uniq[i % 3][0], schwarz_thresh=TAU).screen() for i in range(18)])
+    for i, plan in enumerate(many):
+        assert torch.equal(plan.export(G.EXPORT_B), singles[i % 3].export(G.EXPORT_B)), i
+    for plan in fresh + many:
+        plan.close()
+
+
+def test_setup_batch_rejects_a_repeated_plan(batch_set):
+    _, plans = batch_set
+    p = G.Plan.from_molecule(batch_set[0][0][0], schwarz_thresh=TAU).screen()
+    with pytest.raises(G.DFJKError) as e:
+        G.setup_batch([p, p])
+    assert e.value.status == "INVALID" and "twice" in e.value.message
+    p.close()
+
+
 def test_batch_replays_in_a_hip_graph(batch_set):
     cases, plans = batch_set
     Cs = [torch.as_tensor(C, device="cuda") for _, _, C in cases]
