@@ -180,6 +180,82 @@ def direct_delta_bench(plan, C0, S, full_ms, nbuild):
     return out
 
 
+def batching_bench(nmol=16, reps=3, seed=7):
+    """Batching of uneven molecules: nmol water clusters of 1..12 molecules
+    (seeded sizes), set up one by one against one dfjk_setup_batch (pair
+    records and three-centre integrals of all molecules in shared launches),
+    then their FP64 builds one by one against one dfjk_build_batch (grouped
+    K, reductions and energies) and its HIP-graph replay.  Orbitals are
+    random orthonormal columns of nocc = 5 per water (only shapes matter to
+    the timing); batched results are checked against the single ones.  The
+    best of `reps` timings of each form."""
+    import numpy as np
+    import torch
+    import workload as W
+    from paper_2404_09452_amd import dfjk as G
+
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in rng.integers(1, 13, size=nmol)]
+    mols = []
+    for k, n in enumerate(sizes):
+        z, x = W.water_cluster(n, 4.0 + 1.5 * n ** (1.0 / 3.0), 100 + k) if n > 1 else W.water_monomer()
+        mols.append(W.make_molecule(z, x))
+    Cs = [torch.as_tensor(np.linalg.qr(rng.standard_normal((m.nao, m.nelec // 2)))[0], device="cuda")
+          for m in mols]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0), out
+
+    single_setup, batch_setup = [], []
+    plans = None
+    for _ in range(reps):
+        ps = [G.Plan.from_molecule(m, schwarz_thresh=1e-14).screen() for m in mols]
+        t, _ = timed(lambda: [p.setup() for p in ps])
+        single_setup.append(t)
+        pb = [G.Plan.from_molecule(m, schwarz_thresh=1e-14).screen() for m in mols]
+        t, _ = timed(lambda: G.setup_batch(pb))
+        batch_setup.append(t)
+        same_B = all(torch.equal(a.export(G.EXPORT_B), b.export(G.EXPORT_B)) for a, b in zip(ps, pb))
+        for p in ps:
+            p.close()
+        if plans is not None:
+            for p in plans:
+                p.close()
+        plans = pb
+    noccs = [C.shape[1] for C in Cs]
+    batch = G.Batch(plans, noccs)
+    outs = [(torch.empty((p.nao, p.nao), dtype=torch.float64, device="cuda"),
+             torch.empty((p.nao, p.nao), dtype=torch.float64, device="cuda"),
+             torch.empty(2, dtype=torch.float64, device="cuda")) for p in plans]
+    singles = [(torch.empty_like(o[0]), torch.empty_like(o[1]), torch.empty_like(o[2])) for o in outs]
+    single_build, batch_build, graph_build = [], [], []
+    for _ in range(reps + 1):   # the first pass warms up
+        t, _ = timed(lambda: [p.build(C=C, out=o) for p, C, o in zip(plans, Cs, singles)])
+        single_build.append(t)
+        t, _ = timed(lambda: batch.build(Cs, outs=outs))
+        batch_build.append(t)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.build(Cs, outs=outs)
+    for _ in range(reps):
+        t, _ = timed(g.replay)
+        graph_build.append(t)
+    dK = max(float((o[1] - q[1]).abs().max() / q[1].abs().max()) for o, q in zip(outs, singles))
+    for p in plans:
+        p.close()
+    return {"workload": "%d water clusters of 1-12 molecules (sizes %s), FP64" % (nmol, sizes),
+            "nao_total": int(sum(m.nao for m in mols)),
+            "setup_ms": {"one_by_one": round(min(single_setup), 2), "setup_batch": round(min(batch_setup), 2)},
+            "setup_B_bitwise_equal": bool(same_B),
+            "build_ms": {"one_by_one": round(min(single_build[1:]), 3), "build_batch": round(min(batch_build[1:]), 3),
+                         "build_batch_graph_replay": round(min(graph_build), 3)},
+            "max_rel_dK_batch_vs_single": dK}
+
+
 def make_inputs(n=32, box=10.0, geom_seed=1, cocc_seed=1):
     import workload as W
     z, x = W.water_cluster(n, box, geom_seed)
@@ -569,6 +645,9 @@ def main():
                     help="run only N setups of the 128-water cluster and print their stage times (for profiling "
                          "the integral kernels)")
     ap.add_argument("--no-direct", action="store_true", help="skip the four-centre direct J/K leg")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batching leg (setup and builds of 16 uneven molecules)")
+    ap.add_argument("--only-batching", action="store_true", help="run only the batching leg and print its JSON")
     ap.add_argument("--only-direct", action="store_true",
                     help="run only the four-centre direct J/K leg on the 32-water cluster and print its JSON")
     ap.add_argument("--direct-builds", type=int, default=5)
@@ -605,6 +684,9 @@ def main():
         return
     if args.only_large_setup:
         print(json.dumps({"water128_setup": large_setup_bench(args.only_large_setup)}))
+        return
+    if args.only_batching:
+        print(json.dumps({"batching": batching_bench()}))
         return
     if args.only_large:
         print(json.dumps({"water128": large_bench(args.large_builds)}))
@@ -749,6 +831,11 @@ def main():
         print("bench: four-centre direct J/K", file=sys.stderr, flush=True)
         direct = direct_bench(mol, Cd, nbuild=args.direct_builds, E_df=ref_E, S=S)
 
+    batching = None
+    if not args.no_batching:
+        print("bench: batching of uneven molecules", file=sys.stderr, flush=True)
+        batching = batching_bench()
+
     # split-count autotuner on the same molecule (outside the timed steps)
     tplan.setup()
     chosen, cand_ms = tplan.autotune(Cd[0])
@@ -800,6 +887,7 @@ def main():
         "serving": serving,
         "water128": large,
         "direct_scf": direct,
+        "batching": batching,
         "autotune_K_split": autotune,
         "roofline_by_step": by_step,
         "fp64_detail": {k: v for k, v in f64.items() if k not in ("E_J", "E_K")},

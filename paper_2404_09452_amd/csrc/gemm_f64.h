@@ -213,30 +213,6 @@ void k_gemm_f64(GemmArgs g)
     gemm_tile<T, WGM, WGN, NN>(g, blockIdx.x, blockIdx.y);
 }
 
-// Grouped form: up to kGemmGroupMax independent GEMMs (one per molecule of a
-// batch) in one launch.  Workgroup b belongs to GEMM p with
-// wg_start[p] <= b < wg_start[p + 1] and takes its (tile, split) from the
-// local index, tiles fastest.  The descriptors travel by value in the kernel
-// arguments, so the launch needs no device-side table (and can be captured).
-constexpr int kGemmGroupMax = 16;
-struct GemmGroup {
-    int32_t n;
-    int32_t wg_start[kGemmGroupMax + 1];
-    int32_t ntiles[kGemmGroupMax];
-    GemmArgs g[kGemmGroupMax];
-};
-
-template <int T, int WGM, int WGN, bool NN>
-__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(4)))
-void k_gemm_f64_grouped(GemmGroup grp)
-{
-    const int b = blockIdx.x;
-    int p = 0;
-    while (p + 1 < grp.n && b >= grp.wg_start[p + 1]) ++p;
-    const int local = b - grp.wg_start[p];
-    gemm_tile<T, WGM, WGN, NN>(grp.g[p], local % grp.ntiles[p], local / grp.ntiles[p]);
-}
-
 // T = 128 uses eight waves (4 x 2, 32x64 per wave) to keep four waves per
 // SIMD resident; T = 64 uses four waves (2 x 2).
 template <int T, bool NN>
@@ -250,31 +226,6 @@ inline void gemm_f64(GemmArgs g, int nsplit, hipStream_t s)
         hipLaunchKernelGGL((k_gemm_f64<128, 4, 2, NN>), dim3(ntiles, nsplit), dim3(512), 0, s, g);
     else
         hipLaunchKernelGGL((k_gemm_f64<64, 2, 2, NN>), dim3(ntiles, nsplit), dim3(256), 0, s, g);
-}
-
-// n GEMMs with 128-wide tiles (NT operand order), gs[i] split nsplit[i] ways
-// into its partial buffer, in launches of at most kGemmGroupMax GEMMs.
-inline void gemm_f64_grouped(const GemmArgs *gs, const int *nsplit, int n, hipStream_t s)
-{
-    for (int first = 0; first < n; first += kGemmGroupMax) {
-        GemmGroup grp{};
-        grp.n = 0;
-        int total = 0;
-        for (int i = first; i < n && grp.n < kGemmGroupMax; ++i) {
-            GemmArgs g = gs[i];
-            g.ntm = (int)((g.M + 127) / 128);
-            g.ntn = (int)((g.N + 127) / 128);
-            const int nt = g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntn;
-            grp.g[grp.n] = g;
-            grp.ntiles[grp.n] = nt;
-            grp.wg_start[grp.n] = total;
-            total += nt * nsplit[i];
-            ++grp.n;
-        }
-        grp.wg_start[grp.n] = total;
-        if (total > 0)
-            hipLaunchKernelGGL((k_gemm_f64_grouped<128, 4, 2, false>), dim3(total), dim3(512), 0, s, grp);
-    }
 }
 
 }  // namespace dfjk

@@ -89,6 +89,7 @@ __global__ __launch_bounds__(256) void k_c_partial(const double *__restrict__ B,
     if (f1 > nf_pad) f1 = nf_pad;
     double s0 = 0.0, s1 = 0.0;
     int64_t f = f0;
+#pragma unroll 4
     for (; f + 1 < f1; f += 2) {
         s0 += d[f] * B[f * ld + P];
         s1 += d[f + 1] * B[(f + 1) * ld + P];
@@ -1140,7 +1141,10 @@ int batch_nsplit(const Plan *const *plans, int n)
 void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const double *const *C, double *const *J,
                         double *const *K, double *const *E, char *const *scratch, hipStream_t s)
 {
-    std::vector<GemmArgs> gs;
+    std::vector<Plan *> joins;
+    std::vector<const double *> kx;
+    std::vector<double *> kp;
+    std::vector<int64_t> km, kk, ks;
     std::vector<int> ns;
     for (int i = 0; i < n; ++i) {
         Plan &p = *plans[i];
@@ -1153,29 +1157,37 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         hipLaunchKernelGGL(k_density, dim3((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16)), dim3(256), 0,
                            s, C[i], nao, (int32_t)L.ncol, 2.0, D);
         p.prof.mark(ST_DENSITY, false);
+        // J on the plan's side stream beside the other molecules' work,
+        // joined before the energies (the only later step that reads c)
+        hipStream_t js = s;
+        if (side_stream(p)) {
+            (void)hipEventRecord(p.ev_jfork, s);
+            (void)hipStreamWaitEvent(p.j_stream, p.ev_jfork, 0);
+            js = p.j_stream;
+            joins.push_back(&p);
+        }
+        p.prof.stream = js;
         p.prof.mark(ST_J, true);
-        launch_j(p, L, D, J[i], sc, s);
+        launch_j(p, L, D, J[i], sc, js);
         p.prof.mark(ST_J, false);
+        p.prof.stream = s;
+        if (js != s) (void)hipEventRecord(p.ev_jdone, js);
         if (L.nslab == 1 && L.precision == DFJK_FP64) {
             p.prof.mark(ST_HALFTRANS, true);
             const double *Cp = pad_coef(p, C[i], (int32_t)L.ncol, sc, L.o_Cp, s);
             launch_ht(p, DFJK_FP64, p.d.B, p.naux_pad, Cp, (int32_t)L.ncol, 0, p.naux_pad, sc + L.o_X, nullptr, s);
             p.prof.mark(ST_HALFTRANS, false);
-            GemmArgs g{};
-            g.A = reinterpret_cast<const double *>(sc + L.o_X); g.lda = L.kdim;
-            g.B = g.A; g.ldb = L.kdim;
-            g.M = g.N = nao;
-            g.k_begin = 0; g.k_end = L.kdim;
-            g.ksplit = align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16);
-            g.alpha = 1.0; g.lower = 1;
-            g.partial = reinterpret_cast<double *>(sc + L.o_Kpart);
-            gs.push_back(g);
+            kx.push_back(reinterpret_cast<const double *>(sc + L.o_X));
+            km.push_back(nao);
+            kk.push_back(L.kdim);
+            ks.push_back((int64_t)align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16));
             ns.push_back(L.nsplit_k);
+            kp.push_back(reinterpret_cast<double *>(sc + L.o_Kpart));
         } else {
             contract_slabs(p, L, C[i], nullptr, L.ncol, sc, s);
         }
     }
-    gemm_f64_grouped(gs.data(), ns.data(), (int)gs.size(), s);
+    launch_syrk_f64_group((int)kx.size(), kx.data(), km.data(), kk.data(), ks.data(), ns.data(), kp.data(), s);
     for (int first = 0; first < n; first += kReduceGroupMax) {
         ReduceGroup grp{};
         int total = 0;
@@ -1195,6 +1207,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         grp.blk_start[grp.n] = total;
         hipLaunchKernelGGL(k_k_reduce_grouped, dim3(total, reduce_chunks(kTileK)), dim3(256), 0, s, grp, 2.0);
     }
+    for (Plan *p : joins) (void)hipStreamWaitEvent(s, p->ev_jdone, 0);
     for (int first = 0; first < n; first += kEnergyGroupMax) {
         EnergyGroup grp{};
         int m = 0;

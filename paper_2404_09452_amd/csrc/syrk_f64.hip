@@ -48,10 +48,9 @@ struct SyrkArgs {
 // 11:8; a field at its maximum does not wait)
 template <int N> constexpr int wait_vm() { return (N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8); }
 
+// Workgroup `blk` of a launch over g (ntiles x nsplit workgroups).
 template <int T, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN)
-__attribute__((amdgpu_waves_per_eu(T == 64 ? 3 : 2)))
-void k_syrk_f64(SyrkArgs g)
+__device__ __forceinline__ void syrk_tile(SyrkArgs g, unsigned blk)
 {
     constexpr int NW = WGM * WGN;
     constexpr int WTM = T / WGM, WTN = T / WGN, MB = WTM / 16, NB = WTN / 16;
@@ -70,12 +69,12 @@ void k_syrk_f64(SyrkArgs g)
     // their panels in one L2 instead of every L2 fetching every panel.
     int tile, split;
     if (g.nsplit % kXcds == 0) {
-        const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+        const int xcd = blk % kXcds, local = blk / kXcds;
         split = xcd + kXcds * (local / ntiles);
         tile = local % ntiles;
     } else {
-        split = blockIdx.x / ntiles;
-        tile = blockIdx.x % ntiles;
+        split = blk / ntiles;
+        tile = blk % ntiles;
     }
     int tm, tn;
     if (g.lower) {
@@ -205,6 +204,36 @@ void k_syrk_f64(SyrkArgs g)
             }
 }
 
+template <int T, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(T == 64 ? 3 : 2)))
+void k_syrk_f64(SyrkArgs g)
+{
+    syrk_tile<T, WGM, WGN>(g, blockIdx.x);
+}
+
+// The K syrk of several molecules in one launch (batches of small
+// molecules): workgroup b runs workgroup b - blk_start[m] of molecule m's own
+// launch, descriptors by value (no device table, so the launch can be
+// captured).  Each molecule's partial tiles are those of its own launch.
+constexpr int kSyrkGroupMax = 16;
+struct SyrkGroup {
+    int32_t n;
+    uint32_t blk_start[kSyrkGroupMax + 1];
+    SyrkArgs g[kSyrkGroupMax];
+};
+static_assert(sizeof(SyrkGroup) <= 4096, "kernel arguments are limited to 4 KB");
+
+template <int T, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(T == 64 ? 3 : 2)))
+void k_syrk_f64_group(SyrkGroup grp)
+{
+    int m = 0;
+    while (m + 1 < grp.n && blockIdx.x >= grp.blk_start[m + 1]) ++m;
+    syrk_tile<T, WGM, WGN>(grp.g[m], blockIdx.x - grp.blk_start[m]);
+}
+
 }  // namespace
 
 // Split-K partial tiles of A B^T (A = B for the lower-tile syrk): M rows of
@@ -227,6 +256,39 @@ void launch_syrk_f64(bool lower, const double *A, const double *B, int64_t M, in
         hipLaunchKernelGGL((k_syrk_f64<96, 2, 2>), dim3(nwg), dim3(256), 0, s, g);
     else
         hipLaunchKernelGGL((k_syrk_f64<64, 2, 2>), dim3(nwg), dim3(256), 0, s, g);
+}
+
+// Lower-tile syrk partials of several molecules on 128-wide tiles, up to
+// kSyrkGroupMax per launch: molecule i has M[i] rows of X (A[i], kdim[i]
+// long), nsplit[i] splits of ksplit[i] (a multiple of 16) and its partials
+// at partial[i], laid out as launch_syrk_f64 lays them out.
+void launch_syrk_f64_group(int n, const double *const *A, const int64_t *M, const int64_t *kdim,
+                           const int64_t *ksplit, const int *nsplit, double *const *partial, hipStream_t s)
+{
+    SyrkGroup grp{};
+    int64_t total = 0;
+    auto flush = [&]() {
+        if (grp.n == 0) return;
+        grp.blk_start[grp.n] = (uint32_t)total;
+        hipLaunchKernelGGL((k_syrk_f64_group<128, 4, 2>), dim3((unsigned)total), dim3(512), 0, s, grp);
+        grp = SyrkGroup{};
+        total = 0;
+    };
+    for (int i = 0; i < n; ++i) {
+        SyrkArgs g{};
+        g.A = A[i]; g.B = A[i]; g.ld = kdim[i]; g.M = M[i]; g.N = M[i]; g.kdim = kdim[i]; g.ksplit = ksplit[i];
+        g.ntm = g.ntn = (int)((M[i] + 127) / 128);
+        g.lower = 1;
+        g.nsplit = nsplit[i];
+        g.partial = partial[i];
+        const int64_t nwg = (int64_t)g.ntm * (g.ntm + 1) / 2 * nsplit[i];
+        if (nwg <= 0) continue;
+        if (grp.n == kSyrkGroupMax || total + nwg > (int64_t)UINT32_MAX / 2) flush();
+        grp.blk_start[grp.n] = (uint32_t)total;
+        grp.g[grp.n++] = g;
+        total += nwg;
+    }
+    flush();
 }
 
 // C = A B^T with B lower triangular in (n, k) (B(n, k) = 0 for k > n), both
