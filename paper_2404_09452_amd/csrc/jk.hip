@@ -151,6 +151,7 @@ struct HTArgs {
     void *Xlo;                // second plane for the BF16 split; block scales for int8
     int64_t p_begin, plen;    // aux slab (multiples of 128)
     const int32_t *order;     // blockIdx.y -> AO function (longest list first)
+    int32_t nslice;           // int8 slices written (the rest of each chunk is left as it was)
 };
 
 
@@ -183,7 +184,8 @@ template <int NCOL> struct HtLds {
 // for non-negative doubles), e = the least exponent with 2^e > |x|max
 // 128/127, the scale 2^e to g.Xlo; then x 2^-e = sum_s a_s 2^{-7(s+1)} by
 // repeated rounding, every step exact in FP64 (a_0 = rint(128 x 2^-e) in
-// [-127, 127], later a_s in [-64, 64]).  The pad column stores zeros.
+// [-127, 127], later a_s in [-64, 64]); slices 0 .. nslice - 1 are stored
+// (four for int8_fast, whose K never reads a_4).  The pad column stores zeros.
 // Slicing runs from LDS, 32 aux rows at a time: the two waves that hold them
 // write their FP64 values to the first operand buffer in k order, then every
 // thread slices four consecutive k and stores one 4-byte word per slice, so
@@ -266,6 +268,7 @@ __device__ __forceinline__ void store_i8(const HTArgs &g, const f64x4 (&acc)[NIB
             unsigned char *d = dst + (k / kI8Chunk) * (kI8Chunk * kI8Slices) + (k % kI8Chunk);
 #pragma unroll
             for (int sl = 0; sl < kI8Slices; ++sl) {
+                if (sl >= g.nslice) break;
                 unsigned int word = 0;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -835,7 +838,7 @@ static void launch_ht(const Plan &p, int precision, const double *B, int64_t ld,
                       int64_t p_begin, int64_t plen, void *X, void *Xlo, hipStream_t s)
 {
     HTArgs h{B, ld, Cp, ncol, (int32_t)ht_ldc(ncol), p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen,
-             p.d.hk_order};
+             p.d.hk_order, precision == DFJK_MIXED_INT8_FAST ? kI8Slices - 1 : kI8Slices};
     dispatch_halftrans(precision, h, p.nao, s);
 }
 
