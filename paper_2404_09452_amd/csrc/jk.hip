@@ -300,8 +300,7 @@ constexpr int kHtWaitVm0 = 0 | (7 << 4) | (15 << 8);
 // chunk never waits on an index load.  The padded partner lists make every
 // chunk whole; the padded coefficients keep every 16-byte piece in bounds.
 template <int OUT, int NIB>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
-void k_halftrans(HTArgs g)
+__device__ __forceinline__ void halftrans_tile(HTArgs g, unsigned bx, unsigned by, unsigned bz)
 {
     constexpr int KC = kHtChunk, NCOL = NIB * 16;
     constexpr int LDA = HtLds<NCOL>::LDA, LDC = HtLds<NCOL>::LDC;
@@ -310,9 +309,9 @@ void k_halftrans(HTArgs g)
     // one from a DMA into the other and does not wait for unrelated loads
     __shared__ __attribute__((aligned(1024))) double sb0[HtLds<NCOL>::DOUBLES];
     __shared__ __attribute__((aligned(1024))) double sb1[HtLds<NCOL>::DOUBLES];
-    const int mu = g.order[blockIdx.y];
-    const int64_t p0 = g.p_begin + (int64_t)blockIdx.x * 128;
-    const int ic0 = blockIdx.z * NCOL;
+    const int mu = g.order[by];
+    const int64_t p0 = g.p_begin + (int64_t)bx * 128;
+    const int ic0 = bz * NCOL;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int kb = g.hk_off[mu], ke = g.hk_off[mu + 1];
@@ -408,6 +407,37 @@ void k_halftrans(HTArgs g)
     }
 }
 
+template <int OUT, int NIB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_halftrans(HTArgs g)
+{
+    halftrans_tile<OUT, NIB>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// FP64 half transforms of several molecules (the same fragment count) in one
+// launch: workgroup b runs workgroup b - blk_start[m] of molecule m's own
+// grid (gx P tiles fastest, then gy AO functions, then column passes), with
+// its arguments passed by value, so small molecules share the chip.
+constexpr int kHtGroupMax = 16;
+struct HtGroup {
+    int32_t n;
+    uint32_t blk_start[kHtGroupMax + 1];
+    uint32_t gx[kHtGroupMax], gy[kHtGroupMax];
+    HTArgs g[kHtGroupMax];
+};
+static_assert(sizeof(HtGroup) <= 4096, "kernel arguments are limited to 4 KB");
+
+template <int NIB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_halftrans_group(HtGroup grp)
+{
+    int m = 0;
+    while (m + 1 < grp.n && blockIdx.x >= grp.blk_start[m + 1]) ++m;
+    const unsigned local = blockIdx.x - grp.blk_start[m];
+    const unsigned bx = local % grp.gx[m], rest = local / grp.gx[m];
+    halftrans_tile<OUT_F64, NIB>(grp.g[m], bx, rest % grp.gy[m], rest / grp.gy[m]);
+}
+
 // Coefficients for the half transform: Cp[nao + 1][ldc] with C in the first
 // ncol columns of the first nao rows and zeros elsewhere.
 __global__ __launch_bounds__(256) void k_pad_coef(const double *__restrict__ C, int64_t nao, int32_t ncol,
@@ -433,6 +463,43 @@ static void launch_halftrans(const HTArgs &h, int64_t nao, hipStream_t s)
 #undef HT_CASE
 }
 static_assert(kHtMaxFrag == 10, "launch_halftrans instantiates 1..kHtMaxFrag fragments");
+
+// FP64 half transforms of several molecules: those with the same fragment
+// count share launches of k_halftrans_group (up to kHtGroupMax each).
+static void launch_halftrans_groups(const std::vector<std::pair<HTArgs, int64_t>> &hs, hipStream_t s)
+{
+    for (int nib = 1; nib <= kHtMaxFrag; ++nib) {
+        HtGroup grp{};
+        int64_t total = 0;
+        auto flush = [&]() {
+            if (grp.n == 0) return;
+            grp.blk_start[grp.n] = (uint32_t)total;
+#define HT_CASE(N) \
+    case N: hipLaunchKernelGGL((k_halftrans_group<N>), dim3((unsigned)total), dim3(512), 0, s, grp); break;
+            switch (nib) {
+                HT_CASE(1) HT_CASE(2) HT_CASE(3) HT_CASE(4) HT_CASE(5) HT_CASE(6) HT_CASE(7) HT_CASE(8)
+                HT_CASE(9) HT_CASE(10)
+            }
+#undef HT_CASE
+            grp = HtGroup{};
+            total = 0;
+        };
+        for (const auto &e : hs) {
+            const HTArgs &h = e.first;
+            if (ht_pass_frags(h.ncol) != nib) continue;
+            const int64_t gx = h.plen / 128, gy = e.second, gz = ht_passes(h.ncol);
+            const int64_t nb = gx * gy * gz;
+            if (nb <= 0) continue;
+            if (grp.n == kHtGroupMax || total + nb > (int64_t)UINT32_MAX / 2) flush();
+            grp.blk_start[grp.n] = (uint32_t)total;
+            grp.gx[grp.n] = (uint32_t)gx;
+            grp.gy[grp.n] = (uint32_t)gy;
+            grp.g[grp.n++] = h;
+            total += nb;
+        }
+        flush();
+    }
+}
 
 static void dispatch_halftrans(int precision, const HTArgs &h, int64_t nao, hipStream_t s)
 {
@@ -834,12 +901,17 @@ static const double *pad_coef(const Plan &p, const double *C, int32_t ncol, char
 }
 
 // Half transform of one aux slab of B (rows ld apart) with padded coefficients Cp.
+static HTArgs ht_args(const Plan &p, int precision, const double *B, int64_t ld, const double *Cp, int32_t ncol,
+                      int64_t p_begin, int64_t plen, void *X, void *Xlo)
+{
+    return HTArgs{B, ld, Cp, ncol, (int32_t)ht_ldc(ncol), p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen,
+                  p.d.hk_order, precision == DFJK_MIXED_INT8_FAST ? kI8Slices - 1 : kI8Slices};
+}
+
 static void launch_ht(const Plan &p, int precision, const double *B, int64_t ld, const double *Cp, int32_t ncol,
                       int64_t p_begin, int64_t plen, void *X, void *Xlo, hipStream_t s)
 {
-    HTArgs h{B, ld, Cp, ncol, (int32_t)ht_ldc(ncol), p.d.hk_off, p.d.hk_row, p.d.hk_nu, X, Xlo, p_begin, plen,
-             p.d.hk_order, precision == DFJK_MIXED_INT8_FAST ? kI8Slices - 1 : kI8Slices};
-    dispatch_halftrans(precision, h, p.nao, s);
+    dispatch_halftrans(precision, ht_args(p, precision, B, ld, Cp, ncol, p_begin, plen, X, Xlo), p.nao, s);
 }
 
 // Steps 5-6 for every aux slab: the half transform of C1 (and of C2 for the
@@ -1145,6 +1217,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
                         double *const *K, double *const *E, char *const *scratch, hipStream_t s)
 {
     std::vector<Plan *> joins;
+    std::vector<std::pair<HTArgs, int64_t>> hts;   // arguments and AO count of each grouped half transform
     std::vector<const double *> kx;
     std::vector<double *> kp;
     std::vector<int64_t> km, kk, ks;
@@ -1176,10 +1249,10 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         p.prof.stream = s;
         if (js != s) (void)hipEventRecord(p.ev_jdone, js);
         if (L.nslab == 1 && L.precision == DFJK_FP64) {
-            p.prof.mark(ST_HALFTRANS, true);
             const double *Cp = pad_coef(p, C[i], (int32_t)L.ncol, sc, L.o_Cp, s);
-            launch_ht(p, DFJK_FP64, p.d.B, p.naux_pad, Cp, (int32_t)L.ncol, 0, p.naux_pad, sc + L.o_X, nullptr, s);
-            p.prof.mark(ST_HALFTRANS, false);
+            hts.emplace_back(ht_args(p, DFJK_FP64, p.d.B, p.naux_pad, Cp, (int32_t)L.ncol, 0, p.naux_pad,
+                                     sc + L.o_X, nullptr),
+                             nao);
             kx.push_back(reinterpret_cast<const double *>(sc + L.o_X));
             km.push_back(nao);
             kk.push_back(L.kdim);
@@ -1190,6 +1263,8 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
             contract_slabs(p, L, C[i], nullptr, L.ncol, sc, s);
         }
     }
+    // the half transforms of the one-slab FP64 molecules, grouped by fragment count
+    launch_halftrans_groups(hts, s);
     launch_syrk_f64_group((int)kx.size(), kx.data(), km.data(), kk.data(), ks.data(), ns.data(), kp.data(), s);
     for (int first = 0; first < n; first += kReduceGroupMax) {
         ReduceGroup grp{};
