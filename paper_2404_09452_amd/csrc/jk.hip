@@ -132,6 +132,179 @@ __global__ __launch_bounds__(256) void k_j_rows(const double *__restrict__ B, in
 }
 
 // ---------------------------------------------------------------------------
+// The same steps (density, zero-padded coefficients, J) for the molecules of a
+// batch in shared launches, one per step: workgroup b of a step belongs to
+// molecule m for blk_start[m] <= b < blk_start[m + 1] and runs what block
+// b - blk_start[m] of that molecule's own launch runs, with the same
+// arithmetic per element, so J and c are bitwise those of separate builds.
+struct PreArgs {
+    const double *C;          // nao x nocc orbitals
+    double *D, *Cp, *J;       // density (2 C C^T), padded coefficients, J
+    const int32_t *f_mu, *f_nu;
+    const double *f_w, *B;
+    double *dvec, *cpart, *cvec;
+    int64_t nao, nf, nf_pad, ld;
+    int32_t nocc, ldc, nsplit_c, pad_;
+};
+constexpr int kPreGroupMax = 16;
+struct PreGroup {
+    int32_t n;
+    uint32_t blk_start[kPreGroupMax + 1];
+    PreArgs a[kPreGroupMax];
+};
+static_assert(sizeof(PreGroup) <= 4096, "kernel arguments are limited to 4 KB");
+enum { PRE_DENSITY, PRE_PAD, PRE_FILL_J, PRE_GATHER, PRE_CPART, PRE_CREDUCE, PRE_JROWS, PRE_STEPS };
+
+__device__ __forceinline__ int pre_member(const PreGroup &g, unsigned &local)
+{
+    int m = 0;
+    while (m + 1 < g.n && blockIdx.x >= g.blk_start[m + 1]) ++m;
+    local = blockIdx.x - g.blk_start[m];
+    return m;
+}
+
+// Workgroups of step `st` for one molecule (its own launch's grid, flattened
+// x fastest).
+static int64_t pre_blocks(int st, const PreArgs &a)
+{
+    switch (st) {
+    case PRE_DENSITY: { const int64_t g = (a.nao + 15) / 16; return g * g; }
+    case PRE_PAD: return ((a.nao + 1) * a.ldc + 255) / 256;
+    case PRE_FILL_J: return (a.nao * a.nao + 255) / 256;
+    case PRE_GATHER: return (a.nf_pad + 255) / 256;
+    case PRE_CPART: return ((a.ld + 255) / 256) * a.nsplit_c;
+    case PRE_CREDUCE: return (a.ld + 255) / 256;
+    default: return (a.nf + 3) / 4;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_density_group(PreGroup g)
+{
+    unsigned local;
+    const PreArgs &a = g.a[pre_member(g, local)];
+    const unsigned gx = (unsigned)((a.nao + 15) / 16);
+    __shared__ double Ca[16][65], Cb[16][65];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t m0 = (int64_t)(local / gx) * 16, n0 = (int64_t)(local % gx) * 16;
+    const int64_t nao = a.nao;
+    const int nocc = a.nocc;
+    double s = 0.0;
+    for (int i0 = 0; i0 < nocc; i0 += 64) {
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int r = e / 64, c = e % 64;
+            const bool ok = i0 + c < nocc;
+            Ca[r][c] = (ok && m0 + r < nao) ? a.C[(m0 + r) * nocc + i0 + c] : 0.0;
+            Cb[r][c] = (ok && n0 + r < nao) ? a.C[(n0 + r) * nocc + i0 + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c) s += Ca[ty][c] * Cb[tx][c];
+        __syncthreads();
+    }
+    if (m0 + ty < nao && n0 + tx < nao) a.D[(m0 + ty) * nao + n0 + tx] = 2.0 * s;
+}
+
+__global__ __launch_bounds__(256) void k_pad_fill_group(PreGroup g, int step)
+{
+    unsigned local;
+    const PreArgs &a = g.a[pre_member(g, local)];
+    const int64_t i = (int64_t)local * 256 + threadIdx.x;
+    if (step == PRE_PAD) {
+        if (i >= (a.nao + 1) * a.ldc) return;
+        const int64_t r = i / a.ldc, c = i % a.ldc;
+        a.Cp[i] = (r < a.nao && c < a.nocc) ? a.C[r * a.nocc + c] : 0.0;
+    } else if (step == PRE_FILL_J) {
+        if (i < a.nao * a.nao) a.J[i] = 0.0;
+    } else {   // PRE_GATHER
+        if (i >= a.nf_pad) return;
+        a.dvec[i] = (i < a.nf) ? a.f_w[i] * a.D[(int64_t)a.f_mu[i] * a.nao + a.f_nu[i]] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_c_partial_group(PreGroup g)
+{
+    unsigned local;
+    const PreArgs &a = g.a[pre_member(g, local)];
+    const unsigned gx = (unsigned)((a.ld + 255) / 256);
+    const int64_t P = (int64_t)(local % gx) * 256 + threadIdx.x;
+    const int64_t split = local / gx, ld = a.ld;
+    if (P >= ld) return;
+    const int64_t f0 = split * kCSplitRows;
+    int64_t f1 = f0 + kCSplitRows;
+    if (f1 > a.nf_pad) f1 = a.nf_pad;
+    const double *__restrict__ d = a.dvec;
+    const double *__restrict__ B = a.B;
+    double s0 = 0.0, s1 = 0.0;
+    int64_t f = f0;
+#pragma unroll 4
+    for (; f + 1 < f1; f += 2) {
+        s0 += d[f] * B[f * ld + P];
+        s1 += d[f + 1] * B[(f + 1) * ld + P];
+    }
+    if (f < f1) s0 += d[f] * B[f * ld + P];
+    a.cpart[split * ld + P] = s0 + s1;
+}
+
+__global__ __launch_bounds__(256) void k_c_reduce_group(PreGroup g)
+{
+    unsigned local;
+    const PreArgs &a = g.a[pre_member(g, local)];
+    const int64_t P = (int64_t)local * 256 + threadIdx.x;
+    if (P >= a.ld) return;
+    double s = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < a.nsplit_c; ++k) s += a.cpart[k * a.ld + P];
+    a.cvec[P] = s;
+}
+
+__global__ __launch_bounds__(256) void k_j_rows_group(PreGroup g)
+{
+    unsigned local;
+    const PreArgs &a = g.a[pre_member(g, local)];
+    const int64_t f = (int64_t)local * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (f >= a.nf) return;
+    const double *row = a.B + f * a.ld;
+    double s = 0.0;
+    for (int64_t P = lane; P < a.ld; P += 64) s += row[P] * a.cvec[P];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        const int64_t mu = a.f_mu[f], nu = a.f_nu[f];
+        a.J[mu * a.nao + nu] = s;
+        if (a.f_w[f] > 1.5) a.J[nu * a.nao + mu] = s;
+    }
+}
+
+// The steps in order, each as shared launches of up to kPreGroupMax molecules.
+static void launch_pre_groups(const std::vector<PreArgs> &as, hipStream_t s)
+{
+    for (int st = 0; st < PRE_STEPS; ++st) {
+        for (size_t first = 0; first < as.size(); first += kPreGroupMax) {
+            PreGroup g{};
+            int64_t total = 0;
+            for (size_t i = first; i < as.size() && g.n < kPreGroupMax; ++i) {
+                g.blk_start[g.n] = (uint32_t)total;
+                g.a[g.n++] = as[i];
+                total += pre_blocks(st, as[i]);
+            }
+            g.blk_start[g.n] = (uint32_t)total;
+            if (total <= 0) continue;
+            const dim3 grid((unsigned)total), block(256);
+            switch (st) {
+            case PRE_DENSITY: hipLaunchKernelGGL(k_density_group, grid, block, 0, s, g); break;
+            case PRE_PAD:
+            case PRE_FILL_J:
+            case PRE_GATHER: hipLaunchKernelGGL(k_pad_fill_group, grid, block, 0, s, g, st); break;
+            case PRE_CPART: hipLaunchKernelGGL(k_c_partial_group, grid, block, 0, s, g); break;
+            case PRE_CREDUCE: hipLaunchKernelGGL(k_c_reduce_group, grid, block, 0, s, g); break;
+            default: hipLaunchKernelGGL(k_j_rows_group, grid, block, 0, s, g); break;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Half transform.  MFMA operands: A = B[row_k][P] (lane: P = l%16,
 // k = l/16), B = Cs[k][i] (lane: k = l/16, i = l%16); accumulator r holds
 // row P = l/16 + 4r.
@@ -1217,6 +1390,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
                         double *const *K, double *const *E, char *const *scratch, hipStream_t s)
 {
     std::vector<Plan *> joins;
+    std::vector<PreArgs> pre;
     std::vector<std::pair<HTArgs, int64_t>> hts;   // arguments and AO count of each grouped half transform
     std::vector<const double *> kx;
     std::vector<double *> kp;
@@ -1228,6 +1402,30 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         char *sc = scratch[i];
         const int64_t nao = p.nao;
         double *D = reinterpret_cast<double *>(sc + L.o_D);
+        if (L.nslab == 1 && L.precision == DFJK_FP64) {
+            // density, padded coefficients and J in the shared launches of
+            // launch_pre_groups, the half transform and K grouped after them
+            PreArgs a{};
+            a.C = C[i]; a.D = D; a.J = J[i];
+            a.Cp = reinterpret_cast<double *>(sc + L.o_Cp);
+            a.f_mu = p.d.f_mu; a.f_nu = p.d.f_nu; a.f_w = p.d.f_w; a.B = p.d.B;
+            a.dvec = reinterpret_cast<double *>(sc + L.o_d);
+            a.cpart = reinterpret_cast<double *>(sc + L.o_cpart);
+            a.cvec = reinterpret_cast<double *>(sc + L.o_c);
+            a.nao = nao; a.nf = p.nf; a.nf_pad = p.nf_pad; a.ld = p.naux_pad;
+            a.nocc = (int32_t)L.ncol; a.ldc = (int32_t)ht_ldc(L.ncol); a.nsplit_c = L.nsplit_c;
+            pre.push_back(a);
+            hts.emplace_back(ht_args(p, DFJK_FP64, p.d.B, p.naux_pad, a.Cp, (int32_t)L.ncol, 0, p.naux_pad,
+                                     sc + L.o_X, nullptr),
+                             nao);
+            kx.push_back(reinterpret_cast<const double *>(sc + L.o_X));
+            km.push_back(nao);
+            kk.push_back(L.kdim);
+            ks.push_back((int64_t)align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16));
+            ns.push_back(L.nsplit_k);
+            kp.push_back(reinterpret_cast<double *>(sc + L.o_Kpart));
+            continue;
+        }
         p.prof.stream = s;
         p.prof.mark(ST_DENSITY, true);
         hipLaunchKernelGGL(k_density, dim3((unsigned)((nao + 15) / 16), (unsigned)((nao + 15) / 16)), dim3(256), 0,
@@ -1248,21 +1446,9 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         p.prof.mark(ST_J, false);
         p.prof.stream = s;
         if (js != s) (void)hipEventRecord(p.ev_jdone, js);
-        if (L.nslab == 1 && L.precision == DFJK_FP64) {
-            const double *Cp = pad_coef(p, C[i], (int32_t)L.ncol, sc, L.o_Cp, s);
-            hts.emplace_back(ht_args(p, DFJK_FP64, p.d.B, p.naux_pad, Cp, (int32_t)L.ncol, 0, p.naux_pad,
-                                     sc + L.o_X, nullptr),
-                             nao);
-            kx.push_back(reinterpret_cast<const double *>(sc + L.o_X));
-            km.push_back(nao);
-            kk.push_back(L.kdim);
-            ks.push_back((int64_t)align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16));
-            ns.push_back(L.nsplit_k);
-            kp.push_back(reinterpret_cast<double *>(sc + L.o_Kpart));
-        } else {
-            contract_slabs(p, L, C[i], nullptr, L.ncol, sc, s);
-        }
+        contract_slabs(p, L, C[i], nullptr, L.ncol, sc, s);
     }
+    launch_pre_groups(pre, s);
     // the half transforms of the one-slab FP64 molecules, grouped by fragment count
     launch_halftrans_groups(hts, s);
     launch_syrk_f64_group((int)kx.size(), kx.data(), km.data(), kk.data(), ks.data(), ns.data(), kp.data(), s);
