@@ -379,7 +379,7 @@ void launch_density(const double *C, int64_t nao, int32_t nocc, double scale, do
 // A B^T, lower tiles or every tile, T = 64 or 128
 void launch_syrk_f64(bool lower, const double *A, const double *B, int64_t M, int64_t kdim, int64_t ksplit,
                      int nsplit, int T, double *partial, hipStream_t s);
-void launch_syrk_f64_group(int n, const double *const *A, const int64_t *M, const int64_t *kdim,
+void launch_syrk_f64_group(int T, int n, const double *const *A, const int64_t *M, const int64_t *kdim,
                            const int64_t *ksplit, const int *nsplit, double *const *partial, hipStream_t s);
 void launch_gemm_nt_tri(const double *A, const double *B, double *C, int64_t M, int64_t N, int64_t ld,
                         hipStream_t s);

@@ -815,13 +815,15 @@ __global__ __launch_bounds__(256) void k_k_reduce(const double *__restrict__ par
     reduce_tile(part, nsplit, ntm, T, nao, scale, D, K, Epart, blockIdx.x, blockIdx.y);
 }
 
-// Grouped reduction for a batch: blocks blk_start[p] .. blk_start[p+1]-1 (times
-// reduce_chunks(kTileK) chunks in y) reduce molecule p.  Descriptors by value.
+// Grouped reduction for a batch: blocks blk_start[p] .. blk_start[p+1]-1 reduce
+// molecule p, whose tiles are T[p] wide; the grid has reduce_chunks(kTileK)
+// chunks in y (the most any width needs) and molecule p uses the first
+// reduce_chunks(T[p]).  Descriptors by value.
 constexpr int kReduceGroupMax = 16;
 struct ReduceGroup {
     int32_t n;
     int32_t blk_start[kReduceGroupMax + 1];
-    int32_t nsplit[kReduceGroupMax], ntm[kReduceGroupMax];
+    int32_t nsplit[kReduceGroupMax], ntm[kReduceGroupMax], T[kReduceGroupMax];
     int64_t nao[kReduceGroupMax];
     const double *part[kReduceGroupMax], *D[kReduceGroupMax];
     double *K[kReduceGroupMax], *Epart[kReduceGroupMax];
@@ -832,8 +834,9 @@ __global__ __launch_bounds__(256) void k_k_reduce_grouped(ReduceGroup grp, doubl
     const int b = blockIdx.x;
     int p = 0;
     while (p + 1 < grp.n && b >= grp.blk_start[p + 1]) ++p;
-    reduce_tile(grp.part[p], grp.nsplit[p], grp.ntm[p], kTileK, grp.nao[p], scale, grp.D[p], grp.K[p], grp.Epart[p],
-                b - grp.blk_start[p], blockIdx.y);
+    if ((int)blockIdx.y >= reduce_chunks(grp.T[p])) return;   // past this molecule's rows
+    reduce_tile(grp.part[p], grp.nsplit[p], grp.ntm[p], grp.T[p], grp.nao[p], scale, grp.D[p], grp.K[p],
+                grp.Epart[p], b - grp.blk_start[p], blockIdx.y);
 }
 
 __device__ __forceinline__ void energies_body(const double *__restrict__ c, int64_t naux,
@@ -1395,7 +1398,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
     std::vector<const double *> kx;
     std::vector<double *> kp;
     std::vector<int64_t> km, kk, ks;
-    std::vector<int> ns;
+    std::vector<int> ns, kt;
     for (int i = 0; i < n; ++i) {
         Plan &p = *plans[i];
         const BuildLayout &L = Ls[i];
@@ -1423,6 +1426,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
             kk.push_back(L.kdim);
             ks.push_back((int64_t)align_up((size_t)((L.kdim + L.nsplit_k - 1) / L.nsplit_k), 16));
             ns.push_back(L.nsplit_k);
+            kt.push_back(L.ktile);
             kp.push_back(reinterpret_cast<double *>(sc + L.o_Kpart));
             continue;
         }
@@ -1451,7 +1455,20 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
     launch_pre_groups(pre, s);
     // the half transforms of the one-slab FP64 molecules, grouped by fragment count
     launch_halftrans_groups(hts, s);
-    launch_syrk_f64_group((int)kx.size(), kx.data(), km.data(), kk.data(), ks.data(), ns.data(), kp.data(), s);
+    for (int T : {64, 96, 128}) {   // one grouped syrk per tile width
+        std::vector<const double *> gx;
+        std::vector<double *> gp;
+        std::vector<int64_t> gm, gk, gs;
+        std::vector<int> gn;
+        for (size_t i = 0; i < kx.size(); ++i)
+            if (kt[i] == T) {
+                gx.push_back(kx[i]); gp.push_back(kp[i]); gm.push_back(km[i]); gk.push_back(kk[i]);
+                gs.push_back(ks[i]); gn.push_back(ns[i]);
+            }
+        if (!gx.empty())
+            launch_syrk_f64_group(T, (int)gx.size(), gx.data(), gm.data(), gk.data(), gs.data(), gn.data(),
+                                  gp.data(), s);
+    }
     for (int first = 0; first < n; first += kReduceGroupMax) {
         ReduceGroup grp{};
         int total = 0;
@@ -1461,6 +1478,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
             grp.blk_start[q] = total;
             grp.nsplit[q] = (int32_t)(L.nslab * L.nsplit_k);
             grp.ntm[q] = L.ntile;
+            grp.T[q] = L.ktile;
             grp.nao[q] = L.nao;
             grp.part[q] = reinterpret_cast<const double *>(scratch[i] + L.o_Kpart);
             grp.D[q] = reinterpret_cast<const double *>(scratch[i] + L.o_D);
@@ -1480,7 +1498,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
             grp.c[m] = reinterpret_cast<const double *>(scratch[i] + L.o_c);
             grp.naux[m] = L.naux_pad;
             grp.Epart[m] = reinterpret_cast<const double *>(scratch[i] + L.o_Epart);
-            grp.nEpart[m] = (int64_t)L.ntile * (L.ntile + 1) / 2 * reduce_chunks(kTileK);
+            grp.nEpart[m] = (int64_t)L.ntile * (L.ntile + 1) / 2 * reduce_chunks(L.ktile);
             grp.E[m] = E[i];
         }
         hipLaunchKernelGGL(k_energies_grouped, dim3(m), dim3(256), 0, s, grp, -0.25);

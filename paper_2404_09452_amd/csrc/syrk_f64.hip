@@ -258,11 +258,11 @@ void launch_syrk_f64(bool lower, const double *A, const double *B, int64_t M, in
         hipLaunchKernelGGL((k_syrk_f64<64, 2, 2>), dim3(nwg), dim3(256), 0, s, g);
 }
 
-// Lower-tile syrk partials of several molecules on 128-wide tiles, up to
-// kSyrkGroupMax per launch: molecule i has M[i] rows of X (A[i], kdim[i]
+// Lower-tile syrk partials of several molecules on T-wide tiles (64, 96 or
+// 128), up to kSyrkGroupMax per launch: molecule i has M[i] rows of X (A[i], kdim[i]
 // long), nsplit[i] splits of ksplit[i] (a multiple of 16) and its partials
 // at partial[i], laid out as launch_syrk_f64 lays them out.
-void launch_syrk_f64_group(int n, const double *const *A, const int64_t *M, const int64_t *kdim,
+void launch_syrk_f64_group(int T, int n, const double *const *A, const int64_t *M, const int64_t *kdim,
                            const int64_t *ksplit, const int *nsplit, double *const *partial, hipStream_t s)
 {
     SyrkGroup grp{};
@@ -270,14 +270,19 @@ void launch_syrk_f64_group(int n, const double *const *A, const int64_t *M, cons
     auto flush = [&]() {
         if (grp.n == 0) return;
         grp.blk_start[grp.n] = (uint32_t)total;
-        hipLaunchKernelGGL((k_syrk_f64_group<128, 4, 2>), dim3((unsigned)total), dim3(512), 0, s, grp);
+        if (T == 128)
+            hipLaunchKernelGGL((k_syrk_f64_group<128, 4, 2>), dim3((unsigned)total), dim3(512), 0, s, grp);
+        else if (T == 96)
+            hipLaunchKernelGGL((k_syrk_f64_group<96, 2, 2>), dim3((unsigned)total), dim3(256), 0, s, grp);
+        else
+            hipLaunchKernelGGL((k_syrk_f64_group<64, 2, 2>), dim3((unsigned)total), dim3(256), 0, s, grp);
         grp = SyrkGroup{};
         total = 0;
     };
     for (int i = 0; i < n; ++i) {
         SyrkArgs g{};
         g.A = A[i]; g.B = A[i]; g.ld = kdim[i]; g.M = M[i]; g.N = M[i]; g.kdim = kdim[i]; g.ksplit = ksplit[i];
-        g.ntm = g.ntn = (int)((M[i] + 127) / 128);
+        g.ntm = g.ntn = (int)((M[i] + T - 1) / T);
         g.lower = 1;
         g.nsplit = nsplit[i];
         g.partial = partial[i];
