@@ -331,6 +331,30 @@ def test_batch_matches_single_builds(batch_set, prec):
         assert rel(outs[2][1].cpu().numpy(), ref["K"]) <= 1e-10
 
 
+def test_batch_with_mixed_tile_widths(batch_set):
+    """A batch whose molecules' K tiles differ (plans forced to 128-, 64- and
+    96-wide tiles and one left to the rule): the grouped syrk launches per
+    width and the grouped reduction with per-molecule widths give each
+    molecule its single build's J bitwise and K up to the split-K order."""
+    cases, _ = batch_set
+    uniq = cases[:4]
+    plans = [G.Plan.from_molecule(m, schwarz_thresh=TAU, k_tile=kt).screen().setup()
+             for (m, _, _), kt in zip(uniq, (128, 64, 96, 0))]
+    Cs = [C for _, _, C in uniq]
+    outs = G.Batch(plans, [C.shape[1] for C in Cs]).build(Cs)
+    torch.cuda.synchronize()
+    for plan, C, (J, K, E) in zip(plans, Cs, outs):
+        J1, K1, E1 = (t.cpu().numpy() for t in plan.build(C=C))
+        assert np.array_equal(J.cpu().numpy(), J1)
+        assert rel(K.cpu().numpy(), K1) <= 1e-13
+        assert abs(E.cpu().numpy()[1] - E1[1]) <= 1e-13 * abs(E1[1])
+    mol, _, C = uniq[0]
+    ref = oracle.dfjk(mol, C=C)
+    assert rel(outs[0][1].cpu().numpy(), ref["K"]) <= 1e-10
+    for plan in plans:
+        plan.close()
+
+
 def test_setup_batch_matches_single_setups(batch_set):
     """dfjk_setup_batch on uneven molecules (1, 2, 3 and 5 waters) and on 18
     plans (more than one grouped launch per integral class): the three-centre
