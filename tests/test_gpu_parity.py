@@ -333,13 +333,17 @@ def test_batch_matches_single_builds(batch_set, prec):
 
 def test_batch_with_mixed_tile_widths(batch_set):
     """A batch whose molecules' K tiles differ (plans forced to 128-, 64- and
-    96-wide tiles and one left to the rule): the grouped syrk launches per
-    width and the grouped reduction with per-molecule widths give each
-    molecule its single build's J bitwise and K up to the split-K order."""
+    96-wide tiles and one left to the rule) beside a molecule that needs
+    several aux slabs (not grouped): the grouped syrk launches per width and
+    the grouped reduction with per-molecule widths give each molecule its
+    single build's J bitwise and K up to the split-K order."""
     cases, _ = batch_set
-    uniq = cases[:4]
+    uniq = cases[:4] + [cases[2]]
     plans = [G.Plan.from_molecule(m, schwarz_thresh=TAU, k_tile=kt).screen().setup()
-             for (m, _, _), kt in zip(uniq, (128, 64, 96, 0))]
+             for (m, _, _), kt in zip(uniq[:4], (128, 64, 96, 0))]
+    # and one molecule on 128-wide aux slabs (several slabs: its own path in the batch)
+    plans.append(G.Plan.from_molecule(uniq[4][0], schwarz_thresh=TAU, aux_slab=128).screen().setup())
+    assert plans[-1].build_shape(uniq[4][2].shape[1])["nslab"] > 1
     Cs = [C for _, _, C in uniq]
     outs = G.Batch(plans, [C.shape[1] for C in Cs]).build(Cs)
     torch.cuda.synchronize()
