@@ -188,7 +188,8 @@ def batching_bench(nmol=16, reps=3, seed=7):
     K, reductions and energies) and its HIP-graph replay.  Orbitals are
     random orthonormal columns of nocc = 5 per water (only shapes matter to
     the timing); batched results are checked against the single ones.  The
-    best of `reps` timings of each form."""
+    best of `reps` timings of each form; then the builds once more in
+    int8_fast, one by one and batched."""
     import numpy as np
     import torch
     import workload as W
@@ -245,6 +246,15 @@ def batching_bench(nmol=16, reps=3, seed=7):
         t, _ = timed(g.replay)
         graph_build.append(t)
     dK = max(float((o[1] - q[1]).abs().max() / q[1].abs().max()) for o, q in zip(outs, singles))
+    # the same in int8_fast (slices, grouped half transforms and int8 K)
+    batch8 = G.Batch(plans, noccs, "int8_fast")
+    single8, batched8 = [], []
+    for _ in range(reps + 1):
+        t, _ = timed(lambda: [p.build(C=C, precision="int8_fast", out=o) for p, C, o in zip(plans, Cs, singles)])
+        single8.append(t)
+        t, _ = timed(lambda: batch8.build(Cs, outs=outs))
+        batched8.append(t)
+    dK8 = max(float((o[1] - q[1]).abs().max() / q[1].abs().max()) for o, q in zip(outs, singles))
     for p in plans:
         p.close()
     return {"workload": "%d water clusters of 1-12 molecules (sizes %s), FP64" % (nmol, sizes),
@@ -253,7 +263,9 @@ def batching_bench(nmol=16, reps=3, seed=7):
             "setup_B_bitwise_equal": bool(same_B),
             "build_ms": {"one_by_one": round(min(single_build[1:]), 3), "build_batch": round(min(batch_build[1:]), 3),
                          "build_batch_graph_replay": round(min(graph_build), 3)},
-            "max_rel_dK_batch_vs_single": dK}
+            "max_rel_dK_batch_vs_single": dK,
+            "build_ms_int8_fast": {"one_by_one": round(min(single8[1:]), 3), "build_batch": round(min(batched8[1:]), 3)},
+            "max_rel_dK_batch_vs_single_int8_fast": dK8}
 
 
 def make_inputs(n=32, box=10.0, geom_seed=1, cocc_seed=1):

@@ -587,8 +587,8 @@ void k_halftrans(HTArgs g)
     halftrans_tile<OUT, NIB>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-// FP64 half transforms of several molecules (the same fragment count) in one
-// launch: workgroup b runs workgroup b - blk_start[m] of molecule m's own
+// Half transforms of several molecules (the same output and fragment count)
+// in one launch: workgroup b runs workgroup b - blk_start[m] of molecule m's own
 // grid (gx P tiles fastest, then gy AO functions, then column passes), with
 // its arguments passed by value, so small molecules share the chip.
 constexpr int kHtGroupMax = 16;
@@ -600,7 +600,7 @@ struct HtGroup {
 };
 static_assert(sizeof(HtGroup) <= 4096, "kernel arguments are limited to 4 KB");
 
-template <int NIB>
+template <int OUT, int NIB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_halftrans_group(HtGroup grp)
 {
@@ -608,7 +608,7 @@ void k_halftrans_group(HtGroup grp)
     while (m + 1 < grp.n && blockIdx.x >= grp.blk_start[m + 1]) ++m;
     const unsigned local = blockIdx.x - grp.blk_start[m];
     const unsigned bx = local % grp.gx[m], rest = local / grp.gx[m];
-    halftrans_tile<OUT_F64, NIB>(grp.g[m], bx, rest % grp.gy[m], rest / grp.gy[m]);
+    halftrans_tile<OUT, NIB>(grp.g[m], bx, rest % grp.gy[m], rest / grp.gy[m]);
 }
 
 // Coefficients for the half transform: Cp[nao + 1][ldc] with C in the first
@@ -637,8 +637,10 @@ static void launch_halftrans(const HTArgs &h, int64_t nao, hipStream_t s)
 }
 static_assert(kHtMaxFrag == 10, "launch_halftrans instantiates 1..kHtMaxFrag fragments");
 
-// FP64 half transforms of several molecules: those with the same fragment
-// count share launches of k_halftrans_group (up to kHtGroupMax each).
+// Half transforms of several molecules with output OUT (FP64 or int8
+// slices): those with the same fragment count share launches of
+// k_halftrans_group (up to kHtGroupMax each).
+template <int OUT>
 static void launch_halftrans_groups(const std::vector<std::pair<HTArgs, int64_t>> &hs, hipStream_t s)
 {
     for (int nib = 1; nib <= kHtMaxFrag; ++nib) {
@@ -648,7 +650,7 @@ static void launch_halftrans_groups(const std::vector<std::pair<HTArgs, int64_t>
             if (grp.n == 0) return;
             grp.blk_start[grp.n] = (uint32_t)total;
 #define HT_CASE(N) \
-    case N: hipLaunchKernelGGL((k_halftrans_group<N>), dim3((unsigned)total), dim3(512), 0, s, grp); break;
+    case N: hipLaunchKernelGGL((k_halftrans_group<OUT, N>), dim3((unsigned)total), dim3(512), 0, s, grp); break;
             switch (nib) {
                 HT_CASE(1) HT_CASE(2) HT_CASE(3) HT_CASE(4) HT_CASE(5) HT_CASE(6) HT_CASE(7) HT_CASE(8)
                 HT_CASE(9) HT_CASE(10)
@@ -893,6 +895,8 @@ int mixed_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus);
 int i8_nsplit(int64_t nao, int64_t kdim, bool lower, int num_cus);
 void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, const double *sB, int64_t nao,
                     int64_t kdim, int nsplit, bool fast, double *part, hipStream_t s);
+void launch_gemm_i8_group(bool fast, int n, const void *const *X, const double *const *sX, const int64_t *nao,
+                          const int64_t *kdim, const int *nsplit, double *const *part, hipStream_t s);
 
 static int choose_ksplit(int ntiles, int64_t kdim, int num_cus, int per_cu = 2)
 {
@@ -1394,7 +1398,13 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
 {
     std::vector<Plan *> joins;
     std::vector<PreArgs> pre;
-    std::vector<std::pair<HTArgs, int64_t>> hts;   // arguments and AO count of each grouped half transform
+    std::vector<std::pair<HTArgs, int64_t>> hts, hts8;   // arguments and AO count of each grouped half transform
+    std::vector<const void *> i8x;                        // grouped int8 K: slices, scales, sizes, splits, partials
+    std::vector<const double *> i8s;
+    std::vector<int64_t> i8m, i8k;
+    std::vector<int> i8n;
+    std::vector<double *> i8p;
+    bool i8fast = false;
     std::vector<const double *> kx;
     std::vector<double *> kp;
     std::vector<int64_t> km, kk, ks;
@@ -1405,7 +1415,7 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         char *sc = scratch[i];
         const int64_t nao = p.nao;
         double *D = reinterpret_cast<double *>(sc + L.o_D);
-        if (L.nslab == 1 && L.precision == DFJK_FP64) {
+        if (L.nslab == 1 && (L.precision == DFJK_FP64 || is_int8(L.precision))) {
             // density, padded coefficients and J in the shared launches of
             // launch_pre_groups, the half transform and K grouped after them
             PreArgs a{};
@@ -1418,6 +1428,20 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
             a.nao = nao; a.nf = p.nf; a.nf_pad = p.nf_pad; a.ld = p.naux_pad;
             a.nocc = (int32_t)L.ncol; a.ldc = (int32_t)ht_ldc(L.ncol); a.nsplit_c = L.nsplit_c;
             pre.push_back(a);
+            if (is_int8(L.precision)) {
+                void *Xlo = sc + L.o_Xlo;   // block scales
+                hts8.emplace_back(ht_args(p, L.precision, p.d.B, p.naux_pad, a.Cp, (int32_t)L.ncol, 0, p.naux_pad,
+                                          sc + L.o_X, Xlo),
+                                  nao);
+                i8x.push_back(sc + L.o_X);
+                i8s.push_back(static_cast<const double *>(Xlo));
+                i8m.push_back(nao);
+                i8k.push_back(x_kdim(L.precision, p.naux_pad, L.ncol));
+                i8n.push_back(L.nsplit_k);
+                i8p.push_back(reinterpret_cast<double *>(sc + L.o_Kpart));
+                i8fast = L.precision == DFJK_MIXED_INT8_FAST;
+                continue;
+            }
             hts.emplace_back(ht_args(p, DFJK_FP64, p.d.B, p.naux_pad, a.Cp, (int32_t)L.ncol, 0, p.naux_pad,
                                      sc + L.o_X, nullptr),
                              nao);
@@ -1453,8 +1477,12 @@ void launch_build_batch(int n, Plan *const *plans, const BuildLayout *Ls, const 
         contract_slabs(p, L, C[i], nullptr, L.ncol, sc, s);
     }
     launch_pre_groups(pre, s);
-    // the half transforms of the one-slab FP64 molecules, grouped by fragment count
-    launch_halftrans_groups(hts, s);
+    // the half transforms of the one-slab molecules, grouped by output and fragment count
+    launch_halftrans_groups<OUT_F64>(hts, s);
+    launch_halftrans_groups<OUT_I8>(hts8, s);
+    if (!i8x.empty())
+        launch_gemm_i8_group(i8fast, (int)i8x.size(), i8x.data(), i8s.data(), i8m.data(), i8k.data(), i8n.data(),
+                             i8p.data(), s);
     for (int T : {64, 96, 128}) {   // one grouped syrk per tile width
         std::vector<const double *> gx;
         std::vector<double *> gp;

@@ -274,9 +274,7 @@ struct I8Args {
 // NFW per wave, padded with loads into a spare LDS slot so that every wave
 // issues the same count (the vmcnt immediate below).
 template <int WGM, int WGN, int RB, int CB, bool FAST>
-__global__ __launch_bounds__(64 * WGM * WGN)
-__attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4)))
-void k_gemm_i8(I8Args g)
+__device__ __forceinline__ void gemm_i8_tile(I8Args g, unsigned blk)
 {
     constexpr int NW = WGM * WGN, NT = 64 * NW;
     constexpr int AR = WGM * RB * 16, BR = WGN * CB * 16;                 // rows of the two operands
@@ -301,12 +299,12 @@ void k_gemm_i8(I8Args g)
     const int nth = 2 * (g.lower ? g.ntm * (g.ntm + 1) / 2 : g.ntm * g.ntm);   // tile halves per split
     int split, th;
     if (g.nsplit % kXcds == 0) {
-        const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+        const int xcd = blk % kXcds, local = blk / kXcds;
         split = xcd + kXcds * (local / nth);
         th = local % nth;
     } else {
-        split = blockIdx.x / nth;
-        th = blockIdx.x % nth;
+        split = blk / nth;
+        th = blk % nth;
     }
     const int half = th & 1, tile = th >> 1;
     int tm, tn;
@@ -470,6 +468,34 @@ void k_gemm_i8(I8Args g)
             }
 }
 
+template <int WGM, int WGN, int RB, int CB, bool FAST>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4)))
+void k_gemm_i8(I8Args g)
+{
+    gemm_i8_tile<WGM, WGN, RB, CB, FAST>(g, blockIdx.x);
+}
+
+// The int8 K of several molecules in one launch (batches): workgroup b runs
+// workgroup b - blk_start[m] of molecule m's own launch, descriptors by value.
+constexpr int kI8GroupMax = 16;
+struct I8Group {
+    int32_t n;
+    uint32_t blk_start[kI8GroupMax + 1];
+    I8Args g[kI8GroupMax];
+};
+static_assert(sizeof(I8Group) <= 4096, "kernel arguments are limited to 4 KB");
+
+template <int WGM, int WGN, int RB, int CB, bool FAST>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4)))
+void k_gemm_i8_group(I8Group grp)
+{
+    int m = 0;
+    while (m + 1 < grp.n && blockIdx.x >= grp.blk_start[m + 1]) ++m;
+    gemm_i8_tile<WGM, WGN, RB, CB, FAST>(grp.g[m], blockIdx.x - grp.blk_start[m]);
+}
+
 // Split count of the int8 K: workgroups run one per CU, all with the same
 // k length, so the time is (rounds of workgroups) x (k per split).  Counts
 // that are multiples of the XCD count run whole splits per XCD (rounds
@@ -529,6 +555,48 @@ void launch_gemm_i8(bool lower, const void *A, const double *sA, const void *B, 
         hipLaunchKernelGGL((k_gemm_i8<kI8WavesM, 2, 8 / kI8WavesM, 2, true>), grid, block, 0, s, g);
     else
         hipLaunchKernelGGL((k_gemm_i8<kI8WavesM, 2, 8 / kI8WavesM, 2, false>), grid, block, 0, s, g);
+}
+
+// Lower-tile int8 K partials of several molecules (one X and its block
+// scales each, kdim[i] long, nsplit[i] splits), as launch_gemm_i8 lays them
+// out, in launches of up to kI8GroupMax molecules.
+void launch_gemm_i8_group(bool fast, int n, const void *const *X, const double *const *sX, const int64_t *nao,
+                          const int64_t *kdim, const int *nsplit, double *const *part, hipStream_t s)
+{
+    I8Group grp{};
+    int64_t total = 0;
+    const dim3 block(64 * 2 * kI8WavesM);
+    auto flush = [&]() {
+        if (grp.n == 0) return;
+        grp.blk_start[grp.n] = (uint32_t)total;
+        if (fast)
+            hipLaunchKernelGGL((k_gemm_i8_group<kI8WavesM, 2, 8 / kI8WavesM, 2, true>), dim3((unsigned)total), block,
+                               0, s, grp);
+        else
+            hipLaunchKernelGGL((k_gemm_i8_group<kI8WavesM, 2, 8 / kI8WavesM, 2, false>), dim3((unsigned)total), block,
+                               0, s, grp);
+        grp = I8Group{};
+        total = 0;
+    };
+    for (int i = 0; i < n; ++i) {
+        I8Args g{};
+        g.A = static_cast<const unsigned char *>(X[i]);
+        g.B = g.A;
+        g.sA = sX[i]; g.sB = sX[i];
+        g.kdim = kdim[i]; g.M = nao[i];
+        g.ntm = (int)((nao[i] + T - 1) / T);
+        g.lower = 1;
+        g.ksplit = (int64_t)align_up((size_t)(((kdim[i] / kI8Block) + nsplit[i] - 1) / nsplit[i]), 1) * kI8Block;
+        g.partial = part[i];
+        g.nsplit = nsplit[i];
+        const int64_t nwg = 2 * (int64_t)(g.ntm * (g.ntm + 1) / 2) * nsplit[i];
+        if (nwg <= 0) continue;
+        if (grp.n == kI8GroupMax || total + nwg > (int64_t)UINT32_MAX / 2) flush();
+        grp.blk_start[grp.n] = (uint32_t)total;
+        grp.g[grp.n++] = g;
+        total += nwg;
+    }
+    flush();
 }
 
 // Split count: one round of workgroups (two per CU), each split a multiple

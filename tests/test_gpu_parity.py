@@ -303,7 +303,7 @@ def batch_set():
     return cases, plans
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "int8"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "int8", "int8_fast"])
 def test_batch_matches_single_builds(batch_set, prec):
     cases, plans = batch_set
     Cs = [C for _, _, C in cases]
@@ -322,7 +322,7 @@ def test_batch_matches_single_builds(batch_set, prec):
             # the batch contracts one aux slab where a single build may use two
             # (overlapped), which moves the FP32 chunk boundaries (int8: the
             # scale blocks, at the 2^-33 truncation level)
-            tol = 1e-9 if prec == "int8" else 1e-6
+            tol = 1e-9 if prec.startswith("int8") else 1e-6
             assert rel(K, K1) <= tol
             assert abs(E[1] - E1[1]) <= tol * abs(E1[1])
     if prec == "fp64":   # one molecule against the oracle
