@@ -245,11 +245,15 @@ class BatchedGpuExecutor(GpuExecutor):
                         b.build([st["Cs"][st["k"]] for st in sts],
                                 outs=[(st["J"], st["K"], st["Es"][st["k"]]) for st in sts], stream=self._stream)
                         del b
-                    self._stream.synchronize()
                 for st in group:
                     st["k"] += 1
                     if st["k"] == len(st["Cs"]):
                         finished.append(st)
+                # steps queue behind one another on the loop's stream (its
+                # arena is allocated and reused there, in stream order); the
+                # host waits only when a request's results are handed back
+                if finished:
+                    self._stream.synchronize()
             except Exception as e:  # fail every request of the step, keep serving
                 for st in group:
                     st["error"] = repr(e)
